@@ -1,0 +1,304 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Proportional Similarity hot path on one GPU.
+
+A step is one pass of the whole path over the resident synthetic input:
+per-vector sums, the min-product numerators and the FP64 metric epilogue
+(2-way), plus the pair-numerator prepass for 3-way.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+Workloads (seeded, synthetic; shapes of the paper's problems):
+  gwas_20000x16384   2-way, 20000 fields x 16384 vectors, FP32, 70% zeros,
+                     nonzeros Exponential(mean 2)            (default)
+  uniform_1024x256   2-way, FP32 U[0,1)
+  levels_8192x32768  2-way, uint8 levels {0..3}
+  sparse_4096x1024   3-way, FP32 U[0,1) with 50% zeros
+  batched_64_uneven  64 independent 2-way problems in one captured launch
+
+Comparisons are counted as the paper counts them: one per field and unique
+tuple (n_f C(n_v,2) for 2-way, n_f C(n_v,3) for 3-way).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD16 units = 64 lanes per clock per CU, 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # non-packed VALU lane-ops / s
+INT8_MFMA_PEAK_TOPS = 5000.0                 # dense int8 matrix-core ops / s (2 per MAC)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gwas_20000x16384")
+    ap.add_argument("--storage", default="auto", choices=["auto", "f32", "f16"])
+    ap.add_argument("--acc", default="auto", choices=["auto", "plain", "blocked"])
+    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-problem", action="store_true",
+                    help="batched workload: one launch per problem instead of the plan")
+    return ap.parse_args(argv)
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream libps launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = []
+
+    def mark(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def add(self, a, b):
+        self.pairs.append((a, b))
+
+    def mean_ms(self):
+        self.torch.cuda.synchronize()
+        v = [a.elapsed_time(b) for a, b in self.pairs]
+        return sum(v) / len(v) if v else float("nan")
+
+
+def cpu_baseline_pairs(V, n_f, seconds, seed=123):
+    import numpy as np
+
+    import oracle
+    g = np.random.default_rng(seed)
+    n_v = V.shape[0]
+    s = oracle.sums(V)
+
+    def run(m):
+        a = g.integers(0, n_v, size=m)
+        b = (a + 1 + g.integers(0, n_v - 1, size=m)) % n_v
+        t0 = time.perf_counter()
+        oracle.c2_pairs(V, a, b, s=s)
+        return time.perf_counter() - t0
+
+    m = 256
+    t = run(m)
+    while t < 0.2 and m < (1 << 24):
+        m *= 4
+        t = run(m)
+    m = max(256, int(m * seconds / max(t, 1e-9)))
+    t = run(m)
+    return {"value": m * n_f / t, "unit": "comparisons/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{m} random pairs of the full input, {n_f} fields each "
+                      f"(oracle c2 of listed pairs, {t:.1f} s)"}
+
+
+def cpu_baseline_triples(V, n_f, seconds, seed=123):
+    import numpy as np
+
+    import oracle
+    g = np.random.default_rng(seed)
+    n_v = V.shape[0]
+    s = oracle.sums(V)
+
+    def run(m):
+        t = np.sort(g.integers(0, n_v, size=(3 * m, 3)), axis=1)
+        t = t[(t[:, 0] < t[:, 1]) & (t[:, 1] < t[:, 2])][:m]
+        t0 = time.perf_counter()
+        oracle.c3_triples(V, t[:, 0], t[:, 1], t[:, 2], s=s)
+        return time.perf_counter() - t0, len(t)
+
+    m = 256
+    t, m = run(m)
+    while t < 0.2 and m < (1 << 22):
+        t, m = run(m * 4)
+    t, m = run(max(256, int(m * seconds / max(t, 1e-9))))
+    # each listed triple evaluates its three pair terms directly as well
+    return {"value": m * n_f / t, "unit": "comparisons/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{m} random triples of the full input, {n_f} fields each "
+                      f"(oracle c3 of listed triples, pair terms included, {t:.1f} s)"}
+
+
+def roofline_valu(ops_per_cmp, cmp, kernel_ms):
+    achieved = ops_per_cmp * cmp / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None}
+
+
+def main(argv=None):
+    args = parse(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is described in DESIGN.md, not implemented)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1705_08210_amd import ps
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    wl = args.workload
+    K, W = args.steps, args.warmup
+    timer = Timer(torch)
+    extra = {}
+
+    if wl in ("gwas_20000x16384", "uniform_1024x256", "levels_8192x32768"):
+        V = workloads.WORKLOADS[wl](0)
+        if args.storage == "f16" and V.dtype == np.float32:
+            V = workloads.to_f16(V)
+        n_v, n_f = V.shape
+        Vd = torch.from_numpy(V).to(dev)
+        s = torch.empty(n_v, dtype=torch.float64, device=dev)
+        m = n_v * (n_v - 1) // 2
+        c2 = torch.empty(m, dtype=torch.float32, device=dev)
+        levels = int(V.max()) if V.dtype == np.uint8 else 0
+
+        def step(rec):
+            ps.vector_sums(Vd, out=s, want_bad=False)
+            a = timer.mark() if rec else None
+            ps.ps2(Vd, s=s, c2=c2, acc=args.acc, path=args.path, levels=levels,
+                   tile=args.tile)
+            if rec:
+                timer.add(a, timer.mark())
+
+        cmp = n_f * m
+        if V.dtype == np.uint8:
+            dtype, ops_per_cmp = "u8", 0.25            # v_sad_u8: 4 comparisons / op
+        elif V.dtype == np.float16:
+            dtype, ops_per_cmp = "f16", 1.0            # pk_min + dot2 per 2 comparisons
+        else:
+            dtype, ops_per_cmp = "f32", 2.0            # min + add per comparison
+        kernel = "ps_mg2_kernel"
+        config = {"workload": wl, "way": 2, "n_f": n_f, "n_v": n_v}
+        cpu = (lambda: cpu_baseline_pairs(V, n_f, args.cpu_seconds))
+        parity_fn = ("pairs", V)
+    elif wl == "sparse_4096x1024":
+        V = workloads.sparse_4096x1024(0)
+        if args.storage == "f16":
+            V = workloads.to_f16(V)
+        n_v, n_f = V.shape
+        Vd = torch.from_numpy(V).to(dev)
+        s = torch.empty(n_v, dtype=torch.float64, device=dev)
+        n2 = torch.empty(n_v * (n_v - 1) // 2, dtype=torch.float32, device=dev)
+        c3 = torch.empty(math.comb(n_v, 3), dtype=torch.float32, device=dev)
+
+        def step(rec):
+            ps.vector_sums(Vd, out=s, want_bad=False)
+            ps.ps2(Vd, s=s, want_c2=False, want_n2=True, n2=n2, acc=args.acc,
+                   tile=args.tile)
+            a = timer.mark() if rec else None
+            ps.ps3(Vd, s=s, n2=n2, c3=c3, acc=args.acc, tile=args.tile)
+            if rec:
+                timer.add(a, timer.mark())
+
+        cmp = n_f * math.comb(n_v, 3)
+        dtype = "f16" if V.dtype == np.float16 else "f32"
+        ops_per_cmp = 1.0 if dtype == "f16" else 2.0
+        kernel = "ps_mg3_kernel"
+        config = {"workload": wl, "way": 3, "n_f": n_f, "n_v": n_v}
+        cpu = (lambda: cpu_baseline_triples(V, n_f, args.cpu_seconds))
+        parity_fn = ("triples", V)
+    elif wl == "batched_64_uneven":
+        Vs_np = workloads.batched_64_uneven(0)
+        Vs = [torch.from_numpy(x).to(dev) for x in Vs_np]
+        cmp = sum(x.shape[1] * x.shape[0] * (x.shape[0] - 1) // 2 for x in Vs_np)
+        outs = ps._batch_outputs(Vs)
+        if args.per_problem:
+            def step(rec):
+                a = timer.mark() if rec else None
+                for V_, (c, _, _) in zip(Vs, outs):
+                    ps.ps2(V_, c2=c, acc=args.acc, tile=args.tile)
+                if rec:
+                    timer.add(a, timer.mark())
+        else:
+            plan = ps.BatchedPlan(Vs, outs=outs, acc=args.acc, tile=args.tile)
+
+            def step(rec):
+                a = timer.mark() if rec else None
+                plan.run()
+                if rec:
+                    timer.add(a, timer.mark())
+        dtype, ops_per_cmp = "f32", 2.0
+        kernel = "ps_mgb_kernel" if not args.per_problem else "ps_mg2_kernel"
+        config = {"workload": wl, "way": 2, "problems": len(Vs),
+                  "mode": "per-problem launches" if args.per_problem else "one graph"}
+        big = max(range(len(Vs_np)), key=lambda t: Vs_np[t].size)
+        cpu = (lambda: cpu_baseline_pairs(Vs_np[big], Vs_np[big].shape[1], args.cpu_seconds))
+        parity_fn = None
+    else:
+        print(f"unknown workload {wl}", file=sys.stderr)
+        return 2
+
+    for _ in range(W):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / K * 1e3
+    kernel_ms = timer.mean_ms()
+
+    # quick sampled parity against the oracle (not timed)
+    if parity_fn is not None:
+        import oracle
+        kind, Vh = parity_fn
+        g = np.random.default_rng(7)
+        if kind == "pairs":
+            I = g.integers(0, n_v, 2048)
+            J = (I + 1 + g.integers(0, n_v - 1, 2048)) % n_v
+            I, J = np.minimum(I, J), np.maximum(I, J)
+            got = c2.cpu().numpy()[J * (J - 1) // 2 + I]
+            ref = oracle.c2_pairs(Vh, I, J)
+        else:
+            t = np.sort(g.integers(0, n_v, size=(6000, 3)), axis=1)
+            t = t[(t[:, 0] < t[:, 1]) & (t[:, 1] < t[:, 2])][:2048]
+            i, j, k = t[:, 0], t[:, 1], t[:, 2]
+            off = (n_v - 1) * (j * (j - 1) // 2) - ((j - 1) * j * (2 * j - 1)) // 6
+            got = c3.cpu().numpy()[off - 0 + (k - j - 1) * j + i]
+            ref = oracle.c3_triples(Vh, i, j, k)
+        nz = ref > 0
+        rel = np.abs(got[nz] - ref[nz]) / ref[nz]
+        extra["parity_sample"] = {"tuples": int(len(ref)),
+                                  "max_rel_err": float(rel.max()) if rel.size else 0.0,
+                                  "max_abs_err": float(np.abs(got - ref).max())}
+
+    value = cmp * K / wall
+    line = {
+        "metric": "elementwise comparisons/sec, 2-way & 3-way PS, 1 MI355X; % of VALU/MFMA peak",
+        "value": value, "unit": "comparisons/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic (seeded numpy PCG64)",
+        "config": config,
+        "roofline": dict(roofline_valu(ops_per_cmp, cmp, kernel_ms), kernel=kernel,
+                         kernel_ms=round(kernel_ms, 4)),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu()
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

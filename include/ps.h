@@ -1,0 +1,235 @@
+/*
+ * ps.h -- C ABI of libps, the MI355X (gfx950) library for the 2-way and
+ * 3-way Proportional Similarity (PS, Czekanowski) metric of Joubert et al.,
+ * "Parallel Accelerated Vector Similarity Calculations for Genomics
+ * Applications" (arXiv 1705.08210).
+ *
+ * Notation (0-based).  V holds n_v non-negative vectors of n_f fields.
+ * Vector i is stored at V[i*ld + q], q < n_f, ld >= n_f elements: the
+ * column-major n_f x n_v matrix of Section 3.1.
+ *
+ *   s_i        = sum_q v_{i,q}                              (Section 2.1)
+ *   n2(i,j)    = sum_q min(v_{i,q}, v_{j,q})                (Section 2.1)
+ *   c2(i,j)    = 2 n2(i,j) / (s_i + s_j)                    (Section 2.1)
+ *   n3'(i,j,k) = sum_q min(v_{i,q}, v_{j,q}, v_{k,q})       (Section 2.2)
+ *   n3(i,j,k)  = n2(i,j) + n2(i,k) + n2(j,k) - n3'(i,j,k)   (Section 2.2, Eq. 1)
+ *   c3(i,j,k)  = (3/2) n3 / (s_i + s_j + s_k)               (Section 2.2)
+ *
+ * A metric whose denominator is 0 (all-zero vectors) is returned as 0.
+ * Only distinct tuples are produced: pairs i<j and triples i<j<k (the
+ * symmetry reductions of Sections 2.1 and 2.2).
+ *
+ * Packed output layouts
+ *   2-way, colex:  index(i,j) = j(j-1)/2 + i,  i < j.   For a fixed j the
+ *                  i are contiguous.
+ *   3-way, j-slab: index(i,j,k) = off(j) + (k-j-1) j + i,  i < j < k,
+ *                  off(j) = sum_{t<j} t (n_v-1-t).  Middle index j is the
+ *                  slowest, so the triples of a range of j values (a stage,
+ *                  Section 4.2) form one contiguous block.
+ *
+ * Conventions
+ *  - Every pointer argument named V, s, c2, c3, n2, bad_count or workspace
+ *    is a DEVICE pointer owned by the caller.  Problem and option structs
+ *    are host memory, read during the call only.
+ *  - Calls are asynchronous on `stream` (0 = the null stream) and never
+ *    synchronise the device.  The library allocates no memory that the
+ *    caller sees; scratch comes from the caller's workspace, sized by the
+ *    matching *_workspace_size call.
+ *  - Arguments are checked before anything is launched; on an error nothing
+ *    is written and ps_last_error() describes it.  Faults in kernels show up
+ *    at the caller's next synchronisation.
+ *  - Inputs outside the domain (negative, NaN, Inf) are not checked on the
+ *    compute path; ps_vector_sums counts them.  Results for such inputs are
+ *    unspecified.
+ *  - Thread safety: calls may be made from several host threads; calls that
+ *    share a workspace buffer must be ordered by the caller.
+ */
+#ifndef PS_H
+#define PS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PS_OK = 0,
+    PS_ERR_ARG = 1,          /* bad size, null pointer, misaligned pointer */
+    PS_ERR_DTYPE = 2,        /* unknown or unsupported storage type */
+    PS_ERR_WORKSPACE = 3,    /* workspace too small (see *_workspace_size) */
+    PS_ERR_HIP = 4,          /* a HIP runtime call failed */
+    PS_ERR_UNSUPPORTED = 5   /* valid request this build does not implement */
+} ps_status;
+
+/* Storage type of V. */
+typedef enum {
+    PS_F32 = 0,   /* float;   FP32 min, FP32 accumulation                     */
+    PS_F16 = 1,   /* _Float16; packed FP16 min, FP32 accumulation             */
+    PS_U8 = 2     /* uint8 integer levels; exact integer arithmetic           */
+} ps_dtype;
+
+/* FP32 accumulation of the numerator sums (floating storage only). */
+typedef enum {
+    PS_ACC_AUTO = 0,     /* BLOCKED when n_f > 2048, else PLAIN */
+    PS_ACC_PLAIN = 1,    /* one running FP32 sum per output */
+    PS_ACC_BLOCKED = 2   /* FP32 partial per field tile, then added to the
+                            running sum: error grows with tile + n_f/tile
+                            instead of n_f */
+} ps_acc;
+
+/* Compute path for the pair numerators. */
+typedef enum {
+    PS_PATH_AUTO = 0,    /* U8 with 1 <= levels <= 15: MFMA; otherwise VALU */
+    PS_PATH_VALU = 1,    /* register-blocked min/add on the vector ALUs */
+    PS_PATH_MFMA = 2     /* U8 only: min(a,b) = sum_{t=1..levels} [a>=t][b>=t],
+                            an exact int8 matrix-core contraction with int32
+                            accumulation; needs levels >= max(V) */
+} ps_path;
+
+typedef struct {
+    int32_t acc;      /* ps_acc */
+    int32_t path;     /* ps_path */
+    int32_t levels;   /* PS_U8 + MFMA: upper bound on the values of V, 1..127 */
+    int32_t tile;     /* 0 = library choice (tuning table); else 1 + index
+                         into the tile configurations of ps_tile_config */
+} ps_opts;
+
+/* Human-readable name of a status code (static string). */
+const char* ps_status_string(ps_status st);
+/* Message of the last error on the calling host thread (static per thread). */
+const char* ps_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t ps_version(void);
+
+/*
+ * Per-vector sums s_i = sum_q v_{i,q} (the denominator terms of Sections 2.1
+ * and 2.2), accumulated in FP64 (exact for PS_U8).
+ *   V          device, n_v vectors, element type `dtype`, stride ld >= n_f
+ *   s          device, n_v doubles (written)
+ *   bad_count  device int32 or NULL; when given it is overwritten with the
+ *              number of entries that are negative, NaN or infinite
+ * n_v == 0 is a no-op.  Errors: PS_ERR_ARG, PS_ERR_DTYPE, PS_ERR_HIP.
+ */
+ps_status ps_vector_sums(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
+                         int64_t ld, double* s, int32_t* bad_count,
+                         hipStream_t stream);
+
+/* Workspace bytes that ps2_compute needs for these arguments (0 if none).
+ * s_given / n2 are as they will be passed to ps2_compute. */
+size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
+                          int32_t s_given, const ps_opts* opts);
+
+/*
+ * 2-way metric over all pairs i<j (Section 2.1) via the min-product
+ * "mGEMM" N2 = V^T o_min V of Section 3.1, restricted to the upper triangle.
+ *   s       device FP64 sums from ps_vector_sums, or NULL to compute them
+ *           into the workspace
+ *   c2      device float, n_v(n_v-1)/2, colex layout; may be NULL if n2 given
+ *   n2      device, optional raw numerators n2(i,j) in colex layout: float
+ *           for PS_F32/PS_F16, int32 for PS_U8; may be NULL
+ *   workspace / ws_bytes   device scratch, at least ps2_workspace_size()
+ *   opts    may be NULL (all defaults)
+ * Each c2 is formed in FP64 from the numerator and FP64 sums, then rounded
+ * once to FP32.  n_v < 2 writes nothing.
+ */
+ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
+                      int64_t ld, const double* s, float* c2, void* n2,
+                      void* workspace, size_t ws_bytes, const ps_opts* opts,
+                      hipStream_t stream);
+
+/* Workspace bytes that ps3_compute needs (s_given / n2_given as passed). */
+size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
+                          int32_t s_given, int32_t n2_given, const ps_opts* opts);
+
+/*
+ * 3-way metric over the triples i<j<k whose middle index j lies in
+ * [j_begin, j_end) (Section 2.2, Eq. 1; the per-j slices B_j = X_j^T o_min V
+ * of Section 3.2, with X_j = min(V, v_j) formed while staging operands and
+ * never stored).  A stage of the paper's staged runs (Section 4.2) is a j
+ * range; calling with consecutive ranges and concatenating the outputs gives
+ * the full j-slab layout.
+ *   s      device FP64 sums, or NULL (computed into the workspace)
+ *   n2     device pair numerators in colex layout (float for F32/F16, int32
+ *          for U8, as written by ps2_compute for the same V), or NULL to
+ *          compute them into the workspace
+ *   c3     device float; receives the triples of [j_begin, j_end) packed in
+ *          j-slab order starting at offset 0 (i.e. at global index
+ *          off(j_begin))
+ * Needs 1 <= j_begin <= j_end <= n_v-1 (empty range writes nothing).
+ */
+ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
+                      int64_t ld, const double* s, const void* n2,
+                      int64_t j_begin, int64_t j_end, float* c3,
+                      void* workspace, size_t ws_bytes, const ps_opts* opts,
+                      hipStream_t stream);
+
+/* Number of c3 values of the stage [j_begin, j_end): off(j_end)-off(j_begin). */
+int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end);
+
+/* One independent 2-way problem of a batch (all pointers device). */
+typedef struct {
+    const void* V;       /* n_v vectors, stride ld */
+    int64_t n_f, n_v, ld;
+    const double* s;     /* NULL: computed into the workspace */
+    float* c2;           /* colex, n_v(n_v-1)/2 floats (or NULL if n2 given) */
+    void* n2;            /* optional raw numerators, colex */
+} ps_problem;
+
+/* Workspace bytes for a batch of problems. */
+size_t ps2_batched_workspace_size(const ps_problem* probs, int32_t n,
+                                  int32_t dtype, const ps_opts* opts);
+
+/*
+ * Many independent uneven 2-way problems in one persistent launch over a
+ * combined tile list ordered longest-first (the load-balancing idea of
+ * Section 4.1 applied to tiles of one GPU).  Uploads the problem table and
+ * tile list into the workspace from host memory on `stream` and, as the one
+ * exception to the no-synchronisation rule, waits for `stream` once so that
+ * the upload has completed before returning; then launches.  Use the plan
+ * calls below to upload once and replay without any host wait.  All problems
+ * share `dtype`.
+ */
+ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype,
+                              void* workspace, size_t ws_bytes,
+                              const ps_opts* opts, hipStream_t stream);
+
+/* A captured batch: the upload is done once at creation and the launches
+ * (sums, counter reset, persistent compute) are captured in a HIP graph. */
+typedef struct ps_plan ps_plan;
+
+/* Builds the tile list, uploads it (synchronously, once) and captures the
+ * launch sequence into a graph.  The workspace must stay valid and
+ * untouched by others until ps_plan_destroy. */
+ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs,
+                                 int32_t n, int32_t dtype, const ps_opts* opts,
+                                 void* workspace, size_t ws_bytes,
+                                 hipStream_t stream);
+/* Replays the captured graph on `stream`. */
+ps_status ps_plan_execute(ps_plan* plan, hipStream_t stream);
+void ps_plan_destroy(ps_plan* plan);
+
+/*
+ * Tile configurations (for tuning).  `way` is 2 or 3.  Returns the number of
+ * compiled configurations for (dtype, way, path); when idx is in range
+ * writes the output-tile rows/cols and field-tile depth of configuration idx.
+ */
+int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx,
+                       int32_t* bm, int32_t* bn, int32_t* bk);
+
+/* Register a tuned choice: for (dtype, way, path) and problems with
+ * n_f in [nf_lo, nf_hi) and n_v in [nv_lo, nv_hi), use tile configuration
+ * `idx`.  Later registrations take precedence.  Host-side table only. */
+ps_status ps_tune_register(int32_t dtype, int32_t way, int32_t path,
+                           int64_t nf_lo, int64_t nf_hi, int64_t nv_lo,
+                           int64_t nv_hi, int32_t idx);
+/* Forget all registered choices. */
+void ps_tune_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PS_H */

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) library for the 2-way and 3-way Proportional Similarity
+metric (Joubert et al., arXiv 1705.08210).  The compute path is the C ABI of
+include/ps.h (libps.so, hand-written HIP kernels); ``ps`` is its binding."""
+
+from .ps import (BatchedPlan, PSError, ps2, ps2_batched, ps3, stage_size, tile_configs,
+                 tune_clear, tune_register, vector_sums)
+
+__all__ = ["BatchedPlan", "PSError", "ps2", "ps2_batched", "ps3", "stage_size",
+           "tile_configs", "tune_clear", "tune_register", "vector_sums"]

@@ -1,0 +1,196 @@
+// mg_common.hip -- per-vector sums, the 3-way tile prefix, and small fill
+// kernels shared by the entry points.
+#include <type_traits>
+
+#include "mgemm_core.h"
+
+namespace ps {
+
+// ---------------------------------------------------------------------------
+// Per-vector sums s_i = sum_q v_{i,q} in FP64 (exact integers for PS_U8),
+// plus the count of entries outside the domain v >= 0 (negative, NaN, Inf).
+// One wave per vector; 16-byte coalesced loads along the fields.
+// ---------------------------------------------------------------------------
+template <int DT>
+__device__ __forceinline__ void sum_word(uint32_t w, double& acc, uint64_t& iacc, int& bad) {
+    if constexpr (DT == PS_F32) {
+        acc += (double)as_f32(w);
+        bad += ((w & 0x7f800000u) == 0x7f800000u) | ((w >> 31) & (w != 0x80000000u));
+    } else if constexpr (DT == PS_F16) {
+        const h2_t h = as_h2(w);
+        acc += (double)(float)h.x;
+        acc += (double)(float)h.y;
+        const uint32_t lo = w & 0xffffu, hi = w >> 16;
+        bad += ((lo & 0x7c00u) == 0x7c00u) | ((lo >> 15) & (lo != 0x8000u));
+        bad += ((hi & 0x7c00u) == 0x7c00u) | ((hi >> 15) & (hi != 0x8000u));
+    } else {
+        iacc += (w & 0xffu) + ((w >> 8) & 0xffu) + ((w >> 16) & 0xffu) + (w >> 24);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void sum_row(const char* row, int64_t n_f, bool vec,
+                                        double& acc, uint64_t& iacc, int& bad) {
+    constexpr int ESZ = Ops<DT>::kEsz;
+    const int lane = threadIdx.x % 64;
+    const int64_t nbytes = n_f * ESZ;
+    int64_t done = 0;
+    if (vec) {
+        const int64_t full = nbytes / 16 * 16;
+        for (int64_t b = (int64_t)lane * 16; b < full; b += 64 * 16) {
+            const uint4 v = *(const uint4*)(row + b);
+            sum_word<DT>(v.x, acc, iacc, bad);
+            sum_word<DT>(v.y, acc, iacc, bad);
+            sum_word<DT>(v.z, acc, iacc, bad);
+            sum_word<DT>(v.w, acc, iacc, bad);
+        }
+        done = full / ESZ;
+    }
+    for (int64_t q = done + lane; q < n_f; q += 64) {
+        uint32_t w;
+        if (ESZ == 4) w = *(const uint32_t*)(row + 4 * q);
+        else if (ESZ == 2) w = *(const unsigned short*)(row + 2 * q);
+        else w = *(const unsigned char*)(row + q);
+        sum_word<DT>(w, acc, iacc, bad);  // zero upper parts contribute 0
+    }
+}
+
+__device__ __forceinline__ void wave_reduce(double& acc, uint64_t& iacc, int& bad) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off);
+        iacc += __shfl_xor(iacc, off);
+        bad += __shfl_xor(bad, off);
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void ps_sums_kernel(const void* V, int64_t n_f, int64_t n_v,
+                                                      int64_t ld, double* s, int32_t* bad) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (i >= n_v) return;  // whole waves leave together; no block barrier below
+    constexpr int ESZ = Ops<DT>::kEsz;
+    const char* row = (const char*)V + i * ld * ESZ;
+    const bool vec = ((uintptr_t)V % 16 == 0) && ((ld * ESZ) % 16 == 0);
+    double acc = 0.0;
+    uint64_t iacc = 0;
+    int nbad = 0;
+    sum_row<DT>(row, n_f, vec, acc, iacc, nbad);
+    wave_reduce(acc, iacc, nbad);
+    if (threadIdx.x % 64 == 0) {
+        s[i] = DT == PS_U8 ? (double)iacc : acc;
+        if (bad && nbad) atomicAdd(bad, nbad);
+    }
+}
+
+// Sums for the problems of a batch that did not bring their own: blockIdx.y
+// is the problem, need_s[p] != 0 marks the ones to compute into p.s.
+template <int DT>
+__global__ __launch_bounds__(256) void ps_batched_sums_kernel(const DevProblem* probs,
+                                                              const int32_t* need_s) {
+    const int p = blockIdx.y;
+    if (!need_s[p]) return;
+    const DevProblem pr = probs[p];
+    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (i >= pr.n_v) return;
+    constexpr int ESZ = Ops<DT>::kEsz;
+    const char* row = (const char*)pr.V + i * pr.ld * ESZ;
+    const bool vec = ((uintptr_t)pr.V % 16 == 0) && ((pr.ld * ESZ) % 16 == 0);
+    double acc = 0.0;
+    uint64_t iacc = 0;
+    int nbad = 0;
+    sum_row<DT>(row, pr.n_f, vec, acc, iacc, nbad);
+    wave_reduce(acc, iacc, nbad);
+    if (threadIdx.x % 64 == 0) ((double*)pr.s)[i] = DT == PS_U8 ? (double)iacc : acc;
+}
+
+__global__ void ps_zero_i32_kernel(int32_t* p, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(ps_zero_i32_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)),
+                       dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(const void* V, int32_t dt, int64_t n_f, int64_t n_v, int64_t ld,
+                       double* s, int32_t* bad, hipStream_t st) {
+    if (bad) {
+        hipError_t e = launch_zero_i32(bad, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    if (n_v == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_v + 3) / 4));
+    switch (dt) {
+    case PS_F32: hipLaunchKernelGGL(ps_sums_kernel<PS_F32>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
+    case PS_F16: hipLaunchKernelGGL(ps_sums_kernel<PS_F16>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
+    case PS_U8:  hipLaunchKernelGGL(ps_sums_kernel<PS_U8>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_sums(const DevProblem* probs, const int32_t* need_s, int32_t n,
+                               int32_t dt, int64_t max_nv, hipStream_t st) {
+    if (n <= 0 || max_nv <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((max_nv + 3) / 4), (unsigned)n);
+    switch (dt) {
+    case PS_F32: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F32>, grid, dim3(256), 0, st, probs, need_s); break;
+    case PS_F16: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F16>, grid, dim3(256), 0, st, probs, need_s); break;
+    case PS_U8:  hipLaunchKernelGGL(ps_batched_sums_kernel<PS_U8>, grid, dim3(256), 0, st, probs, need_s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix over the middle indices j in [jb, je) of the tile counts
+// ceil(j / bm) * ceil((n_v - 1 - j) / bm); prefix has je - jb + 1 entries.
+// One workgroup of 1024 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void ps_prefix3_kernel(int64_t n_v, int64_t jb, int64_t je,
+                                                          int bm, int64_t* prefix) {
+    __shared__ int64_t part[1024];
+    const int64_t nj = je - jb;
+    const int64_t per = (nj + 1023) / 1024;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    const int64_t hi = lo + per < nj ? lo + per : nj;
+    int64_t sum = 0;
+    for (int64_t t = lo; t < hi; ++t) {
+        const int64_t j = jb + t;
+        sum += ((j + bm - 1) / bm) * ((n_v - 1 - j + bm - 1) / bm);
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // 1024 partial sums: a serial scan is plenty
+        int64_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t t = lo; t < hi; ++t) {
+        const int64_t j = jb + t;
+        prefix[t] = run;
+        run += ((j + bm - 1) / bm) * ((n_v - 1 - j + bm - 1) / bm);
+    }
+    if (hi == nj && lo < hi) prefix[nj] = run;
+    if (nj == 0 && threadIdx.x == 0) prefix[0] = 0;
+}
+
+hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
+    const int bm = kValuCfgs[a.cfg].bm();
+    hipLaunchKernelGGL(ps_prefix3_kernel, dim3(1), dim3(1024), 0, st, a.n_v, a.j_begin,
+                       a.j_end, bm, a.prefix);
+    return hipGetLastError();
+}
+
+}  // namespace ps

@@ -1,0 +1,48 @@
+// mg_u8.hip -- instantiation of the VALU min-product kernels for PS_U8.
+#include <type_traits>
+
+#include "mgemm_kernels.h"
+
+namespace ps {
+
+namespace {
+template <class Go>
+hipError_t dispatch(int cfg, int acc, Go go) {
+    using std::integral_constant;
+    constexpr bool kFloat = PS_U8 != PS_U8;
+    const bool bl = kFloat && acc == PS_ACC_BLOCKED;
+    switch (cfg) {
+    case 0:
+        if constexpr (kFloat) if (bl) return go(integral_constant<int, 8>(), integral_constant<int, 32>(), std::true_type());
+        return go(integral_constant<int, 8>(), integral_constant<int, 32>(), std::false_type());
+    case 1:
+        if constexpr (kFloat) if (bl) return go(integral_constant<int, 4>(), integral_constant<int, 32>(), std::true_type());
+        return go(integral_constant<int, 4>(), integral_constant<int, 32>(), std::false_type());
+    case 2:
+        if constexpr (kFloat) if (bl) return go(integral_constant<int, 8>(), integral_constant<int, 16>(), std::true_type());
+        return go(integral_constant<int, 8>(), integral_constant<int, 16>(), std::false_type());
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_mg2_u8(const Mg2Launch& a, hipStream_t st) {
+    return dispatch(a.cfg, a.acc, [&](auto tm, auto bkw, auto bl) {
+        return go_mg2<PS_U8, decltype(tm)::value, decltype(bkw)::value, decltype(bl)::value>(a, st);
+    });
+}
+
+hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st) {
+    return dispatch(a.cfg, a.acc, [&](auto tm, auto bkw, auto bl) {
+        return go_mg3<PS_U8, decltype(tm)::value, decltype(bkw)::value, decltype(bl)::value>(a, st);
+    });
+}
+
+hipError_t launch_mgb_u8(const MgBatchLaunch& a, hipStream_t st) {
+    return dispatch(a.cfg, a.acc, [&](auto tm, auto bkw, auto bl) {
+        return go_mgb<PS_U8, decltype(tm)::value, decltype(bkw)::value, decltype(bl)::value>(a, st);
+    });
+}
+
+}  // namespace ps

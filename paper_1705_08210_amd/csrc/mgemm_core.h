@@ -1,0 +1,349 @@
+// mgemm_core.h -- device core of the VALU min-product ("modified GEMM",
+// Section 3.1 of the paper) kernels: one workgroup computes one output tile
+//   acc[r][c] = sum_q op(A[row r, q], B[col c, q])
+// where both operands are vectors of V (field-contiguous rows) and
+//   PS_F32: op = min,                      FP32 accumulation
+//   PS_F16: op = packed FP16 min, summed by a dot product with (1, 1) into FP32
+//   PS_U8 : op = |a - b| summed four bytes at a time (v_sad_u8); the pair
+//           numerator follows from min(a,b) = (a + b - |a-b|) / 2.
+// For the 3-way slices (Section 3.2) the A operand is X_j = min(V, v_j),
+// formed while the field tile is staged into LDS.
+//
+// Layout of the work: 256 threads = 2x2 waves.  Lane (lx, ly) of a wave owns
+// the rows {g*32 + lx*4 + e} and columns {g*32 + ly*4 + e} (e < 4) of the
+// wave's quadrant, so every LDS operand read is one 16-byte ds_read_b128.
+// A wave whose quadrant holds no wanted output (below the diagonal, outside
+// the tetrahedron, past n_v) skips the arithmetic but still helps stage.
+#pragma once
+
+#include "ps_internal.h"
+
+#ifndef PS_UNROLL_BLOCKED
+#define PS_UNROLL_BLOCKED 1
+#endif
+#ifndef PS_UNROLL_PLAIN
+#define PS_UNROLL_PLAIN 4
+#endif
+
+namespace ps {
+
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float as_f32(uint32_t x) { return __builtin_bit_cast(float, x); }
+__device__ __forceinline__ uint32_t as_u32(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ h2_t as_h2(uint32_t x) { return __builtin_bit_cast(h2_t, x); }
+
+// ---------------------------------------------------------------------------
+// Word-level arithmetic per storage type.
+// ---------------------------------------------------------------------------
+template <int DT> struct Ops;
+
+template <> struct Ops<PS_F32> {
+    using Acc = float;
+    static constexpr int kEsz = 4;
+    __device__ __forceinline__ static float first(uint32_t a, uint32_t b) {
+        return __builtin_fminf(as_f32(a), as_f32(b));
+    }
+    __device__ __forceinline__ static float step(float acc, uint32_t a, uint32_t b) {
+        return acc + __builtin_fminf(as_f32(a), as_f32(b));
+    }
+    __device__ __forceinline__ static uint32_t xmin(uint32_t a, uint32_t b) {
+        return as_u32(__builtin_fminf(as_f32(a), as_f32(b)));
+    }
+};
+
+template <> struct Ops<PS_F16> {
+    using Acc = float;
+    static constexpr int kEsz = 2;
+    __device__ __forceinline__ static float first(uint32_t a, uint32_t b) {
+        const h2_t one = {(_Float16)1.0f, (_Float16)1.0f};
+        return __builtin_amdgcn_fdot2(__builtin_elementwise_min(as_h2(a), as_h2(b)),
+                                      one, 0.0f, false);
+    }
+    __device__ __forceinline__ static float step(float acc, uint32_t a, uint32_t b) {
+        const h2_t one = {(_Float16)1.0f, (_Float16)1.0f};
+        return __builtin_amdgcn_fdot2(__builtin_elementwise_min(as_h2(a), as_h2(b)),
+                                      one, acc, false);
+    }
+    __device__ __forceinline__ static uint32_t xmin(uint32_t a, uint32_t b) {
+        return __builtin_bit_cast(uint32_t,
+                                  __builtin_elementwise_min(as_h2(a), as_h2(b)));
+    }
+};
+
+template <> struct Ops<PS_U8> {
+    using Acc = uint32_t;
+    static constexpr int kEsz = 1;
+    __device__ __forceinline__ static uint32_t first(uint32_t a, uint32_t b) {
+        return __builtin_amdgcn_sad_u8(a, b, 0u);
+    }
+    __device__ __forceinline__ static uint32_t step(uint32_t acc, uint32_t a, uint32_t b) {
+        return __builtin_amdgcn_sad_u8(a, b, acc);
+    }
+    // bytewise min through two packed 16-bit mins
+    __device__ __forceinline__ static uint32_t xmin(uint32_t a, uint32_t b) {
+        const uint32_t m = 0x00ff00ffu;
+        u16x2_t lo = __builtin_elementwise_min(__builtin_bit_cast(u16x2_t, a & m),
+                                               __builtin_bit_cast(u16x2_t, b & m));
+        u16x2_t hi = __builtin_elementwise_min(__builtin_bit_cast(u16x2_t, (a >> 8) & m),
+                                               __builtin_bit_cast(u16x2_t, (b >> 8) & m));
+        return __builtin_bit_cast(uint32_t, lo) | (__builtin_bit_cast(uint32_t, hi) << 8);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Staging of one field tile of BM rows into registers, then into LDS laid out
+// word-major: S[w * (BM + 4) + row].  Chunks are 16 bytes; chunk index runs
+// row-fastest so the transposing LDS writes of a wave hit distinct banks.
+// ---------------------------------------------------------------------------
+template <int BM, int BKW>
+struct Stager {
+    static constexpr int kCpr = BKW / 4;                 // chunks per row
+    static constexpr int kCh = BM * kCpr / kThreads;     // chunks per thread
+    static constexpr int kLd = BM + 4;                   // LDS row pitch (words)
+    static_assert(BM * kCpr % kThreads == 0, "tile not divisible");
+    uint4 r[kCh];
+
+    // Load one 16-byte chunk that may straddle the end of the fields, or sit
+    // on a row that is not 16-byte aligned, element by element (zero fill).
+    template <int ESZ>
+    __device__ __forceinline__ static uint4 load_slow(const char* p, int64_t nbytes_left) {
+        union { uint4 v; unsigned char b[16]; unsigned short h[8]; uint32_t w[4]; } u;
+        u.v = make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 16 / ESZ; ++e) {
+            if ((int64_t)e * ESZ < nbytes_left) {
+                if (ESZ == 4) u.w[e] = *(const uint32_t*)(p + 4 * e);
+                else if (ESZ == 2) u.h[e] = *(const unsigned short*)(p + 2 * e);
+                else u.b[e] = *(const unsigned char*)(p + e);
+            }
+        }
+        return u.v;
+    }
+
+    template <int ESZ>
+    __device__ __forceinline__ static uint4 load_chunk(const char* row_base, int64_t b0,
+                                                       int64_t nbytes, bool vec) {
+        if (b0 + 16 <= nbytes && vec) return *(const uint4*)(row_base + b0);
+        if (b0 < nbytes) return load_slow<ESZ>(row_base + b0, nbytes - b0);
+        return make_uint4(0, 0, 0, 0);
+    }
+
+    // rows [row0, row0 + BM) of V, valid below row_end; field-tile byte
+    // offset kb0; nbytes = n_f * element size; ldb = row pitch in bytes.
+    // XJ: replace each word by min(word, word of row xrow) (X_j staging).
+    template <int DT, bool XJ>
+    __device__ __forceinline__ void load(const char* Vb, int64_t ldb, int64_t row0,
+                                         int64_t row_end, int64_t kb0, int64_t nbytes,
+                                         bool vec, const char* xrow) {
+        constexpr int ESZ = Ops<DT>::kEsz;
+#pragma unroll
+        for (int c = 0; c < kCh; ++c) {
+            const int idx = threadIdx.x + c * kThreads;
+            const int row = idx % BM;
+            const int ch = idx / BM;
+            const int64_t grow = row0 + row;
+            const int64_t b0 = kb0 + ch * 16;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (grow < row_end) v = load_chunk<ESZ>(Vb + grow * ldb, b0, nbytes, vec);
+            if (XJ) {
+                const uint4 x = load_chunk<ESZ>(xrow, b0, nbytes, vec);
+                v.x = Ops<DT>::xmin(v.x, x.x);
+                v.y = Ops<DT>::xmin(v.y, x.y);
+                v.z = Ops<DT>::xmin(v.z, x.z);
+                v.w = Ops<DT>::xmin(v.w, x.w);
+            }
+            r[c] = v;
+        }
+    }
+
+    __device__ __forceinline__ void store(uint32_t* S) const {
+#pragma unroll
+        for (int c = 0; c < kCh; ++c) {
+            const int idx = threadIdx.x + c * kThreads;
+            const int row = idx % BM;
+            const int ch = idx / BM;
+            uint32_t* w = S + (ch * 4) * kLd + row;
+            w[0] = r[c].x;
+            w[kLd] = r[c].y;
+            w[2 * kLd] = r[c].z;
+            w[3 * kLd] = r[c].w;
+        }
+    }
+};
+
+// Rows/columns of a lane's micro-tile element (r, c) relative to the tile.
+template <int TM>
+__device__ __forceinline__ int lane_row(int wave, int lx, int r) {
+    return (wave & 1) * (8 * TM) + (r / 4) * 32 + lx * 4 + (r % 4);
+}
+template <int TN>
+__device__ __forceinline__ int lane_col(int wave, int ly, int c) {
+    return (wave >> 1) * (8 * TN) + (c / 4) * 32 + ly * 4 + (c % 4);
+}
+
+// ---------------------------------------------------------------------------
+// One output tile.  acc receives the sums for the lane's micro-tile.
+//   A rows [a_row0, a_row0 + BM) valid below a_end (optionally X_j-staged
+//   against row xj), B rows [b_row0, b_row0 + BN) valid below b_end.
+//   active: whether this wave does the arithmetic.
+// ---------------------------------------------------------------------------
+template <int DT, int TM, int TN, int BKW, bool BLOCKED, bool XJ>
+__device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nbytes,
+                                         bool vec, int64_t a_row0, int64_t a_end,
+                                         int64_t b_row0, int64_t b_end, const char* xrow,
+                                         bool active, uint32_t* As, uint32_t* Bs,
+                                         typename Ops<DT>::Acc (&acc)[TM][TN]) {
+    using Acc = typename Ops<DT>::Acc;
+    constexpr int BM = 16 * TM, BN = 16 * TN;
+    using SA = Stager<BM, BKW>;
+    using SB = Stager<BN, BKW>;
+    const int wave = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int lx = lane % 8, ly = lane / 8;
+    const int ar = (wave & 1) * (8 * TM) + lx * 4;   // first A row of the lane
+    const int bc = (wave >> 1) * (8 * TN) + ly * 4;  // first B column
+
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) acc[r][c] = Acc(0);
+
+    const int64_t tile_bytes = (int64_t)BKW * 4;
+    const int64_t nk = (nbytes + tile_bytes - 1) / tile_bytes;
+    SA sa;
+    SB sb;
+    if (nk > 0) {
+        sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, 0, nbytes, vec, xrow);
+        sb.template load<DT, false>(Vb, ldb, b_row0, b_end, 0, nbytes, vec, nullptr);
+    }
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        __syncthreads();  // previous tile's LDS reads are done
+        sa.store(As);
+        sb.store(Bs);
+        __syncthreads();
+        if (kt + 1 < nk) {  // prefetch the next field tile into registers
+            const int64_t kb = (kt + 1) * tile_bytes;
+            sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
+            sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
+        }
+        if (!active) continue;
+        if constexpr (BLOCKED) {
+            Acc p[TM][TN];
+            {
+                uint32_t a[TM], b[TN];
+#pragma unroll
+                for (int g = 0; g < TM / 4; ++g)
+                    *(uint4*)&a[4 * g] = *(const uint4*)&As[ar + g * 32];
+#pragma unroll
+                for (int g = 0; g < TN / 4; ++g)
+                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[bc + g * 32];
+#pragma unroll
+                for (int r = 0; r < TM; ++r)
+#pragma unroll
+                    for (int c = 0; c < TN; ++c) p[r][c] = Ops<DT>::first(a[r], b[c]);
+            }
+#pragma unroll PS_UNROLL_BLOCKED
+            for (int w = 1; w < BKW; ++w) {
+                uint32_t a[TM], b[TN];
+#pragma unroll
+                for (int g = 0; g < TM / 4; ++g)
+                    *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
+#pragma unroll
+                for (int g = 0; g < TN / 4; ++g)
+                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
+#pragma unroll
+                for (int r = 0; r < TM; ++r)
+#pragma unroll
+                    for (int c = 0; c < TN; ++c) p[r][c] = Ops<DT>::step(p[r][c], a[r], b[c]);
+            }
+#pragma unroll
+            for (int r = 0; r < TM; ++r)
+#pragma unroll
+                for (int c = 0; c < TN; ++c) acc[r][c] += p[r][c];
+        } else {
+            constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
+#pragma unroll kUnroll
+            for (int w = 0; w < BKW; ++w) {
+                uint32_t a[TM], b[TN];
+#pragma unroll
+                for (int g = 0; g < TM / 4; ++g)
+                    *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
+#pragma unroll
+                for (int g = 0; g < TN / 4; ++g)
+                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
+#pragma unroll
+                for (int r = 0; r < TM; ++r)
+#pragma unroll
+                    for (int c = 0; c < TN; ++c)
+                        acc[r][c] = Ops<DT>::step(acc[r][c], a[r], b[c]);
+            }
+        }
+    }
+}
+
+// Block index -> work index so that each XCD receives one contiguous run of
+// the work list (blocks are dealt to the XCDs round-robin by hardware).
+// Needs gridDim.x % kXcds == 0; returns an index in [0, gridDim.x).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t grid) {
+    const int64_t per = grid / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+// Upper-triangle tile t (column-major: (0,0), (0,1), (1,1), (0,2), ...).
+__device__ __forceinline__ void tri_decode(int64_t t, int64_t& bi, int64_t& bj) {
+    int64_t j = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (j * (j + 1) / 2 > t) --j;
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    bj = j;
+    bi = t - j * (j + 1) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues.
+// ---------------------------------------------------------------------------
+
+// 2-way: c2 = 2 n2 / (s_i + s_j) in FP64 (Section 2.1), rounded once to FP32;
+// optional raw numerators.  Output (i, j), i < j, at colex j(j-1)/2 + i.
+template <int DT, int TM, int TN>
+__device__ __forceinline__ void epilogue2(const typename Ops<DT>::Acc (&acc)[TM][TN],
+                                          int64_t row0, int64_t col0, int64_t n_v,
+                                          const double* __restrict__ s, float* c2,
+                                          void* n2) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lx = lane % 8, ly = lane / 8;
+    double sc[TN];
+#pragma unroll
+    for (int c = 0; c < TN; ++c) {
+        const int64_t j = col0 + lane_col<TN>(wave, ly, c);
+        sc[c] = j < n_v ? s[j] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+        const int64_t i = row0 + lane_row<TM>(wave, lx, r);
+        if (i >= n_v) continue;
+        const double si = s[i];
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+            const int64_t j = col0 + lane_col<TN>(wave, ly, c);
+            if (j >= n_v || i >= j) continue;
+            const int64_t idx = j * (j - 1) / 2 + i;
+            double num;
+            if constexpr (DT == PS_U8) {
+                const int64_t v = ((int64_t)si + (int64_t)sc[c] - (int64_t)acc[r][c]) / 2;
+                num = (double)v;
+                if (n2) ((int32_t*)n2)[idx] = (int32_t)v;
+            } else {
+                num = (double)acc[r][c];
+                if (n2) ((float*)n2)[idx] = acc[r][c];
+            }
+            if (c2) {
+                const double d = si + sc[c];
+                c2[idx] = d > 0.0 ? (float)((2.0 * num) / d) : 0.0f;
+            }
+        }
+    }
+}
+
+}  // namespace ps

@@ -1,0 +1,221 @@
+// mgemm_kernels.h -- the VALU kernels built on mgemm_core.h, templated on the
+// storage type.  Each per-type translation unit (mg_f32.hip, mg_f16.hip,
+// mg_u8.hip) includes this once and instantiates the launchers for its type.
+#pragma once
+
+#include "mgemm_core.h"
+
+namespace ps {
+
+template <int DT>
+__device__ __forceinline__ bool rows_vec_ok(const void* V, int64_t ld) {
+    return ((uintptr_t)V % 16 == 0) && ((ld * Ops<DT>::kEsz) % 16 == 0);
+}
+
+// ---------------------------------------------------------------------------
+// 2-way: one workgroup per tile of the upper triangle of N2 = V^T o_min V
+// (Section 3.1; tiles strictly below the diagonal are never visited, the
+// symmetry reduction of Section 2.1).
+// ---------------------------------------------------------------------------
+template <int DT, int TM, int BKW, bool BLOCKED>
+__global__ __launch_bounds__(kThreads, 2) void ps_mg2_kernel(Mg2Launch a, int64_t ntiles) {
+    using Acc = typename Ops<DT>::Acc;
+    constexpr int BM = 16 * TM;
+    __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
+    __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= ntiles) return;
+    int64_t bi, bj;
+    tri_decode(t, bi, bj);
+    const int64_t row0 = bi * BM, col0 = bj * BM;
+    const int wave = threadIdx.x / 64;
+    const int64_t r_lo = row0 + (wave & 1) * 8 * TM;
+    const int64_t c_lo = col0 + (wave >> 1) * 8 * TM;
+    const int64_t c_hi = c_lo + 8 * TM;  // exclusive
+    // some (i, j) with i < j, both < n_v, in this wave's quadrant?
+    const bool active = r_lo < a.n_v && c_lo < a.n_v && r_lo + 1 < c_hi;
+    const int64_t ldb = a.ld * Ops<DT>::kEsz;
+    const int64_t nbytes = a.n_f * Ops<DT>::kEsz;
+    Acc acc[TM][TM];
+    run_tile<DT, TM, TM, BKW, BLOCKED, false>((const char*)a.V, ldb, nbytes,
+                                              rows_vec_ok<DT>(a.V, a.ld), row0, a.n_v,
+                                              col0, a.n_v, nullptr, active, As, Bs, acc);
+    if (active) epilogue2<DT, TM, TM>(acc, row0, col0, a.n_v, a.s, a.c2, a.n2);
+}
+
+// ---------------------------------------------------------------------------
+// 3-way: one workgroup per (j, i-tile, k-tile) of the slices
+// B_j = X_j^T o_min V, X_j = min(V, v_j) (Section 3.2), restricted to i < j < k.
+// With j the middle index the rectangle i < j, k > j holds every triple once.
+// ---------------------------------------------------------------------------
+
+// 3-way epilogue: n3 from Eq. 1 with the pair numerators looked up from the
+// colex table, c3 = (3 n3) / (2 d3) in FP64 (Section 2.2).
+template <int DT, int TM, int TN>
+__device__ __forceinline__ void epilogue3(const typename Ops<DT>::Acc (&acc)[TM][TN],
+                                          int64_t row0, int64_t col0, int64_t j,
+                                          const Mg3Launch& a) {
+    using N2T = typename std::conditional<DT == PS_U8, int32_t, float>::type;
+    const N2T* N2 = (const N2T*)a.n2;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lx = lane % 8, ly = lane / 8;
+    const int64_t n_v = a.n_v;
+    const double sj = a.s[j];
+    const int64_t base = slab_offset(n_v, j) - slab_offset(n_v, a.j_begin);
+    double sk[TN], njk[TN];
+#pragma unroll
+    for (int c = 0; c < TN; ++c) {
+        const int64_t k = col0 + lane_col<TN>(wave, ly, c);
+        sk[c] = k < n_v ? a.s[k] : 0.0;
+        njk[c] = k < n_v ? (double)N2[k * (k - 1) / 2 + j] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+        const int64_t i = row0 + lane_row<TM>(wave, lx, r);
+        if (i >= j) continue;
+        const double si = a.s[i];
+        const double nij = (double)N2[j * (j - 1) / 2 + i];
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+            const int64_t k = col0 + lane_col<TN>(wave, ly, c);
+            if (k >= n_v) continue;
+            const double nik = (double)N2[k * (k - 1) / 2 + i];
+            double n3p;
+            if constexpr (DT == PS_U8) {
+                // sum_q min(x, v_k) = (sum x + s_k - sum |x - v_k|) / 2, with
+                // x = min(v_i, v_j) so that sum x = n2(i, j)
+                n3p = (double)(((int64_t)nij + (int64_t)sk[c] - (int64_t)acc[r][c]) / 2);
+            } else {
+                n3p = (double)acc[r][c];
+            }
+            const double n3 = ((nij + nik) + njk[c]) - n3p;
+            const double d3 = (si + sj) + sk[c];
+            const int64_t idx = base + (k - j - 1) * j + i;
+            a.c3[idx] = d3 > 0.0 ? (float)((3.0 * n3) / (2.0 * d3)) : 0.0f;
+        }
+    }
+}
+
+template <int DT, int TM, int BKW, bool BLOCKED>
+__global__ __launch_bounds__(kThreads, 2) void ps_mg3_kernel(Mg3Launch a) {
+    using Acc = typename Ops<DT>::Acc;
+    constexpr int BM = 16 * TM;
+    __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
+    __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= a.ntiles) return;
+    // slice j: largest jj with prefix[jj] <= t (every slice has >= 1 tile)
+    int64_t lo = 0, hi = a.j_end - a.j_begin;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (a.prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int64_t j = a.j_begin + lo;
+    const int64_t local = t - a.prefix[lo];
+    const int64_t nk = (a.n_v - 1 - j + BM - 1) / BM;
+    const int64_t bi = local / nk, bk = local % nk;
+    const int64_t row0 = bi * BM, col0 = j + 1 + bk * BM;
+    const int wave = threadIdx.x / 64;
+    const int64_t r_lo = row0 + (wave & 1) * 8 * TM;
+    const int64_t c_lo = col0 + (wave >> 1) * 8 * TM;
+    const bool active = r_lo < j && c_lo < a.n_v;
+    const int64_t ldb = a.ld * Ops<DT>::kEsz;
+    const int64_t nbytes = a.n_f * Ops<DT>::kEsz;
+    const char* Vb = (const char*)a.V;
+    Acc acc[TM][TM];
+    run_tile<DT, TM, TM, BKW, BLOCKED, true>(Vb, ldb, nbytes, rows_vec_ok<DT>(a.V, a.ld),
+                                             row0, j, col0, a.n_v, Vb + j * ldb, active,
+                                             As, Bs, acc);
+    if (active) epilogue3<DT, TM, TM>(acc, row0, col0, j, a);
+}
+
+// ---------------------------------------------------------------------------
+// Batched 2-way: a persistent grid pulls tiles of many problems from one
+// list (ordered longest first on the host) through an atomic work counter.
+// ---------------------------------------------------------------------------
+template <int DT, int TM, int BKW, bool BLOCKED>
+__global__ __launch_bounds__(kThreads, 2) void ps_mgb_kernel(MgBatchLaunch a) {
+    using Acc = typename Ops<DT>::Acc;
+    constexpr int BM = 16 * TM;
+    __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
+    __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
+    __shared__ int32_t next;
+    const int wave = threadIdx.x / 64;
+    for (;;) {
+        __syncthreads();  // LDS and `next` free for reuse
+        if (threadIdx.x == 0) next = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int64_t t = next;
+        if (t >= a.ntiles) break;
+        const BatchTile bt = a.tiles[t];
+        const DevProblem p = a.probs[bt.prob];
+        const int64_t row0 = (int64_t)bt.bi * BM, col0 = (int64_t)bt.bj * BM;
+        const int64_t r_lo = row0 + (wave & 1) * 8 * TM;
+        const int64_t c_lo = col0 + (wave >> 1) * 8 * TM;
+        const int64_t c_hi = c_lo + 8 * TM;
+        const bool active = r_lo < p.n_v && c_lo < p.n_v && r_lo + 1 < c_hi;
+        Acc acc[TM][TM];
+        run_tile<DT, TM, TM, BKW, BLOCKED, false>(
+            (const char*)p.V, p.ld * Ops<DT>::kEsz, p.n_f * Ops<DT>::kEsz,
+            rows_vec_ok<DT>(p.V, p.ld), row0, p.n_v, col0, p.n_v, nullptr, active, As, Bs,
+            acc);
+        if (active) epilogue2<DT, TM, TM>(acc, row0, col0, p.n_v, p.s, p.c2, p.n2);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+inline int64_t round_up_xcd(int64_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
+
+template <int DT, int TM, int BKW, bool BL>
+hipError_t go_mg2(const Mg2Launch& a, hipStream_t st) {
+    const int64_t T = tri_tiles(a.n_v, 16 * TM);
+    if (T == 0) return hipSuccess;
+    hipLaunchKernelGGL((ps_mg2_kernel<DT, TM, BKW, BL>), dim3((unsigned)round_up_xcd(T)),
+                       dim3(kThreads), 0, st, a, T);
+    return hipGetLastError();
+}
+
+template <int DT, int TM, int BKW, bool BL>
+hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
+    if (a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW, BL>), dim3((unsigned)round_up_xcd(a.ntiles)),
+                       dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int DT, int TM, int BKW, bool BL>
+hipError_t go_mgb(const MgBatchLaunch& a, hipStream_t st) {
+    if (a.ntiles == 0) return hipSuccess;
+    int64_t grid = a.grid;
+    if (grid <= 0) {  // one resident workgroup per slot of the whole chip
+        int dev = 0, ncu = 0, occ = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, ps_mgb_kernel<DT, TM, BKW, BL>, kThreads, 0);
+        if (e != hipSuccess) return e;
+        grid = (int64_t)ncu * (occ > 0 ? occ : 1);
+    }
+    if (grid > a.ntiles) grid = a.ntiles;
+    hipLaunchKernelGGL((ps_mgb_kernel<DT, TM, BKW, BL>), dim3((unsigned)grid),
+                       dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// Dispatch over the compiled configurations (kValuCfgs) and accumulation.
+#define PS_DISPATCH(GO, DT, ARGS, ST)                                              \
+    do {                                                                           \
+        const bool bl = (DT != PS_U8) && (ARGS).acc == PS_ACC_BLOCKED;             \
+        switch ((ARGS).cfg) {                                                      \
+        case 0: return bl ? GO<DT, 8, 32, true>(ARGS, ST) : GO<DT, 8, 32, false>(ARGS, ST); \
+        case 1: return bl ? GO<DT, 4, 32, true>(ARGS, ST) : GO<DT, 4, 32, false>(ARGS, ST); \
+        case 2: return bl ? GO<DT, 8, 16, true>(ARGS, ST) : GO<DT, 8, 16, false>(ARGS, ST); \
+        default: return hipErrorInvalidValue;                                      \
+        }                                                                          \
+    } while (0)
+
+}  // namespace ps

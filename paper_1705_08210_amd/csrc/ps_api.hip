@@ -1,0 +1,603 @@
+// ps_api.hip -- the C ABI of include/ps.h: argument checks, workspace
+// carving, plan selection and launch sequencing.  No arithmetic of the
+// metric happens here; every step runs in the kernels.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "ps_internal.h"
+
+namespace ps {
+
+const TileCfg kValuCfgs[kNumValuCfgs] = {
+    {8, 8, 32},   // 128 x 128 output tile, 32-word field tile
+    {4, 4, 32},   // 64 x 64
+    {8, 8, 16},   // 128 x 128, 16-word field tile
+};
+
+static thread_local char g_err[512] = "";
+
+ps_status fail(ps_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+static ps_status hip_fail(hipError_t e, const char* what) {
+    return fail(PS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t slab_tiles(int64_t n_v, int64_t jb, int64_t je, int bm, int bn) {
+    int64_t t = 0;
+    for (int64_t j = jb; j < je; ++j) t += ceil_div(j, bm) * ceil_div(n_v - 1 - j, bn);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning table.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    int32_t dt, way, path;
+    int64_t nf_lo, nf_hi, nv_lo, nv_hi;
+    int32_t idx;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+static int default_cfg(int32_t way, int64_t n_v) {
+    if (way == 2) {
+        // 128x128 tiles once they fill every workgroup slot a few times over
+        return tri_tiles(n_v, 128) >= 1024 ? 0 : 1;
+    }
+    return 0;
+}
+
+static int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
+                      const ps_opts* o) {
+    if (o && o->tile > 0) return o->tile - 1;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+            if (it->dt == dt && it->way == way && it->path == path && n_f >= it->nf_lo &&
+                n_f < it->nf_hi && n_v >= it->nv_lo && n_v < it->nv_hi)
+                return it->idx;
+    }
+    return default_cfg(way, n_v);
+}
+
+static int choose_acc(int64_t n_f, const ps_opts* o) {
+    const int a = o ? o->acc : PS_ACC_AUTO;
+    if (a == PS_ACC_PLAIN || a == PS_ACC_BLOCKED) return a;
+    return n_f > 2048 ? PS_ACC_BLOCKED : PS_ACC_PLAIN;
+}
+
+static int choose_path(int32_t dt, const ps_opts* o) {
+    const int p = o ? o->path : PS_PATH_AUTO;
+    if (p == PS_PATH_VALU || p == PS_PATH_MFMA) return p;
+    if (dt == PS_U8 && o && o->levels >= 1 && o->levels <= 15) return PS_PATH_MFMA;
+    return PS_PATH_VALU;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks.
+// ---------------------------------------------------------------------------
+static ps_status check_opts(const ps_opts* o) {
+    if (!o) return PS_OK;
+    if (o->acc < PS_ACC_AUTO || o->acc > PS_ACC_BLOCKED)
+        return fail(PS_ERR_ARG, "opts.acc = %d is not a ps_acc value", o->acc);
+    if (o->path < PS_PATH_AUTO || o->path > PS_PATH_MFMA)
+        return fail(PS_ERR_ARG, "opts.path = %d is not a ps_path value", o->path);
+    if (o->tile < 0 || o->tile > kNumValuCfgs)
+        return fail(PS_ERR_ARG, "opts.tile = %d out of range [0, %d]", o->tile, kNumValuCfgs);
+    if (o->levels < 0 || o->levels > 127)
+        return fail(PS_ERR_ARG, "opts.levels = %d out of range [0, 127]", o->levels);
+    return PS_OK;
+}
+
+static ps_status check_matrix(const void* V, int32_t dt, int64_t n_f, int64_t n_v, int64_t ld) {
+    const int esz = elem_size(dt);
+    if (esz == 0) return fail(PS_ERR_DTYPE, "unknown dtype %d", dt);
+    if (n_f < 0 || n_v < 0) return fail(PS_ERR_ARG, "n_f = %lld, n_v = %lld must be >= 0",
+                                        (long long)n_f, (long long)n_v);
+    if (ld < (n_f > 1 ? n_f : 1))
+        return fail(PS_ERR_ARG, "ld = %lld must be >= max(n_f, 1) = %lld", (long long)ld,
+                    (long long)(n_f > 1 ? n_f : 1));
+    if (n_v > (int64_t)1 << 31)
+        return fail(PS_ERR_ARG, "n_v = %lld exceeds 2^31", (long long)n_v);
+    if (n_v > 0 && n_f > 0 && !V) return fail(PS_ERR_ARG, "V is NULL");
+    if ((uintptr_t)V % esz) return fail(PS_ERR_ARG, "V is not aligned to its element size");
+    return PS_OK;
+}
+
+static bool aligned(const void* p, size_t a) { return (uintptr_t)p % a == 0; }
+
+// Workspace carving: consecutive 256-byte aligned regions.
+struct Carver {
+    char* base;
+    size_t used = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    void* take(size_t bytes) {
+        void* p = base ? base + used : nullptr;
+        used = align_up(used + bytes, 256);
+        return p;
+    }
+};
+
+static hipError_t launch_mg2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
+    switch (dt) {
+    case PS_F32: return launch_mg2_f32(a, st);
+    case PS_F16: return launch_mg2_f16(a, st);
+    default: return launch_mg2_u8(a, st);
+    }
+}
+
+static hipError_t launch_mg3(int32_t dt, const Mg3Launch& a, hipStream_t st) {
+    switch (dt) {
+    case PS_F32: return launch_mg3_f32(a, st);
+    case PS_F16: return launch_mg3_f16(a, st);
+    default: return launch_mg3_u8(a, st);
+    }
+}
+
+static hipError_t launch_mgb(int32_t dt, const MgBatchLaunch& a, hipStream_t st) {
+    switch (dt) {
+    case PS_F32: return launch_mgb_f32(a, st);
+    case PS_F16: return launch_mgb_f16(a, st);
+    default: return launch_mgb_u8(a, st);
+    }
+}
+
+// Sizes of the 2-way workspace regions.  Returns total bytes.
+static size_t ws2_layout(int32_t dt, int64_t n_f, int64_t n_v, int32_t s_given, int path,
+                         int levels, void* ws, double** s_ws, int8_t** planes) {
+    Carver c(ws);
+    double* s = nullptr;
+    if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
+    int8_t* pl = nullptr;
+    if (path == PS_PATH_MFMA && dt == PS_U8)
+        pl = (int8_t*)c.take(mfma_workspace_bytes(n_f, n_v, levels));
+    if (s_ws) *s_ws = s;
+    if (planes) *planes = pl;
+    return c.used;
+}
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" {
+
+const char* ps_status_string(ps_status st) {
+    switch (st) {
+    case PS_OK: return "PS_OK";
+    case PS_ERR_ARG: return "PS_ERR_ARG";
+    case PS_ERR_DTYPE: return "PS_ERR_DTYPE";
+    case PS_ERR_WORKSPACE: return "PS_ERR_WORKSPACE";
+    case PS_ERR_HIP: return "PS_ERR_HIP";
+    case PS_ERR_UNSUPPORTED: return "PS_ERR_UNSUPPORTED";
+    }
+    return "PS_STATUS_UNKNOWN";
+}
+
+const char* ps_last_error(void) { return g_err; }
+
+int32_t ps_version(void) { return 10000; }
+
+ps_status ps_vector_sums(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                         double* s, int32_t* bad_count, hipStream_t stream) {
+    ps_status st = check_matrix(V, dtype, n_f, n_v, ld);
+    if (st != PS_OK) return st;
+    if (n_v > 0 && !s) return fail(PS_ERR_ARG, "s is NULL");
+    if (!aligned(s, 8)) return fail(PS_ERR_ARG, "s is not 8-byte aligned");
+    if (!aligned(bad_count, 4)) return fail(PS_ERR_ARG, "bad_count is not 4-byte aligned");
+    hipError_t e = launch_sums(V, dtype, n_f, n_v, ld, s, bad_count, stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "ps_vector_sums launch");
+}
+
+size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_given,
+                          const ps_opts* opts) {
+    if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
+    const int path = choose_path(dtype, opts);
+    return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0, nullptr,
+                      nullptr, nullptr);
+}
+
+ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                      const double* s, float* c2, void* n2, void* workspace, size_t ws_bytes,
+                      const ps_opts* opts, hipStream_t stream) {
+    ps_status st = check_matrix(V, dtype, n_f, n_v, ld);
+    if (st != PS_OK) return st;
+    if ((st = check_opts(opts)) != PS_OK) return st;
+    if (n_v < 2) return PS_OK;
+    if (!c2 && !n2) return fail(PS_ERR_ARG, "both c2 and n2 are NULL");
+    if (!aligned(c2, 4) || !aligned(n2, 4) || !aligned(s, 8))
+        return fail(PS_ERR_ARG, "misaligned output or sums pointer");
+    const int path = choose_path(dtype, opts);
+    if (path == PS_PATH_MFMA && dtype != PS_U8)
+        return fail(PS_ERR_UNSUPPORTED, "the MFMA path needs PS_U8 data");
+    const int levels = opts ? opts->levels : 0;
+    if (path == PS_PATH_MFMA && levels < 1)
+        return fail(PS_ERR_ARG, "the MFMA path needs opts.levels >= max(V) >= 1");
+    double* s_ws = nullptr;
+    int8_t* planes = nullptr;
+    const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, workspace,
+                                   &s_ws, &planes);
+    if (ws_bytes < need || (need && !workspace))
+        return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
+    hipError_t e;
+    if (!s) {
+        e = launch_sums(V, dtype, n_f, n_v, ld, s_ws, nullptr, stream);
+        if (e != hipSuccess) return hip_fail(e, "sums launch");
+        s = s_ws;
+    }
+    if (path == PS_PATH_MFMA) {
+        MfmaLaunch m{V, n_f, n_v, ld, levels, s, c2, n2, planes, 0};
+        e = launch_mfma2(m, stream);
+        if (e == hipErrorNotSupported)
+            return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");
+        return e == hipSuccess ? PS_OK : hip_fail(e, "mfma launch");
+    }
+    Mg2Launch a{V, n_f, n_v, ld, s, c2, n2, choose_acc(n_f, opts),
+                choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts)};
+    e = launch_mg2(dtype, a, stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "2-way launch");
+}
+
+static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, void* ws,
+                         double** s_ws, void** n2_ws, int64_t** prefix) {
+    Carver c(ws);
+    double* s = nullptr;
+    void* n2 = nullptr;
+    if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
+    if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * 4);
+    int64_t* pre = (int64_t*)c.take((size_t)(n_v + 1) * sizeof(int64_t));
+    if (s_ws) *s_ws = s;
+    if (n2_ws) *n2_ws = n2;
+    if (prefix) *prefix = pre;
+    return c.used;
+}
+
+size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_given,
+                          int32_t n2_given, const ps_opts* opts) {
+    (void)opts;
+    if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
+    return ws3_layout(n_v, s_given, n2_given, nullptr, nullptr, nullptr, nullptr);
+}
+
+int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end) {
+    if (n_v < 3 || j_end <= j_begin) return 0;
+    return slab_offset(n_v, j_end) - slab_offset(n_v, j_begin);
+}
+
+ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                      const double* s, const void* n2, int64_t j_begin, int64_t j_end,
+                      float* c3, void* workspace, size_t ws_bytes, const ps_opts* opts,
+                      hipStream_t stream) {
+    ps_status st = check_matrix(V, dtype, n_f, n_v, ld);
+    if (st != PS_OK) return st;
+    if ((st = check_opts(opts)) != PS_OK) return st;
+    if (opts && opts->path == PS_PATH_MFMA)
+        return fail(PS_ERR_UNSUPPORTED, "3-way runs on the VALU path only");
+    if (n_v < 3) return PS_OK;
+    if (j_begin < 1 || j_end > n_v - 1 || j_begin > j_end)
+        return fail(PS_ERR_ARG, "need 1 <= j_begin <= j_end <= n_v-1, got [%lld, %lld)",
+                    (long long)j_begin, (long long)j_end);
+    if (j_begin == j_end) return PS_OK;
+    if (!c3) return fail(PS_ERR_ARG, "c3 is NULL");
+    if (!aligned(c3, 4) || !aligned(n2, 4) || !aligned(s, 8))
+        return fail(PS_ERR_ARG, "misaligned output, n2 or sums pointer");
+    double* s_ws = nullptr;
+    void* n2_ws = nullptr;
+    int64_t* prefix = nullptr;
+    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, workspace, &s_ws, &n2_ws,
+                                   &prefix);
+    if (ws_bytes < need || !workspace)
+        return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
+    hipError_t e;
+    if (!s) {
+        e = launch_sums(V, dtype, n_f, n_v, ld, s_ws, nullptr, stream);
+        if (e != hipSuccess) return hip_fail(e, "sums launch");
+        s = s_ws;
+    }
+    const int acc = choose_acc(n_f, opts);
+    if (!n2) {  // the pair numerators of Eq. 1 (the 2-way mGEMM prepass)
+        Mg2Launch a{V, n_f, n_v, ld, s, nullptr, n2_ws, acc,
+                    choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts)};
+        e = launch_mg2(dtype, a, stream);
+        if (e != hipSuccess) return hip_fail(e, "3-way numerator prepass launch");
+        n2 = n2_ws;
+    }
+    const int cfg = choose_cfg(dtype, 3, PS_PATH_VALU, n_f, n_v, opts);
+    const int bm = kValuCfgs[cfg].bm();
+    Mg3Launch a{V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, prefix,
+                slab_tiles(n_v, j_begin, j_end, bm, bm), acc, cfg};
+    e = launch_mg3_prefix(a, stream);
+    if (e == hipSuccess) e = launch_mg3(dtype, a, stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");
+}
+
+}  // extern "C"
+
+namespace ps {
+
+// ---------------------------------------------------------------------------
+// Batched 2-way.
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+    DevProblem* probs = nullptr;
+    int32_t* need_s = nullptr;
+    BatchTile* tiles = nullptr;
+    int32_t* counter = nullptr;
+    double* s = nullptr;
+    size_t bytes = 0;
+};
+
+static int64_t batch_sums_len(const ps_problem* p, int32_t n) {
+    int64_t t = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (!p[i].s) t += p[i].n_v;
+    return t;
+}
+
+static int64_t batch_tiles(const ps_problem* p, int32_t n, int bm) {
+    int64_t t = 0;
+    for (int32_t i = 0; i < n; ++i) t += p[i].n_v >= 2 ? tri_tiles(p[i].n_v, bm) : 0;
+    return t;
+}
+
+static BatchLayout batch_layout(const ps_problem* p, int32_t n, int bm, void* ws) {
+    Carver c(ws);
+    BatchLayout L;
+    L.probs = (DevProblem*)c.take(sizeof(DevProblem) * (size_t)(n > 0 ? n : 1));
+    L.need_s = (int32_t*)c.take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    L.counter = (int32_t*)c.take(sizeof(int32_t));
+    L.tiles = (BatchTile*)c.take(sizeof(BatchTile) * (size_t)batch_tiles(p, n, bm));
+    L.s = (double*)c.take(sizeof(double) * (size_t)batch_sums_len(p, n));
+    L.bytes = c.used;
+    return L;
+}
+
+static int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o) {
+    if (o && o->tile > 0) return o->tile - 1;
+    // representative shape: the largest problem by work
+    int64_t best = -1, nf = 0, nv = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t w = p[i].n_f * p[i].n_v * p[i].n_v;
+        if (w > best) best = w, nf = p[i].n_f, nv = p[i].n_v;
+    }
+    (void)nv;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+        if (it->dt == dt && it->way == 0 && nf >= it->nf_lo && nf < it->nf_hi)
+            return it->idx;
+    return 0;
+}
+
+static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, const ps_opts* o) {
+    if (n < 0) return fail(PS_ERR_ARG, "n = %d < 0", n);
+    if (n > 0 && !probs) return fail(PS_ERR_ARG, "probs is NULL");
+    ps_status st = check_opts(o);
+    if (st != PS_OK) return st;
+    if (o && o->path == PS_PATH_MFMA)
+        return fail(PS_ERR_UNSUPPORTED, "batched runs on the VALU path only");
+    for (int32_t i = 0; i < n; ++i) {
+        const ps_problem& p = probs[i];
+        st = check_matrix(p.V, dt, p.n_f, p.n_v, p.ld);
+        if (st != PS_OK) return fail(st, "problem %d: %s", i, ps_last_error());
+        if (p.n_v >= 2 && !p.c2 && !p.n2)
+            return fail(PS_ERR_ARG, "problem %d: both c2 and n2 are NULL", i);
+        if (!aligned(p.c2, 4) || !aligned(p.n2, 4) || !aligned(p.s, 8))
+            return fail(PS_ERR_ARG, "problem %d: misaligned pointer", i);
+        if (p.n_v > ((int64_t)1 << 31) / 2) return fail(PS_ERR_ARG, "problem %d too large", i);
+    }
+    return PS_OK;
+}
+
+// Host-side tables of a batch: device problem records (with workspace sums
+// where the caller gave none) and the tile list, longest problems first.
+static void batch_tables(const ps_problem* probs, int32_t n, int bm, const BatchLayout& L,
+                         std::vector<DevProblem>& dp, std::vector<int32_t>& need,
+                         std::vector<BatchTile>& tiles, int64_t& max_nv) {
+    dp.resize(n);
+    need.resize(n);
+    int64_t soff = 0;
+    max_nv = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const ps_problem& p = probs[i];
+        dp[i] = DevProblem{p.V, p.n_f, p.n_v, p.ld, p.s, p.c2, p.n2};
+        need[i] = p.s ? 0 : 1;
+        if (!p.s) {
+            dp[i].s = L.s + soff;
+            soff += p.n_v;
+        }
+        max_nv = std::max(max_nv, p.n_v);
+    }
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    // every tile of a problem costs ~n_f: longest-processing-time first
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return probs[a].n_f > probs[b].n_f;
+    });
+    tiles.clear();
+    for (int32_t pi : order) {
+        if (probs[pi].n_v < 2) continue;
+        const int64_t nb = ceil_div(probs[pi].n_v, bm);
+        for (int64_t bj = 0; bj < nb; ++bj)
+            for (int64_t bi = 0; bi <= bj; ++bi)
+                tiles.push_back(BatchTile{pi, (int32_t)bi, (int32_t)bj, 0});
+    }
+}
+
+static ps_status batch_enqueue(const BatchLayout& L, int32_t n, int32_t dt, int64_t ntiles,
+                               int64_t max_nv, int acc, int cfg, hipStream_t st) {
+    hipError_t e = launch_batched_sums(L.probs, L.need_s, n, dt, max_nv, st);
+    if (e == hipSuccess) e = launch_zero_i32(L.counter, 1, st);
+    if (e == hipSuccess) {
+        MgBatchLaunch a{L.probs, L.tiles, ntiles, L.counter, 0, acc, cfg};
+        e = launch_mgb(dt, a, st);
+    }
+    return e == hipSuccess ? PS_OK : hip_fail(e, "batched launch");
+}
+
+static int batch_acc(const ps_problem* p, int32_t n, const ps_opts* o) {
+    int64_t nf = 0;
+    for (int32_t i = 0; i < n; ++i) nf = std::max(nf, p[i].n_f);
+    return choose_acc(nf, o);
+}
+
+}  // namespace ps
+
+extern "C" {
+
+size_t ps2_batched_workspace_size(const ps_problem* probs, int32_t n, int32_t dtype,
+                                  const ps_opts* opts) {
+    if (n < 0 || (n > 0 && !probs) || elem_size(dtype) == 0) return 0;
+    const int cfg = batch_cfg(probs, n, dtype, opts);
+    if (cfg < 0 || cfg >= kNumValuCfgs) return 0;
+    return batch_layout(probs, n, kValuCfgs[cfg].bm(), nullptr).bytes;
+}
+
+ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype, void* ws,
+                              size_t ws_bytes, const ps_opts* opts, hipStream_t stream) {
+    ps_status st = check_batch(probs, n, dtype, opts);
+    if (st != PS_OK) return st;
+    if (n == 0) return PS_OK;
+    const int cfg = batch_cfg(probs, n, dtype, opts);
+    const int bm = kValuCfgs[cfg].bm();
+    const BatchLayout L = batch_layout(probs, n, bm, ws);
+    if (ws_bytes < L.bytes || !ws)
+        return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.bytes);
+    if (!aligned(ws, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
+    std::vector<DevProblem> dp;
+    std::vector<int32_t> need;
+    std::vector<BatchTile> tiles;
+    int64_t max_nv;
+    batch_tables(probs, n, bm, L, dp, need, tiles, max_nv);
+    hipError_t e = hipMemcpyAsync(L.probs, dp.data(), sizeof(DevProblem) * n,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L.need_s, need.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
+                           stream);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpyAsync(L.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "batched table upload");
+    // the host tables die at return: wait until the copies have consumed them
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "batched table upload");
+    return batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv,
+                         batch_acc(probs, n, opts), cfg, stream);
+}
+
+struct ps_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs, int32_t n,
+                                 int32_t dtype, const ps_opts* opts, void* ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+    if (!plan) return fail(PS_ERR_ARG, "plan is NULL");
+    *plan = nullptr;
+    ps_status st = check_batch(probs, n, dtype, opts);
+    if (st != PS_OK) return st;
+    const int cfg = batch_cfg(probs, n, dtype, opts);
+    const int bm = kValuCfgs[cfg].bm();
+    const BatchLayout L = batch_layout(probs, n, bm, ws);
+    if (ws_bytes < L.bytes || !ws)
+        return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.bytes);
+    if (!aligned(ws, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
+    std::vector<DevProblem> dp;
+    std::vector<int32_t> need;
+    std::vector<BatchTile> tiles;
+    int64_t max_nv = 0;
+    batch_tables(probs, n, bm, L, dp, need, tiles, max_nv);
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = hipStreamSynchronize(stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(L.probs, dp.data(), sizeof(DevProblem) * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(L.need_s, need.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !tiles.empty())
+            e = hipMemcpy(L.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "plan table upload");
+    }
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "plan capture stream");
+    ps_plan* p = new ps_plan();
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = n > 0 ? batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv,
+                                   batch_acc(probs, n, opts), cfg, cs)
+                   : PS_OK;
+        hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+        if (st == PS_OK && e2 != hipSuccess) st = hip_fail(e2, "plan capture");
+    } else {
+        st = hip_fail(e, "plan capture begin");
+    }
+    if (st == PS_OK) {
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = hip_fail(e, "plan instantiate");
+    }
+    hipStreamDestroy(cs);
+    if (st != PS_OK) {
+        ps_plan_destroy(p);
+        return st;
+    }
+    *plan = p;
+    return PS_OK;
+}
+
+ps_status ps_plan_execute(ps_plan* plan, hipStream_t stream) {
+    if (!plan || !plan->exec) return fail(PS_ERR_ARG, "plan is NULL or empty");
+    hipError_t e = hipGraphLaunch(plan->exec, stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "plan launch");
+}
+
+void ps_plan_destroy(ps_plan* plan) {
+    if (!plan) return;
+    if (plan->exec) hipGraphExecDestroy(plan->exec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    delete plan;
+}
+
+int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx, int32_t* bm,
+                       int32_t* bn, int32_t* bk) {
+    if (elem_size(dtype) == 0 || (way != 2 && way != 3) || path == PS_PATH_MFMA) return 0;
+    if (idx >= 0 && idx < kNumValuCfgs) {
+        const int fpw = 4 / elem_size(dtype);  // fields per 32-bit word
+        if (bm) *bm = kValuCfgs[idx].bm();
+        if (bn) *bn = kValuCfgs[idx].bn();
+        if (bk) *bk = kValuCfgs[idx].bkw * fpw;
+    }
+    return kNumValuCfgs;
+}
+
+ps_status ps_tune_register(int32_t dtype, int32_t way, int32_t path, int64_t nf_lo,
+                           int64_t nf_hi, int64_t nv_lo, int64_t nv_hi, int32_t idx) {
+    if (elem_size(dtype) == 0) return fail(PS_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (way != 0 && way != 2 && way != 3)
+        return fail(PS_ERR_ARG, "way must be 2, 3 (or 0 for batched)");
+    if (idx < 0 || idx >= kNumValuCfgs) return fail(PS_ERR_ARG, "tile index %d out of range", idx);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.push_back(TuneEntry{dtype, way, path, nf_lo, nf_hi, nv_lo, nv_hi, idx});
+    return PS_OK;
+}
+
+void ps_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// ps_internal.h -- declarations shared by the libps translation units.
+// Not installed; the public interface is include/ps.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/ps.h"
+
+namespace ps {
+
+constexpr int kThreads = 256;        // threads per workgroup of the tile kernels
+constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies
+
+// Record an error message for ps_last_error() and return `st`.
+ps_status fail(ps_status st, const char* fmt, ...);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Element size in bytes of a storage type (0 if unknown).
+inline int elem_size(int32_t dt) {
+    return dt == PS_F32 ? 4 : dt == PS_F16 ? 2 : dt == PS_U8 ? 1 : 0;
+}
+
+// Offset of the first triple of slab j in the j-slab layout:
+// sum_{t<j} t (n-1-t) = (n-1) j(j-1)/2 - (j-1) j (2j-1)/6.
+__host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
+    if (j <= 0) return 0;
+    return (n - 1) * (j * (j - 1) / 2) - ((j - 1) * j * (2 * j - 1)) / 6;
+}
+
+// ---------------------------------------------------------------------------
+// Tile configurations of the VALU min-product kernels.
+// A workgroup is 2x2 waves; lane (lx, ly) of a wave owns a TM x TN micro-tile
+// of rows {g*32 + lx*4 + e} and columns {g*32 + ly*4 + e}.  The workgroup
+// output tile is BM x BN = 16*TM x 16*TN; each field tile is BKW 32-bit words
+// (BKW * fields-per-word fields).
+// ---------------------------------------------------------------------------
+struct TileCfg {
+    int tm, tn, bkw;
+    int bm() const { return 16 * tm; }
+    int bn() const { return 16 * tn; }
+};
+
+// Compiled configurations, indexed by ps_opts.tile - 1.
+constexpr int kNumValuCfgs = 3;
+extern const TileCfg kValuCfgs[kNumValuCfgs];
+
+// Arguments of one 2-way launch over the upper-triangle tile list.
+struct Mg2Launch {
+    const void* V;
+    int64_t n_f, n_v, ld;        // ld in elements
+    const double* s;
+    float* c2;                   // may be null
+    void* n2;                    // may be null
+    int acc;                     // PS_ACC_PLAIN / PS_ACC_BLOCKED
+    int cfg;                     // index into kValuCfgs
+};
+
+// Arguments of one 3-way launch over the tiles of middle indices
+// [j_begin, j_end).
+struct Mg3Launch {
+    const void* V;
+    int64_t n_f, n_v, ld;
+    const double* s;
+    const void* n2;              // colex pair numerators
+    int64_t j_begin, j_end;
+    float* c3;
+    int64_t* prefix;             // workspace: j_end - j_begin + 1 int64
+    int64_t ntiles;
+    int acc;
+    int cfg;
+};
+
+// Device problem record of a batched launch.
+struct DevProblem {
+    const void* V;
+    int64_t n_f, n_v, ld;
+    const double* s;
+    float* c2;
+    void* n2;
+};
+
+// One output tile of a batched launch.
+struct BatchTile {
+    int32_t prob, bi, bj, pad;
+};
+
+struct MgBatchLaunch {
+    const DevProblem* probs;
+    const BatchTile* tiles;
+    int64_t ntiles;
+    int32_t* counter;            // work counter, zeroed by the launch sequence
+    int grid;
+    int acc;
+    int cfg;
+};
+
+// Tiles of the 2-way upper triangle for n_v vectors and output tile `bm`.
+inline int64_t tri_tiles(int64_t n_v, int bm) {
+    int64_t nb = ceil_div(n_v, bm);
+    return nb * (nb + 1) / 2;
+}
+
+// Tiles of the 3-way slices j in [jb, je).
+int64_t slab_tiles(int64_t n_v, int64_t jb, int64_t je, int bm, int bn);
+
+// Launchers (one per storage type; defined in the per-type units).
+hipError_t launch_sums(const void* V, int32_t dt, int64_t n_f, int64_t n_v,
+                       int64_t ld, double* s, int32_t* bad, hipStream_t st);
+hipError_t launch_mg2_f32(const Mg2Launch& a, hipStream_t st);
+hipError_t launch_mg2_f16(const Mg2Launch& a, hipStream_t st);
+hipError_t launch_mg2_u8(const Mg2Launch& a, hipStream_t st);
+hipError_t launch_mg3_f32(const Mg3Launch& a, hipStream_t st);
+hipError_t launch_mg3_f16(const Mg3Launch& a, hipStream_t st);
+hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st);
+hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st);
+hipError_t launch_mgb_f32(const MgBatchLaunch& a, hipStream_t st);
+hipError_t launch_mgb_f16(const MgBatchLaunch& a, hipStream_t st);
+hipError_t launch_mgb_u8(const MgBatchLaunch& a, hipStream_t st);
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+hipError_t launch_batched_sums(const DevProblem* probs, const int32_t* need_s, int32_t n,
+                               int32_t dt, int64_t max_nv, hipStream_t st);
+
+// Thermometer int8 MFMA path (PS_U8).
+struct MfmaLaunch {
+    const void* V;
+    int64_t n_f, n_v, ld;
+    int levels;
+    const double* s;
+    float* c2;
+    void* n2;
+    int8_t* planes;              // workspace: levels * n_v * kpad bytes
+    int64_t kpad;                // padded field count of one plane row
+};
+size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels);
+hipError_t launch_mfma2(const MfmaLaunch& a, hipStream_t st);
+
+}  // namespace ps

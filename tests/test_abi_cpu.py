@@ -1,0 +1,158 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/ps.h, and rejects bad arguments before launching
+anything (every call below returns from argument checking, so no HIP call
+is made)."""
+
+import ctypes
+import itertools
+import math
+
+import pytest
+
+ps = pytest.importorskip("paper_1705_08210_amd.ps")
+lib = ps.lib
+
+FAKE = ctypes.c_void_p(0x10000)   # never dereferenced: calls fail before use
+OK, ARG, DTYPE, WS, HIP, UNSUP = range(6)
+
+
+def test_exports_every_declared_function():
+    names = ps.header_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings():
+    assert lib.ps_version() == 10000
+    for st, name in enumerate(["PS_OK", "PS_ERR_ARG", "PS_ERR_DTYPE", "PS_ERR_WORKSPACE",
+                               "PS_ERR_HIP", "PS_ERR_UNSUPPORTED"]):
+        assert lib.ps_status_string(st).decode() == name
+
+
+def opts(acc=0, path=0, levels=0, tile=0):
+    return ctypes.byref(ps.Opts(acc, path, levels, tile))
+
+
+def call2(V=FAKE, dt=0, n_f=10, n_v=5, ld=10, s=None, c2=FAKE, n2=None, ws=FAKE,
+          ws_bytes=1 << 20, o=None):
+    return lib.ps2_compute(V, dt, n_f, n_v, ld, s, c2, n2, ws, ws_bytes, o, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dt=7), DTYPE),
+    (dict(n_f=-1), ARG),
+    (dict(n_v=-3), ARG),
+    (dict(ld=9), ARG),
+    (dict(V=None), ARG),
+    (dict(c2=None, n2=None), ARG),
+    (dict(V=ctypes.c_void_p(0x10002)), ARG),           # not 4-byte aligned for FP32
+    (dict(c2=ctypes.c_void_p(0x10001)), ARG),
+    (dict(ws_bytes=16), WS),                           # sums need 256 bytes
+    (dict(ws=None), WS),
+    (dict(ws=ctypes.c_void_p(0x10010)), ARG),          # workspace not 256-aligned
+    (dict(o=opts(acc=9)), ARG),
+    (dict(o=opts(path=5)), ARG),
+    (dict(o=opts(tile=99)), ARG),
+    (dict(o=opts(levels=200)), ARG),
+    (dict(o=opts(path=2)), UNSUP),                     # MFMA needs uint8 data
+    (dict(dt=2, o=opts(path=2, levels=0)), ARG),       # MFMA needs levels
+])
+def test_ps2_argument_errors(kw, status):
+    assert call2(**kw) == status
+    assert lib.ps_last_error().decode() != ""
+
+
+def test_ps2_no_pairs_is_noop():
+    # n_v < 2: nothing to compute, nothing launched, pointers unused
+    assert call2(n_v=1, c2=None, ws=None, ws_bytes=0) == OK
+    assert call2(n_v=0, c2=None, V=None, ws=None, ws_bytes=0) == OK
+
+
+def test_sums_argument_errors():
+    f = lib.ps_vector_sums
+    assert f(FAKE, 9, 10, 5, 10, FAKE, None, None) == DTYPE
+    assert f(FAKE, 0, 10, 5, 10, None, None, None) == ARG
+    assert f(FAKE, 0, 10, 5, 3, FAKE, None, None) == ARG
+    assert f(FAKE, 0, 10, 5, 10, ctypes.c_void_p(0x10004), None, None) == ARG
+    assert f(FAKE, 0, 10, 5, 10, FAKE, ctypes.c_void_p(0x10002), None) == ARG
+
+
+def call3(V=FAKE, dt=0, n_f=10, n_v=6, ld=10, s=None, n2=None, jb=1, je=5, c3=FAKE,
+          ws=FAKE, ws_bytes=1 << 20, o=None):
+    return lib.ps3_compute(V, dt, n_f, n_v, ld, s, n2, jb, je, c3, ws, ws_bytes, o, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(jb=0), ARG),
+    (dict(je=6), ARG),
+    (dict(jb=4, je=3), ARG),
+    (dict(c3=None), ARG),
+    (dict(ws_bytes=100), WS),
+    (dict(dt=5), DTYPE),
+    (dict(o=opts(path=2)), UNSUP),
+])
+def test_ps3_argument_errors(kw, status):
+    assert call3(**kw) == status
+
+
+def test_ps3_empty_cases_are_noops():
+    assert call3(jb=3, je=3, c3=None, ws=None, ws_bytes=0) == OK
+    assert call3(n_v=2, jb=1, je=1, c3=None, ws=None, ws_bytes=0) == OK
+
+
+def test_workspace_sizes():
+    f = lib.ps2_workspace_size
+    assert f(0, 100, 1000, 0, None) == 8192        # n_v doubles, 256-aligned
+    assert f(0, 100, 1000, 1, None) == 0
+    g = lib.ps3_workspace_size
+    n = 100
+    pairs = n * (n - 1) // 2
+    expect = (math.ceil(n * 8 / 256) * 256 + math.ceil(pairs * 4 / 256) * 256
+              + math.ceil((n + 1) * 8 / 256) * 256)
+    assert g(0, 10, n, 0, 0, None) == expect
+    assert g(0, 10, n, 1, 1, None) == math.ceil((n + 1) * 8 / 256) * 256
+
+
+@pytest.mark.parametrize("n_v", [3, 4, 7, 20])
+def test_stage_sizes_match_jslab_enumeration(n_v):
+    """off(j) of the j-slab layout equals the count of triples with a smaller
+    middle index, enumerated directly."""
+    trip = [(i, j, k) for j in range(1, n_v - 1) for k in range(j + 1, n_v) for i in range(j)]
+    assert lib.ps3_stage_size(n_v, 1, n_v - 1) == math.comb(n_v, 3) == len(trip)
+    for jb, je in itertools.combinations(range(1, n_v), 2):
+        cnt = sum(1 for t in trip if jb <= t[1] < je)
+        assert lib.ps3_stage_size(n_v, jb, je) == cnt
+
+
+def test_tile_configs_and_tuning_table():
+    cfgs = ps.tile_configs()
+    assert cfgs[0] == (128, 128, 32)
+    assert (64, 64, 32) in cfgs
+    import torch
+    assert ps.tile_configs(torch.uint8)[0] == (128, 128, 128)     # 4 fields per word
+    assert ps.tile_configs(torch.float16)[0] == (128, 128, 64)
+    assert lib.ps_tune_register(0, 2, 1, 0, 10, 0, 10, 99) == ARG
+    assert lib.ps_tune_register(0, 4, 1, 0, 10, 0, 10, 0) == ARG
+    assert lib.ps_tune_register(0, 2, 1, 0, 10, 0, 10, 1) == OK
+    lib.ps_tune_clear()
+
+
+def test_batched_argument_errors():
+    arr = (ps.Problem * 2)()
+    arr[0] = ps.Problem(FAKE, 10, 5, 10, None, FAKE, None)
+    arr[1] = ps.Problem(FAKE, 10, 5, 9, None, FAKE, None)     # ld < n_f
+    assert lib.ps2_compute_batched(arr, 2, 0, FAKE, 1 << 20, None, None) == ARG
+    assert "problem 1" in lib.ps_last_error().decode()
+    arr[1] = ps.Problem(FAKE, 10, 5, 10, None, None, None)    # no outputs
+    assert lib.ps2_compute_batched(arr, 2, 0, FAKE, 1 << 20, None, None) == ARG
+    arr[1] = ps.Problem(FAKE, 10, 5, 10, None, FAKE, None)
+    assert lib.ps2_compute_batched(arr, 2, 0, FAKE, 16, None, None) == WS
+    assert lib.ps2_compute_batched(arr, -1, 0, FAKE, 16, None, None) == ARG
+    assert lib.ps2_compute_batched(arr, 0, 0, None, 0, None, None) == OK
+    h = ctypes.c_void_p()
+    assert lib.ps_plan_create_batched(None, arr, 2, 0, None, FAKE, 1 << 20, None) == ARG
+    assert lib.ps_plan_create_batched(ctypes.byref(h), arr, 2, 0, None, FAKE, 16, None) == WS
+    assert h.value is None
+    assert lib.ps_plan_execute(None, None) == ARG
+    lib.ps_plan_destroy(None)

@@ -1,0 +1,220 @@
+"""2-way parity: the HIP path (through the C ABI) against the CPU oracle, on
+seeded inputs that span several tiles with ragged tails, plus the exact
+families and properties that hold at any size."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from psx import (announce, check_exact_f32, check_rel, colex, host, need_gpu,
+                 sample_pairs, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP16_TOL = 1e-3
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def run2(V, **kw):
+    from paper_1705_08210_amd import ps
+    Vd = to_dev(V)
+    c2, n2 = ps.ps2(Vd, want_n2=True, **kw)
+    return host(c2), host(n2)
+
+
+# ---------------------------------------------------------------- sums ----
+
+@pytest.mark.parametrize("kind", ["f32", "f16", "u8"])
+def test_sums_match_oracle(kind):
+    from paper_1705_08210_amd import ps
+    if kind == "u8":
+        V = workloads.levels(301, 1003, seed=3)
+    else:
+        V = workloads.gwas_like(301, 1003, seed=3)
+        if kind == "f16":
+            V = workloads.to_f16(V)
+    announce(f"sums {kind} {V.shape}")
+    s, bad = ps.vector_sums(to_dev(V))
+    s = host(s)
+    ref = oracle.sums(V)
+    if kind == "u8":
+        assert np.array_equal(s, ref)
+    else:
+        check_rel(s, ref, 1e-13, "sums")
+    assert host(bad)[0] == 0
+
+
+def test_sums_count_out_of_domain_entries():
+    from paper_1705_08210_amd import ps
+    V = workloads.uniform(9, 77, seed=1)
+    V[0, 5] = -1.0
+    V[3, 0] = np.nan
+    V[8, 76] = np.inf
+    V[4, 4] = -0.0          # zero: in the domain
+    announce("sums bad count")
+    for dt in (np.float32, np.float16):
+        _, bad = ps.vector_sums(to_dev(V.astype(dt)))
+        assert host(bad)[0] == 3
+
+
+# ------------------------------------------------------- oracle parity ----
+
+def test_uniform_1024x256_full():
+    V = workloads.uniform_1024x256()
+    announce("2-way uniform 1024x256 full")
+    c2, n2 = run2(V)
+    ref, rn2 = oracle.c2_all(V, with_n2=True)
+    check_rel(c2, ref, FP32_TOL, "c2")
+    check_rel(n2, rn2, FP32_TOL, "n2")
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("acc", ["plain", "blocked"])
+def test_ragged_tiles_and_accumulation(tile, acc):
+    V = workloads.gwas_like(300, 1001, seed=7)      # 3 tiles of 128 + tail; K tail
+    announce(f"2-way ragged tile={tile} acc={acc}")
+    c2, n2 = run2(V, tile=tile, acc=acc)
+    ref, rn2 = oracle.c2_all(V, with_n2=True)
+    check_rel(c2, ref, FP32_TOL, "c2")
+    check_rel(n2, rn2, FP32_TOL, "n2")
+
+
+@pytest.mark.parametrize("storage", ["f32", "u8"])
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_integer_levels_bit_exact(storage, tile):
+    V = workloads.levels(263, 777, seed=11)
+    if storage == "f32":
+        V = V.astype(np.float32)
+    announce(f"2-way integer {storage} tile={tile}")
+    c2, n2 = run2(V, tile=tile)
+    ref, rn2 = oracle.c2_all(V, with_n2=True)
+    check_exact_f32(c2, ref, "c2")
+    assert np.array_equal(n2.astype(np.float64), rn2)
+
+
+def test_fp16_storage():
+    V32 = workloads.uniform(200, 1500, seed=5)
+    V16 = workloads.to_f16(V32)
+    announce("2-way fp16 storage")
+    c2, n2 = run2(V16)
+    # kernel error: against the oracle on the FP16-rounded values
+    check_rel(c2, oracle.c2_all(V16), FP32_TOL, "c2 vs fp16 values")
+    # user-visible error: against the FP32 source
+    check_rel(c2, oracle.c2_all(V32), FP16_TOL, "c2 vs fp32 source")
+
+
+@pytest.mark.parametrize("kind", ["f32", "f16", "u8"])
+def test_unaligned_stride(kind):
+    """Rows whose pitch is not a multiple of 16 bytes take the element-wise
+    staging path."""
+    import torch
+    from paper_1705_08210_amd import ps
+    n_v, n_f, ld = 150, 333, 337
+    if kind == "u8":
+        big = workloads.levels(n_v, ld, seed=2)
+    else:
+        big = workloads.sparse_uniform(n_v, ld, seed=2)
+        if kind == "f16":
+            big = workloads.to_f16(big)
+    V = big[:, :n_f]
+    announce(f"2-way unaligned {kind}")
+    Vd = to_dev(big)[:, :n_f]
+    assert Vd.stride(0) == ld
+    c2, n2 = ps.ps2(Vd, want_n2=True)
+    ref, rn2 = oracle.c2_all(V, with_n2=True)
+    if kind == "u8":
+        check_exact_f32(host(c2), ref, "c2")
+    else:
+        check_rel(host(c2), ref, FP32_TOL, "c2")
+    del torch
+
+
+@pytest.mark.parametrize("n_v,n_f", [(2, 1), (3, 5), (127, 31), (128, 32), (129, 33),
+                                     (65, 1), (257, 7)])
+def test_edge_sizes(n_v, n_f):
+    V = workloads.sparse_uniform(n_v, n_f, seed=n_v + n_f)
+    announce(f"2-way edge n_v={n_v} n_f={n_f}")
+    c2, _ = run2(V)
+    check_rel(c2, oracle.c2_all(V), FP32_TOL, "c2")
+
+
+def test_zero_fields_and_zero_vectors():
+    from paper_1705_08210_amd import ps
+    import torch
+    announce("2-way n_f=0 and zero vectors")
+    V0 = torch.zeros((5, 0), dtype=torch.float32, device="cuda")
+    c2, _ = ps.ps2(V0)
+    assert np.all(host(c2) == 0)
+    V = workloads.uniform(40, 50, seed=4)
+    V[[3, 17, 18]] = 0.0
+    c2, _ = run2(V)
+    ref = oracle.c2_all(V)
+    check_rel(c2, ref, FP32_TOL, "c2")
+    assert c2[colex(17, 18)] == 0.0
+
+
+def test_noop_sizes():
+    from paper_1705_08210_amd import ps
+    import torch
+    for n_v in (0, 1):
+        V = torch.rand((n_v, 10), device="cuda")
+        c2, _ = ps.ps2(V)
+        assert c2.numel() == 0
+
+
+def test_given_sums_identical():
+    from paper_1705_08210_amd import ps
+    V = workloads.gwas_like(200, 900, seed=9)
+    announce("2-way given sums")
+    Vd = to_dev(V)
+    s, _ = ps.vector_sums(Vd)
+    a, _ = ps.ps2(Vd)
+    b, _ = ps.ps2(Vd, s=s)
+    assert np.array_equal(host(a), host(b))
+
+
+def test_determinism_and_permutation_equivariance():
+    """Each pair sums its fields in the same order whatever tile it lands
+    in, so permuting the vectors permutes the outputs bit for bit."""
+    V = workloads.gwas_like(300, 2100, seed=12)
+    perm = np.random.default_rng(0).permutation(300)
+    announce("2-way determinism/permutation")
+    a, _ = run2(V)
+    b, _ = run2(V)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    p, _ = run2(V[perm])
+    i, j = np.triu_indices(300, 1)
+    pi, pj = np.minimum(perm[i], perm[j]), np.maximum(perm[i], perm[j])
+    assert np.array_equal(p[colex(i, j)].view(np.uint32), a[colex(pi, pj)].view(np.uint32))
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u8"])
+def test_nested_support_family_exact(storage):
+    """V[perm(q), i] = a_i [q < L_i]: n2 = min(a) min(L), s_i = a_i L_i; all
+    partial sums are exact dyadic values, so every path is bit-exact."""
+    V, a, L = workloads.nested_support(390, 3000, seed=21, integer=(storage == "u8"))
+    if storage == "f16":
+        V = workloads.to_f16(V)
+    announce(f"2-way nested support {storage}")
+    c2, n2 = run2(V)
+    i, j = np.triu_indices(len(a), 1)
+    num = np.minimum(a[i], a[j]) * np.minimum(L[i], L[j])
+    d = a[i] * L[i] + a[j] * L[j]
+    ref = np.where(d > 0, 2 * num / np.where(d > 0, d, 1), 0.0)
+    idx = colex(i, j)
+    check_exact_f32(c2[idx], ref, "c2")
+    assert np.array_equal(n2[idx].astype(np.float64), num)
+
+
+def test_sampled_pairs_match_listed_oracle():
+    V = workloads.gwas_like(700, 4000, seed=13)
+    I, J = sample_pairs(700, 4000, seed=1)
+    announce("2-way sampled pairs 700x4000")
+    c2, _ = run2(V)
+    check_rel(c2[colex(I, J)], oracle.c2_pairs(V, I, J), FP32_TOL, "c2 sampled")

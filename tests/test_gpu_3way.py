@@ -1,0 +1,130 @@
+"""3-way parity: the HIP path (through the C ABI) against the CPU oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from psx import (announce, check_exact_f32, check_rel, host, jslab, need_gpu, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP16_TOL = 1e-3
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def run3(V, **kw):
+    from paper_1705_08210_amd import ps
+    return host(ps.ps3(to_dev(V), **kw))
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_sparse_all_triples(tile):
+    V = workloads.sparse_uniform(150, 501, seed=31)   # 2 tiles of 128 + tail
+    announce(f"3-way sparse 150x501 tile={tile}")
+    c3 = run3(V, tile=tile)
+    check_rel(c3, oracle.c3_all(V), FP32_TOL, "c3")
+
+
+@pytest.mark.parametrize("acc", ["plain", "blocked"])
+def test_accumulation_modes(acc):
+    V = workloads.gwas_like(90, 2500, seed=32)
+    announce(f"3-way acc={acc}")
+    check_rel(run3(V, acc=acc), oracle.c3_all(V), FP32_TOL, "c3")
+
+
+@pytest.mark.parametrize("storage", ["f32", "u8"])
+def test_integer_levels_bit_exact(storage):
+    V = workloads.levels(140, 603, seed=33)
+    if storage == "f32":
+        V = V.astype(np.float32)
+    announce(f"3-way integer {storage}")
+    check_exact_f32(run3(V), oracle.c3_all(V), "c3")
+
+
+def test_fp16_storage():
+    V32 = workloads.sparse_uniform(100, 1200, seed=34)
+    V16 = workloads.to_f16(V32)
+    announce("3-way fp16")
+    c3 = run3(V16)
+    check_rel(c3, oracle.c3_all(V16), FP32_TOL, "c3 vs fp16 values")
+    check_rel(c3, oracle.c3_all(V32), FP16_TOL, "c3 vs fp32 source")
+
+
+@pytest.mark.parametrize("storage", ["f32", "u8"])
+def test_stages_concatenate_to_full_run(storage):
+    """The j-range is the restart unit of staged runs: consecutive stages,
+    concatenated, equal one full run bit for bit."""
+    from paper_1705_08210_amd import ps
+    V = workloads.levels(120, 400, seed=35) if storage == "u8" else \
+        workloads.sparse_uniform(120, 400, seed=35)
+    Vd = to_dev(V)
+    announce(f"3-way stages {storage}")
+    full = host(ps.ps3(Vd))
+    parts = [host(ps.ps3(Vd, j_begin=a, j_end=b)) for a, b in [(1, 2), (2, 40), (40, 41),
+                                                                (41, 119)]]
+    cat = np.concatenate(parts)
+    assert cat.shape == full.shape
+    assert np.array_equal(cat.view(np.uint32), full.view(np.uint32))
+
+
+def test_given_sums_and_numerators_identical():
+    from paper_1705_08210_amd import ps
+    V = workloads.sparse_uniform(110, 700, seed=36)
+    Vd = to_dev(V)
+    announce("3-way given s and n2")
+    s, _ = ps.vector_sums(Vd)
+    _, n2 = ps.ps2(Vd, want_c2=False, want_n2=True)
+    a = host(ps.ps3(Vd))
+    b = host(ps.ps3(Vd, s=s, n2=n2))
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("n_v,n_f", [(3, 1), (4, 2), (5, 64), (129, 3), (66, 65)])
+def test_edge_sizes(n_v, n_f):
+    V = workloads.sparse_uniform(n_v, n_f, seed=n_v * 7 + n_f)
+    announce(f"3-way edge n_v={n_v} n_f={n_f}")
+    check_rel(run3(V), oracle.c3_all(V), FP32_TOL, "c3")
+
+
+def test_zero_vectors():
+    V = workloads.uniform(30, 40, seed=37)
+    V[[2, 3, 9]] = 0.0
+    announce("3-way zero vectors")
+    c3 = run3(V)
+    ref = oracle.c3_all(V)
+    check_rel(c3, ref, FP32_TOL, "c3")
+    assert c3[jslab(30, 2, 3, 9)] == 0.0
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u8"])
+def test_nested_support_family_exact(storage):
+    """n3' = min(a) min(L) on the nested-support family: every path exact."""
+    n_v = 96
+    V, a, L = workloads.nested_support(n_v, 1500, seed=38, integer=(storage == "u8"))
+    if storage == "f16":
+        V = workloads.to_f16(V)
+    announce(f"3-way nested support {storage}")
+    c3 = run3(V)
+    j, k, i = [], [], []
+    for jj in range(1, n_v - 1):
+        kk, ii = np.meshgrid(np.arange(jj + 1, n_v), np.arange(jj), indexing="ij")
+        j.append(np.full(kk.size, jj))
+        k.append(kk.ravel())
+        i.append(ii.ravel())
+    i, j, k = (np.concatenate(x) for x in (i, j, k))
+    idx = jslab(n_v, i, j, k)
+    assert np.array_equal(idx, np.arange(len(idx)))
+
+    def n2(x, y):
+        return np.minimum(a[x], a[y]) * np.minimum(L[x], L[y])
+    n3 = n2(i, j) + n2(i, k) + n2(j, k) - np.minimum(np.minimum(a[i], a[j]), a[k]) * \
+        np.minimum(np.minimum(L[i], L[j]), L[k])
+    d = a[i] * L[i] + a[j] * L[j] + a[k] * L[k]
+    ref = np.where(d > 0, (3 * n3) / (2 * np.where(d > 0, d, 1)), 0.0)
+    check_exact_f32(c3, ref, "c3")
