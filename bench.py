@@ -32,9 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD16 units = 64 lanes per clock per CU, 2.4 GHz.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # non-packed VALU lane-ops / s
-INT8_MFMA_PEAK_TOPS = 5000.0                 # dense int8 matrix-core ops / s (2 per MAC)
+# MI355X: 256 CUs at 2.4 GHz.  FP32 vector 157.3 TFLOP/s = 128 FP32 lanes per
+# clock per CU (an FMA, a min or an add is one lane-op); measured: v_min_f32 and
+# v_add_f32 issue at that rate, while v_pk_min_f16, v_dot2c_f32_f16 and
+# v_sad_u8 issue at 64 lanes per clock per CU.
+FP32_LANE_OPS_TOPS = 256 * 128 * 2.4e9 / 1e12   # 78.64
+HALF_RATE_OPS_TOPS = 256 * 64 * 2.4e9 / 1e12    # 39.32
+INT8_MFMA_PEAK_TOPS = 5000.0                    # dense int8 matrix-core ops / s (2 per MAC)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -132,10 +136,11 @@ def cpu_baseline_triples(V, n_f, seconds, seed=123):
                       f"(oracle c3 of listed triples, pair terms included, {t:.1f} s)"}
 
 
-def roofline_valu(ops_per_cmp, cmp, kernel_ms):
+def roofline(bound, ops_per_cmp, cmp, kernel_ms, peak):
+    """achieved = algorithmic ops of one launch / its mean duration."""
     achieved = ops_per_cmp * cmp / (kernel_ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None}
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None}
 
 
 def main(argv=None):
@@ -181,13 +186,20 @@ def main(argv=None):
                 timer.add(a, timer.mark())
 
         cmp = n_f * m
-        if V.dtype == np.uint8:
-            dtype, ops_per_cmp = "u8", 0.25            # v_sad_u8: 4 comparisons / op
-        elif V.dtype == np.float16:
-            dtype, ops_per_cmp = "f16", 1.0            # pk_min + dot2 per 2 comparisons
-        else:
-            dtype, ops_per_cmp = "f32", 2.0            # min + add per comparison
-        kernel = "ps_mg2_kernel"
+        use_mfma = V.dtype == np.uint8 and (args.path == "mfma" or
+                                            (args.path == "auto" and 1 <= levels <= 15))
+        if use_mfma:   # thermometer planes: `levels` int8 MACs (2 ops) per comparison
+            dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
+            kernel = "ps_mfma2_kernel"
+        elif V.dtype == np.uint8:   # v_sad_u8: 4 comparisons per op
+            dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
+            kernel = "ps_mg2_kernel"
+        elif V.dtype == np.float16:  # pk_min + dot2 per 2 comparisons
+            dtype, bound, ops_per_cmp, peak = "f16", "alu", 1.0, HALF_RATE_OPS_TOPS
+            kernel = "ps_mg2_kernel"
+        else:                        # min + add per comparison
+            dtype, bound, ops_per_cmp, peak = "f32", "alu", 2.0, FP32_LANE_OPS_TOPS
+            kernel = "ps_mg2_kernel"
         config = {"workload": wl, "way": 2, "n_f": n_f, "n_v": n_v}
         cpu = (lambda: cpu_baseline_pairs(V, n_f, args.cpu_seconds))
         parity_fn = ("pairs", V)
@@ -212,7 +224,9 @@ def main(argv=None):
 
         cmp = n_f * math.comb(n_v, 3)
         dtype = "f16" if V.dtype == np.float16 else "f32"
-        ops_per_cmp = 1.0 if dtype == "f16" else 2.0
+        bound = "alu"
+        ops_per_cmp, peak = ((1.0, HALF_RATE_OPS_TOPS) if dtype == "f16"
+                             else (2.0, FP32_LANE_OPS_TOPS))
         kernel = "ps_mg3_kernel"
         config = {"workload": wl, "way": 3, "n_f": n_f, "n_v": n_v}
         cpu = (lambda: cpu_baseline_triples(V, n_f, args.cpu_seconds))
@@ -237,7 +251,7 @@ def main(argv=None):
                 plan.run()
                 if rec:
                     timer.add(a, timer.mark())
-        dtype, ops_per_cmp = "f32", 2.0
+        dtype, bound, ops_per_cmp, peak = "f32", "alu", 2.0, FP32_LANE_OPS_TOPS
         kernel = "ps_mgb_kernel" if not args.per_problem else "ps_mg2_kernel"
         config = {"workload": wl, "way": 2, "problems": len(Vs),
                   "mode": "per-problem launches" if args.per_problem else "one graph"}
@@ -290,7 +304,7 @@ def main(argv=None):
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic (seeded numpy PCG64)",
         "config": config,
-        "roofline": dict(roofline_valu(ops_per_cmp, cmp, kernel_ms), kernel=kernel,
+        "roofline": dict(roofline(bound, ops_per_cmp, cmp, kernel_ms, peak), kernel=kernel,
                          kernel_ms=round(kernel_ms, 4)),
     }
     if not args.no_cpu_baseline:

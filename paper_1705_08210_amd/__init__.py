@@ -5,5 +5,9 @@ include/ps.h (libps.so, hand-written HIP kernels); ``ps`` is its binding."""
 from .ps import (BatchedPlan, PSError, ps2, ps2_batched, ps3, stage_size, tile_configs,
                  tune_clear, tune_register, vector_sums)
 
+from . import autotune as _autotune
+
+_autotune.load()  # tuned tile choices, if a cache was written on this machine type
+
 __all__ = ["BatchedPlan", "PSError", "ps2", "ps2_batched", "ps3", "stage_size",
            "tile_configs", "tune_clear", "tune_register", "vector_sums"]

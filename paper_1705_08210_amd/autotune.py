@@ -1,0 +1,131 @@
+"""Tile tuner for the VALU min-product kernels.
+
+Times every compiled tile configuration (``ps_tile_config``) through the C ABI
+on seeded synthetic inputs of representative shapes, and keeps the fastest per
+(storage type, way, n_f bucket, n_v bucket) in a JSON cache.  ``load()``
+registers a cache with the library (``ps_tune_register``), after which
+``opts.tile = 0`` picks the tuned configuration.  Runs off the timed path.
+
+    python -m paper_1705_08210_amd.autotune [--quick] [--out FILE]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import ps
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+# bucket edges: [lo, hi)
+NF_BUCKETS = [(0, 2048), (2048, 8192), (8192, 1 << 40)]
+NV_BUCKETS = [(0, 1024), (1024, 4096), (4096, 1 << 40)]
+# representative shapes per bucket (n_f, n_v) -- a tile choice depends on
+# how many tiles fill the chip and on the depth of the field loop
+REPS = {
+    2: {(0, 0): (1024, 512), (0, 1): (1024, 2048), (0, 2): (1024, 8192),
+        (1, 0): (4096, 512), (1, 1): (4096, 2048), (1, 2): (4096, 8192),
+        (2, 0): (16384, 512), (2, 1): (16384, 2048), (2, 2): (16384, 6144)},
+    3: {(0, 0): (1024, 256), (1, 0): (4096, 384), (2, 0): (12000, 256),
+        (0, 1): (1024, 1024), (1, 1): (4096, 1024), (2, 1): (12000, 1024)},
+}
+DTYPES = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}
+
+
+def _input(n_v, n_f, dt, seed=0):
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    if dt == torch.uint8:
+        return torch.randint(0, 4, (n_v, n_f), device="cuda", dtype=torch.uint8, generator=g)
+    x = torch.rand((n_v, n_f), device="cuda", generator=g)
+    x = torch.where(torch.rand((n_v, n_f), device="cuda", generator=g) < 0.5, 0.0, x)
+    return x.to(dt)
+
+
+def _time(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    best = math.inf
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3), reps=3, quick=False, log=print):
+    out = []
+    for dname in dtypes:
+        dt = DTYPES[dname]
+        ncfg = len(ps.tile_configs(dt, 2))
+        for way in ways:
+            for (fb, vb), (n_f, n_v) in REPS[way].items():
+                if quick and (fb, vb) not in ((1, 1), (2, 2), (1, 0)):
+                    continue
+                V = _input(n_v, n_f, dt)
+                s, _ = ps.vector_sums(V, want_bad=False)
+                if way == 3:
+                    _, n2 = ps.ps2(V, s=s, want_c2=False, want_n2=True)
+                    c3 = torch.empty(math.comb(n_v, 3), device="cuda")
+                else:
+                    c2 = torch.empty(n_v * (n_v - 1) // 2, device="cuda")
+                times = []
+                for idx in range(ncfg):
+                    if way == 2:
+                        f = (lambda i=idx: ps.ps2(V, s=s, c2=c2, path="valu", tile=i + 1))
+                    else:
+                        f = (lambda i=idx: ps.ps3(V, s=s, n2=n2, c3=c3, tile=i + 1))
+                    times.append(_time(f, reps))
+                best = int(np.argmin(times))
+                rec = {"dtype": dname, "way": way, "nf": list(NF_BUCKETS[fb]),
+                       "nv": list(NV_BUCKETS[vb]), "shape": [n_f, n_v], "tile": best,
+                       "ms": [round(t, 4) for t in times]}
+                log(json.dumps(rec))
+                out.append(rec)
+                del V
+                torch.cuda.empty_cache()
+    return {"device": torch.cuda.get_device_name(0), "time": time.time(), "entries": out}
+
+
+def save(cache, path=CACHE):
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1)
+
+
+def load(path=CACHE) -> int:
+    """Register the cached choices with libps; returns the number registered."""
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        cache = json.load(f)
+    n = 0
+    for e in cache.get("entries", []):
+        ps.tune_register(DTYPES[e["dtype"]], e["way"], "valu", e["nf"], e["nv"], e["tile"])
+        n += 1
+    return n
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=CACHE)
+    ap.add_argument("--dtypes", default="f32,f16,u8")
+    a = ap.parse_args(argv)
+    cache = tune(tuple(a.dtypes.split(",")), reps=a.reps, quick=a.quick)
+    save(cache, a.out)
+    print(f"wrote {a.out} ({len(cache['entries'])} entries)")
+
+
+if __name__ == "__main__":
+    main()

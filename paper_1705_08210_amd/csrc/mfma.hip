@@ -1,16 +1,238 @@
-// mfma.hip -- thermometer int8 matrix-core path for integer-level data.
+// mfma.hip -- 2-way numerators on the matrix cores for integer-level data.
+//
+// For integer values 0 <= v <= L,
+//   min(a, b) = sum_{t=1..L} [a >= t] [b >= t],
+// so with the 0/1 "thermometer" planes T_t = [V >= t] the pair numerators are
+//   n2(i, j) = sum_t sum_q T_t[i, q] T_t[j, q],
+// a dense int8 contraction over K = L * n_f, exact in int32.  This is the
+// paper's min-product (Section 3.1) recast so that the matrix cores can run
+// it.
+//
+// Two kernels:
+//   ps_thermo_expand_kernel  V (uint8, n_v x ld) -> planes P (int8,
+//                            n_v x L*kpad), kpad = n_f rounded up to 64;
+//                            HBM-bound, one pass.
+//   ps_mfma2_kernel          upper-triangle tiles of P P^T with
+//                            v_mfma_i32_32x32x32_i8, FP64 epilogue.
 #include "ps_internal.h"
 
 namespace ps {
 
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+constexpr int kMB = 256;      // output tile rows and columns
+constexpr int kMK = 64;       // field-tile depth in plane bytes
+constexpr int kPitch = 80;    // LDS bytes per tile row (64 + 16: conflict-free b128 reads)
+constexpr int kGroup = 8;     // tile columns per L2-sharing group
+
 size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels) {
-    (void)n_f; (void)n_v; (void)levels;
-    return 0;
+    const int64_t kpad = (n_f + kMK - 1) / kMK * kMK;
+    return (size_t)n_v * (size_t)levels * (size_t)(kpad > 0 ? kpad : kMK);
 }
 
-hipError_t launch_mfma2(const MfmaLaunch& a, hipStream_t st) {
-    (void)a; (void)st;
-    return hipErrorNotSupported;
+// ---------------------------------------------------------------------------
+// Thermometer planes.  One thread per 16 fields of one vector.  For byte
+// values v <= 127, (v | 0x80) - t keeps bit 7 iff v >= t and never borrows
+// across bytes, so four bytes are thresholded per 32-bit operation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ge_bytes(uint32_t x, uint32_t t) {
+    return (((x | 0x80808080u) - t * 0x01010101u) >> 7) & 0x01010101u;
+}
+
+__global__ __launch_bounds__(256) void ps_thermo_expand_kernel(const uint8_t* V, int64_t n_f,
+                                                               int64_t n_v, int64_t ld,
+                                                               int levels, int64_t kpad,
+                                                               int8_t* P) {
+    const int64_t nch = kpad / 16;
+    const int64_t total = n_v * nch;
+    const bool vec = ((uintptr_t)V % 16 == 0) && (ld % 16 == 0);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = t / nch, ch = t % nch;
+        const int64_t q0 = ch * 16;
+        const uint8_t* src = V + row * ld + q0;
+        union { uint4 v; uint8_t b[16]; } u;
+        if (vec && q0 + 16 <= n_f) {
+            u.v = *(const uint4*)src;
+        } else {
+            u.v = make_uint4(0, 0, 0, 0);
+            for (int e = 0; e < 16; ++e)
+                if (q0 + e < n_f) u.b[e] = src[e];
+        }
+        int8_t* dst = P + row * (int64_t)levels * kpad + q0;
+        for (int lev = 1; lev <= levels; ++lev) {
+            uint4 o;
+            o.x = ge_bytes(u.v.x, lev);
+            o.y = ge_bytes(u.v.y, lev);
+            o.z = ge_bytes(u.v.z, lev);
+            o.w = ge_bytes(u.v.w, lev);
+            *(uint4*)(dst + (int64_t)(lev - 1) * kpad) = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile order: columns of the upper triangle are taken kGroup at a time and,
+// inside a group, row by row, so the tiles that run side by side on one XCD
+// share their row and column blocks in L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grouped_tri_decode(int64_t t, int64_t nb, int64_t& bi,
+                                                   int64_t& bj) {
+    // callers guarantee 0 <= t < nb (nb + 1) / 2; every loop below is bounded
+    bi = bj = 0;
+    for (int64_t g0 = 0; g0 < nb; g0 += kGroup) {  // group of columns [g0, g1)
+        const int64_t g1 = g0 + kGroup < nb ? g0 + kGroup : nb;
+        const int64_t cnt = (g1 * (g1 + 1) - g0 * (g0 + 1)) / 2;
+        if (t >= cnt) {
+            t -= cnt;
+            continue;
+        }
+        for (int64_t r = 0; r < g1; ++r) {  // row r covers columns max(r, g0) .. g1-1
+            const int64_t c0 = r > g0 ? r : g0;
+            const int64_t w = g1 - c0;
+            if (t < w) {
+                bi = r;
+                bj = c0 + t;
+                return;
+            }
+            t -= w;
+        }
+        return;
+    }
+}
+
+struct MfmaArgs {
+    const int8_t* P;
+    int64_t kp;           // plane-row length in bytes (levels * kpad), multiple of kMK
+    int64_t n_v;
+    const double* s;
+    float* c2;
+    int32_t* n2;
+    int64_t nb, ntiles;
+};
+
+// 512 threads = 8 waves; wave w owns j rows [(w%2)*128, +128) and i columns
+// [(w/2)*64, +64) of the 256 x 256 tile: 4 x 2 blocks of 32 x 32.
+constexpr int kMThreads = 512;
+
+__global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t As[kMB * kPitch];   // j rows
+    __shared__ __attribute__((aligned(16))) int8_t Bs[kMB * kPitch];   // i rows
+    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    if (t >= a.ntiles) return;
+    int64_t bi, bj;
+    grouped_tri_decode(t, a.nb, bi, bj);
+    const int64_t i0 = bi * kMB, j0 = bj * kMB;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wr = (wave % 2) * 128;        // j offset of the wave's block
+    const int wc = (wave / 2) * 64;         // i offset
+    // some i < j with both < n_v among rows j0+wr.. and columns i0+wc..?
+    const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
+
+    v16i_t acc[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = (v16i_t){};
+
+    // staging: 256 rows x 64 bytes per operand = 1024 16-byte chunks; 2 + 2
+    // per thread, four threads per row
+    uint4 ra[2], rb[2];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int idx = threadIdx.x + c * kMThreads;
+            const int row = idx / 4, ch = idx % 4;
+            const int64_t gj = j0 + row, gi = i0 + row;
+            ra[c] = gj < a.n_v ? *(const uint4*)(a.P + gj * a.kp + k0 + ch * 16)
+                               : make_uint4(0, 0, 0, 0);
+            rb[c] = gi < a.n_v ? *(const uint4*)(a.P + gi * a.kp + k0 + ch * 16)
+                               : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int idx = threadIdx.x + c * kMThreads;
+            const int row = idx / 4, ch = idx % 4;
+            *(uint4*)(As + row * kPitch + ch * 16) = ra[c];
+            *(uint4*)(Bs + row * kPitch + ch * 16) = rb[c];
+        }
+    };
+
+    const int64_t nk = a.kp / kMK;
+    load(0);
+    const int fr = lane % 32, fk = (lane / 32) * 16;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (kt + 1 < nk) load((kt + 1) * kMK);
+        if (!active) continue;
+#pragma unroll
+        for (int ks = 0; ks < kMK / 32; ++ks) {
+            v4i_t fa[4], fb[2];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                fa[m] = *(const v4i_t*)(As + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+                fb[n] = *(const v4i_t*)(Bs + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n], acc[m][n],
+                                                                      0, 0, 0);
+        }
+    }
+    if (!active) return;
+
+    // D[row][col] of a 32x32 block: col = lane % 32, row = (r/4)*8 + (lane/32)*4 + r%4;
+    // rows are j, columns are i, so 32 lanes store 32 consecutive i of one j
+    const int64_t ib = i0 + wc + (lane % 32);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t j = j0 + wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
+            if (j >= a.n_v) continue;
+            const double sj = a.s[j];
+            const int64_t base = j * (j - 1) / 2;
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const int64_t i = ib + n * 32;
+                if (i >= j) continue;
+                const int32_t num = acc[m][n][r];
+                if (a.n2) a.n2[base + i] = num;
+                if (a.c2) {
+                    const double d = a.s[i] + sj;
+                    a.c2[base + i] = d > 0.0 ? (float)((2.0 * (double)num) / d) : 0.0f;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_mfma2(const MfmaLaunch& m, hipStream_t st) {
+    if (m.n_v < 2) return hipSuccess;
+    const int64_t kpad = (m.n_f + kMK - 1) / kMK * kMK;
+    const int64_t kp = (int64_t)m.levels * (kpad > 0 ? kpad : kMK);
+    const int64_t total = m.n_v * ((kpad > 0 ? kpad : kMK) / 16);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(ps_thermo_expand_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const uint8_t*)m.V, m.n_f, m.n_v, m.ld, m.levels,
+                       kpad > 0 ? kpad : (int64_t)kMK, m.planes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nb = (m.n_v + kMB - 1) / kMB;
+    const int64_t T = nb * (nb + 1) / 2;
+    MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T};
+    const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(ps_mfma2_kernel, dim3((unsigned)grid), dim3(kMThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace ps

@@ -18,7 +18,7 @@ __device__ __forceinline__ bool rows_vec_ok(const void* V, int64_t ld) {
 // symmetry reduction of Section 2.1).
 // ---------------------------------------------------------------------------
 template <int DT, int TM, int BKW, bool BLOCKED>
-__global__ __launch_bounds__(kThreads, 2) void ps_mg2_kernel(Mg2Launch a, int64_t ntiles) {
+__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launch a, int64_t ntiles) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
@@ -97,7 +97,7 @@ __device__ __forceinline__ void epilogue3(const typename Ops<DT>::Acc (&acc)[TM]
 }
 
 template <int DT, int TM, int BKW, bool BLOCKED>
-__global__ __launch_bounds__(kThreads, 2) void ps_mg3_kernel(Mg3Launch a) {
+__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launch a) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kThreads, 2) void ps_mg3_kernel(Mg3Launch a) {
 // list (ordered longest first on the host) through an atomic work counter.
 // ---------------------------------------------------------------------------
 template <int DT, int TM, int BKW, bool BLOCKED>
-__global__ __launch_bounds__(kThreads, 2) void ps_mgb_kernel(MgBatchLaunch a) {
+__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchLaunch a) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];

@@ -218,3 +218,34 @@ def test_sampled_pairs_match_listed_oracle():
     announce("2-way sampled pairs 700x4000")
     c2, _ = run2(V)
     check_rel(c2[colex(I, J)], oracle.c2_pairs(V, I, J), FP32_TOL, "c2 sampled")
+
+
+# ------------------------------------------------ thermometer MFMA path ----
+
+@pytest.mark.parametrize("n_v,n_f,L", [(300, 1001, 3), (257, 64, 1), (513, 333, 7),
+                                       (2, 5, 3), (256, 128, 3), (40, 3000, 15)])
+def test_mfma_thermometer_bit_exact(n_v, n_f, L):
+    """min(a,b) = sum_t [a>=t][b>=t] on integer levels: the int8 matrix-core
+    path must equal the oracle (and the VALU path) bit for bit."""
+    probs = np.full(L + 1, 1.0 / (L + 1))
+    V = workloads.levels(n_v, n_f, seed=n_v + L, probs=probs)
+    announce(f"2-way mfma n_v={n_v} n_f={n_f} L={L}")
+    c2, n2 = run2(V, path="mfma", levels=L)
+    ref, rn2 = oracle.c2_all(V, with_n2=True)
+    check_exact_f32(c2, ref, "c2")
+    assert np.array_equal(n2.astype(np.float64), rn2)
+    v2, vn2 = run2(V, path="valu")
+    assert np.array_equal(c2.view(np.uint32), v2.view(np.uint32))
+    assert np.array_equal(n2, vn2)
+
+
+def test_mfma_auto_path_and_unaligned_rows():
+    """levels in 1..15 selects the matrix-core path by default; rows whose
+    pitch is not 16-byte aligned are expanded element by element."""
+    from paper_1705_08210_amd import ps
+    big = workloads.levels(200, 517, seed=41)
+    V = big[:, :511]
+    announce("2-way mfma auto + unaligned")
+    Vd = to_dev(big)[:, :511]
+    c2, _ = ps.ps2(Vd, levels=3)
+    check_exact_f32(host(c2), oracle.c2_all(V), "c2")
