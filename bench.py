@@ -57,6 +57,9 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-problem", action="store_true",
                     help="batched workload: one launch per problem instead of the plan")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device (a plain copy kernel of known "
+                         "size, to scale HBM byte counters of a profiler run)")
     return ap.parse_args(argv)
 
 
@@ -261,6 +264,14 @@ def main(argv=None):
     else:
         print(f"unknown workload {wl}", file=sys.stderr)
         return 2
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        extra["copy_calibration_bytes"] = 1 << 30
+        del src, dst
 
     for _ in range(W):
         step(False)

@@ -34,9 +34,10 @@ hipError_t launch_mg2_u8(const Mg2Launch& a, hipStream_t st) {
 }
 
 hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st) {
-    return dispatch(a.cfg, a.acc, [&](auto tm, auto bkw, auto bl) {
+    hipError_t e = dispatch(a.cfg, a.acc, [&](auto tm, auto bkw, auto bl) {
         return go_mg3<PS_U8, decltype(tm)::value, decltype(bkw)::value, decltype(bl)::value>(a, st);
     });
+    return e == hipSuccess ? go_c3_finish<PS_U8>(a, st) : e;
 }
 
 hipError_t launch_mgb_u8(const MgBatchLaunch& a, hipStream_t st) {

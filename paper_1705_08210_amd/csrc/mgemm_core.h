@@ -200,31 +200,6 @@ __device__ __forceinline__ int lane_col(int wave, int ly, int c) {
 }
 
 // ---------------------------------------------------------------------------
-// One field word of the micro-tile: p[r][c] (+)= term(a[r], b[c]).  For the
-// floating types the terms of a row are formed first and added afterwards,
-// so no add waits on the min issued just before it.
-// ---------------------------------------------------------------------------
-template <int DT, int TM, int TN, bool FIRST>
-__device__ __forceinline__ void mac(typename Ops<DT>::Acc (&p)[TM][TN], const uint32_t (&a)[TM],
-                                    const uint32_t (&b)[TN]) {
-#pragma unroll
-    for (int r = 0; r < TM; ++r) {
-        if constexpr (DT == PS_U8) {
-#pragma unroll
-            for (int c = 0; c < TN; ++c)
-                p[r][c] = FIRST ? Ops<DT>::first(a[r], b[c]) : Ops<DT>::step(p[r][c], a[r], b[c]);
-        } else {
-            uint32_t t[TN];
-#pragma unroll
-            for (int c = 0; c < TN; ++c) t[c] = Ops<DT>::term(a[r], b[c]);
-#pragma unroll
-            for (int c = 0; c < TN; ++c)
-                p[r][c] = FIRST ? Ops<DT>::accum(0.0f, t[c]) : Ops<DT>::accum(p[r][c], t[c]);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // One output tile.  acc receives the sums for the lane's micro-tile.
 //   A rows [a_row0, a_row0 + BM) valid below a_end (optionally X_j-staged
 //   against row xj), B rows [b_row0, b_row0 + BN) valid below b_end.
@@ -253,55 +228,83 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
 
     const int64_t tile_bytes = (int64_t)BKW * 4;
     const int64_t nk = (nbytes + tile_bytes - 1) / tile_bytes;
+    // The plain 2-way variant prefetches the next field tile into registers
+    // while computing; the blocked variant (twice the accumulators) and the
+    // 3-way slices (which also stage v_j) load each tile just before staging
+    // it and rely on the other resident workgroups to cover the latency.
+    constexpr bool kPrefetch = !BLOCKED && !XJ;
     SA sa;
     SB sb;
-    if (nk > 0) {
+    if (kPrefetch && nk > 0) {
         sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, 0, nbytes, vec, xrow);
         sb.template load<DT, false>(Vb, ldb, b_row0, b_end, 0, nbytes, vec, nullptr);
     }
     for (int64_t kt = 0; kt < nk; ++kt) {
+        if (!kPrefetch) {
+            const int64_t kb = kt * tile_bytes;
+            sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
+            sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
+        }
         __syncthreads();  // previous tile's LDS reads are done
         sa.store(As);
         sb.store(Bs);
         __syncthreads();
-        if (kt + 1 < nk) {  // prefetch the next field tile into registers
+        if (kPrefetch && kt + 1 < nk) {  // prefetch the next field tile into registers
             const int64_t kb = (kt + 1) * tile_bytes;
             sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
             sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
         }
         if (!active) continue;
-        Acc p[TM][TN];
-        uint32_t a0[TM], b0[TN], a1[TM], b1[TN];
-        // operands of field word w: 16-byte reads, software-pipelined one
-        // word ahead of the arithmetic
-        auto rd = [&](uint32_t (&a)[TM], uint32_t (&b)[TN], int w) {
-#pragma unroll
-            for (int g = 0; g < TM / 4; ++g)
-                *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
-#pragma unroll
-            for (int g = 0; g < TN / 4; ++g)
-                *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
-        };
-        rd(a0, b0, 0);
-        rd(a1, b1, 1);
         if constexpr (BLOCKED) {
-            mac<DT, TM, TN, true>(p, a0, b0);    // the tile's partial starts here
-        } else {
-            mac<DT, TM, TN, false>(acc, a0, b0);
-        }
-#pragma unroll 1
-        for (int w = 2; w < BKW; w += 2) {
-            rd(a0, b0, w);
-            mac<DT, TM, TN, false>(BLOCKED ? p : acc, a1, b1);
-            rd(a1, b1, w + 1);
-            mac<DT, TM, TN, false>(BLOCKED ? p : acc, a0, b0);
-        }
-        mac<DT, TM, TN, false>(BLOCKED ? p : acc, a1, b1);
-        if constexpr (BLOCKED) {
+            Acc p[TM][TN];
+            {
+                uint32_t a[TM], b[TN];
+#pragma unroll
+                for (int g = 0; g < TM / 4; ++g)
+                    *(uint4*)&a[4 * g] = *(const uint4*)&As[ar + g * 32];
+#pragma unroll
+                for (int g = 0; g < TN / 4; ++g)
+                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[bc + g * 32];
+#pragma unroll
+                for (int r = 0; r < TM; ++r)
+#pragma unroll
+                    for (int c = 0; c < TN; ++c) p[r][c] = Ops<DT>::first(a[r], b[c]);
+            }
+#pragma unroll PS_UNROLL_BLOCKED
+            for (int w = 1; w < BKW; ++w) {
+                uint32_t a[TM], b[TN];
+#pragma unroll
+                for (int g = 0; g < TM / 4; ++g)
+                    *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
+#pragma unroll
+                for (int g = 0; g < TN / 4; ++g)
+                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
+#pragma unroll
+                for (int r = 0; r < TM; ++r)
+#pragma unroll
+                    for (int c = 0; c < TN; ++c) p[r][c] = Ops<DT>::step(p[r][c], a[r], b[c]);
+            }
 #pragma unroll
             for (int r = 0; r < TM; ++r)
 #pragma unroll
                 for (int c = 0; c < TN; ++c) acc[r][c] += p[r][c];
+        } else {
+            constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
+#pragma unroll kUnroll
+            for (int w = 0; w < BKW; ++w) {
+                uint32_t a[TM], b[TN];
+#pragma unroll
+                for (int g = 0; g < TM / 4; ++g)
+                    *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
+#pragma unroll
+                for (int g = 0; g < TN / 4; ++g)
+                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
+#pragma unroll
+                for (int r = 0; r < TM; ++r)
+#pragma unroll
+                    for (int c = 0; c < TN; ++c)
+                        acc[r][c] = Ops<DT>::step(acc[r][c], a[r], b[c]);
+            }
         }
     }
 }

@@ -49,49 +49,28 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
 // With j the middle index the rectangle i < j, k > j holds every triple once.
 // ---------------------------------------------------------------------------
 
-// 3-way epilogue: n3 from Eq. 1 with the pair numerators looked up from the
-// colex table, c3 = (3 n3) / (2 d3) in FP64 (Section 2.2).
+// 3-way, first half of the epilogue: the raw slice sums (n3' for the
+// floating types, sum |min(v_i,v_j) - v_k| for uint8) are stored as 32-bit
+// patterns at the triple's packed index; ps_c3_finish_kernel turns them into
+// c3 in place.  Keeping Eq. 1 out of the tile kernel keeps its register
+// footprint (and so its occupancy) that of the bare min-product.
 template <int DT, int TM, int TN>
-__device__ __forceinline__ void epilogue3(const typename Ops<DT>::Acc (&acc)[TM][TN],
-                                          int64_t row0, int64_t col0, int64_t j,
-                                          const Mg3Launch& a) {
-    using N2T = typename std::conditional<DT == PS_U8, int32_t, float>::type;
-    const N2T* N2 = (const N2T*)a.n2;
+__device__ __forceinline__ void store_slice(const typename Ops<DT>::Acc (&acc)[TM][TN],
+                                            int64_t row0, int64_t col0, int64_t j,
+                                            const Mg3Launch& a) {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int lx = lane % 8, ly = lane / 8;
-    const int64_t n_v = a.n_v;
-    const double sj = a.s[j];
-    const int64_t base = slab_offset(n_v, j) - slab_offset(n_v, a.j_begin);
-    double sk[TN], njk[TN];
-#pragma unroll
-    for (int c = 0; c < TN; ++c) {
-        const int64_t k = col0 + lane_col<TN>(wave, ly, c);
-        sk[c] = k < n_v ? a.s[k] : 0.0;
-        njk[c] = k < n_v ? (double)N2[k * (k - 1) / 2 + j] : 0.0;
-    }
+    const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin);
+    uint32_t* out = (uint32_t*)a.c3;
 #pragma unroll
     for (int r = 0; r < TM; ++r) {
         const int64_t i = row0 + lane_row<TM>(wave, lx, r);
         if (i >= j) continue;
-        const double si = a.s[i];
-        const double nij = (double)N2[j * (j - 1) / 2 + i];
 #pragma unroll
         for (int c = 0; c < TN; ++c) {
             const int64_t k = col0 + lane_col<TN>(wave, ly, c);
-            if (k >= n_v) continue;
-            const double nik = (double)N2[k * (k - 1) / 2 + i];
-            double n3p;
-            if constexpr (DT == PS_U8) {
-                // sum_q min(x, v_k) = (sum x + s_k - sum |x - v_k|) / 2, with
-                // x = min(v_i, v_j) so that sum x = n2(i, j)
-                n3p = (double)(((int64_t)nij + (int64_t)sk[c] - (int64_t)acc[r][c]) / 2);
-            } else {
-                n3p = (double)acc[r][c];
-            }
-            const double n3 = ((nij + nik) + njk[c]) - n3p;
-            const double d3 = (si + sj) + sk[c];
-            const int64_t idx = base + (k - j - 1) * j + i;
-            a.c3[idx] = d3 > 0.0 ? (float)((3.0 * n3) / (2.0 * d3)) : 0.0f;
+            if (k >= a.n_v) continue;
+            out[base + (k - j - 1) * j + i] = __builtin_bit_cast(uint32_t, acc[r][c]);
         }
     }
 }
@@ -126,7 +105,53 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
     run_tile<DT, TM, TM, BKW, BLOCKED, true>(Vb, ldb, nbytes, rows_vec_ok<DT>(a.V, a.ld),
                                              row0, j, col0, a.n_v, Vb + j * ldb, active,
                                              As, Bs, acc);
-    if (active) epilogue3<DT, TM, TM>(acc, row0, col0, j, a);
+    if (active) store_slice<DT, TM, TM>(acc, row0, col0, j, a);
+}
+
+// 3-way, second half of the epilogue (Eq. 1, Section 2.2): one workgroup per
+// slice j; the triples of the slice are contiguous in the j-slab layout, with
+// i fastest.  n3 = ((n2(i,j) + n2(i,k)) + n2(j,k)) - n3', d3 = (s_i + s_j) + s_k,
+// c3 = (3 n3) / (2 d3) in FP64, rounded once to FP32.
+template <int DT>
+__global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
+    using N2T = typename std::conditional<DT == PS_U8, int32_t, float>::type;
+    const int64_t j = a.j_begin + blockIdx.x;
+    if (j >= a.j_end) return;
+    const N2T* N2 = (const N2T*)a.n2;
+    const int64_t n_v = a.n_v;
+    const int64_t base = slab_offset(n_v, j) - slab_offset(n_v, a.j_begin);
+    const int64_t cnt = (n_v - 1 - j) * j;
+    const double sj = a.s[j];
+    const int64_t nj = j * (j - 1) / 2;
+    uint32_t* io = (uint32_t*)a.c3;
+    for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+        const int64_t k = j + 1 + t / j, i = t % j;
+        const uint32_t raw = io[base + t];
+        const double nij = (double)N2[nj + i];
+        const double nik = (double)N2[k * (k - 1) / 2 + i];
+        const double njk = (double)N2[k * (k - 1) / 2 + j];
+        const double sk = a.s[k];
+        double n3p;
+        if constexpr (DT == PS_U8) {
+            // sum_q min(x, v_k) = (sum x + s_k - sum |x - v_k|) / 2 with
+            // x = min(v_i, v_j), so sum x = n2(i, j)
+            n3p = (double)(((int64_t)nij + (int64_t)sk - (int64_t)raw) / 2);
+        } else {
+            n3p = (double)__builtin_bit_cast(float, raw);
+        }
+        const double n3 = ((nij + nik) + njk) - n3p;
+        const double d3 = (a.s[i] + sj) + sk;
+        io[base + t] = __builtin_bit_cast(uint32_t,
+                                          d3 > 0.0 ? (float)((3.0 * n3) / (2.0 * d3)) : 0.0f);
+    }
+}
+
+template <int DT>
+hipError_t go_c3_finish(const Mg3Launch& a, hipStream_t st) {
+    if (a.j_end <= a.j_begin) return hipSuccess;
+    hipLaunchKernelGGL(ps_c3_finish_kernel<DT>, dim3((unsigned)(a.j_end - a.j_begin)),
+                       dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
