@@ -73,11 +73,14 @@ typedef enum {
 
 /* FP32 accumulation of the numerator sums (floating storage only). */
 typedef enum {
-    PS_ACC_AUTO = 0,     /* BLOCKED when n_f > 2048, else PLAIN */
-    PS_ACC_PLAIN = 1,    /* one running FP32 sum per output */
-    PS_ACC_BLOCKED = 2   /* FP32 partial per field tile, then added to the
-                            running sum: error grows with tile + n_f/tile
-                            instead of n_f */
+    PS_ACC_AUTO = 0,     /* BLOCKED when n_f > 4096, else PLAIN */
+    PS_ACC_PLAIN = 1,    /* one running FP32 sum per output over all fields */
+    PS_ACC_BLOCKED = 2   /* ps2_compute / ps3_compute: the fields are split
+                            into chunks of 4096, each chunk is summed in FP32
+                            and the chunk sums are added in FP64 in a fixed
+                            order (deterministic; needs workspace for the
+                            chunk partials).  Batched calls: an FP32 partial
+                            per field tile added to the running FP32 sum. */
 } ps_acc;
 
 /* Compute path for the pair numerators. */
@@ -140,9 +143,11 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
                       void* workspace, size_t ws_bytes, const ps_opts* opts,
                       hipStream_t stream);
 
-/* Workspace bytes that ps3_compute needs (s_given / n2_given as passed). */
+/* Workspace bytes that ps3_compute needs for the stage [j_begin, j_end)
+ * (s_given / n2_given as they will be passed). */
 size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
-                          int32_t s_given, int32_t n2_given, const ps_opts* opts);
+                          int32_t s_given, int32_t n2_given, int64_t j_begin,
+                          int64_t j_end, const ps_opts* opts);
 
 /*
  * 3-way metric over the triples i<j<k whose middle index j lies in

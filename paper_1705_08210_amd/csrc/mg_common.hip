@@ -186,6 +186,36 @@ __global__ __launch_bounds__(1024) void ps_prefix3_kernel(int64_t n_v, int64_t j
     if (nj == 0 && threadIdx.x == 0) prefix[0] = 0;
 }
 
+// Field-chunk split, 2-way finish: n2 = sum over chunks in FP64 (fixed order),
+// then the Section 2.1 ratio.  One thread per pair, colex order.
+__global__ __launch_bounds__(256) void ps_finish2_kernel(Mg2Launch a) {
+    const int64_t np = a.n_v * (a.n_v - 1) / 2;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < np;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = (int64_t)((1.0 + __builtin_sqrt(1.0 + 8.0 * (double)idx)) * 0.5);
+        while (j * (j - 1) / 2 > idx) --j;
+        while ((j + 1) * j / 2 <= idx) ++j;
+        const int64_t i = idx - j * (j - 1) / 2;
+        double num = 0.0;
+        for (int c = 0; c < a.nchunks; ++c) num += (double)a.partial[c * np + idx];
+        if (a.n2) ((float*)a.n2)[idx] = (float)num;
+        if (a.c2) {
+            const double d = a.s[i] + a.s[j];
+            a.c2[idx] = d > 0.0 ? (float)((2.0 * num) / d) : 0.0f;
+        }
+    }
+}
+
+hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
+    (void)dt;  // the split applies to floating storage only; partials are FP32
+    const int64_t np = a.n_v * (a.n_v - 1) / 2;
+    if (np <= 0) return hipSuccess;
+    int64_t blocks = (np + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(ps_finish2_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
     const int bm = kValuCfgs[a.cfg].bm();
     hipLaunchKernelGGL(ps_prefix3_kernel, dim3(1), dim3(1024), 0, st, a.n_v, a.j_begin,

@@ -204,13 +204,15 @@ __device__ __forceinline__ int lane_col(int wave, int ly, int c) {
 //   A rows [a_row0, a_row0 + BM) valid below a_end (optionally X_j-staged
 //   against row xj), B rows [b_row0, b_row0 + BN) valid below b_end.
 //   active: whether this wave does the arithmetic.
+//   [kt0, kt1): the field tiles summed (kt1 < 0: all of them).
 // ---------------------------------------------------------------------------
 template <int DT, int TM, int TN, int BKW, bool BLOCKED, bool XJ>
 __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nbytes,
                                          bool vec, int64_t a_row0, int64_t a_end,
                                          int64_t b_row0, int64_t b_end, const char* xrow,
                                          bool active, uint32_t* As, uint32_t* Bs,
-                                         typename Ops<DT>::Acc (&acc)[TM][TN]) {
+                                         typename Ops<DT>::Acc (&acc)[TM][TN],
+                                         int64_t kt0 = 0, int64_t kt1 = -1) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM, BN = 16 * TN;
     using SA = Stager<BM, BKW>;
@@ -227,7 +229,8 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
         for (int c = 0; c < TN; ++c) acc[r][c] = Acc(0);
 
     const int64_t tile_bytes = (int64_t)BKW * 4;
-    const int64_t nk = (nbytes + tile_bytes - 1) / tile_bytes;
+    const int64_t nk_all = (nbytes + tile_bytes - 1) / tile_bytes;
+    const int64_t nk = kt1 < 0 || kt1 > nk_all ? nk_all : kt1;
     // The plain 2-way variant prefetches the next field tile into registers
     // while computing; the blocked variant (twice the accumulators) and the
     // 3-way slices (which also stage v_j) load each tile just before staging
@@ -235,11 +238,12 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
     constexpr bool kPrefetch = !BLOCKED && !XJ;
     SA sa;
     SB sb;
-    if (kPrefetch && nk > 0) {
-        sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, 0, nbytes, vec, xrow);
-        sb.template load<DT, false>(Vb, ldb, b_row0, b_end, 0, nbytes, vec, nullptr);
+    if (kPrefetch && kt0 < nk) {
+        const int64_t kb = kt0 * tile_bytes;
+        sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
+        sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
     }
-    for (int64_t kt = 0; kt < nk; ++kt) {
+    for (int64_t kt = kt0; kt < nk; ++kt) {
         if (!kPrefetch) {
             const int64_t kb = kt * tile_bytes;
             sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);

@@ -17,14 +17,35 @@ __device__ __forceinline__ bool rows_vec_ok(const void* V, int64_t ld) {
 // (Section 3.1; tiles strictly below the diagonal are never visited, the
 // symmetry reduction of Section 2.1).
 // ---------------------------------------------------------------------------
+// Raw pair sums of one field chunk, colex order, as 32-bit patterns.
+template <int DT, int TM, int TN>
+__device__ __forceinline__ void store_pairs_raw(const typename Ops<DT>::Acc (&acc)[TM][TN],
+                                                int64_t row0, int64_t col0, int64_t n_v,
+                                                uint32_t* dst) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lx = lane % 8, ly = lane / 8;
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+        const int64_t i = row0 + lane_row<TM>(wave, lx, r);
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+            const int64_t j = col0 + lane_col<TN>(wave, ly, c);
+            if (j >= n_v || i >= j) continue;
+            dst[j * (j - 1) / 2 + i] = __builtin_bit_cast(uint32_t, acc[r][c]);
+        }
+    }
+}
+
 template <int DT, int TM, int BKW, bool BLOCKED>
 __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launch a, int64_t ntiles) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
     __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t >= ntiles) return;
+    // work item = (field chunk, tile), chunk-major
+    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+    if (w >= ntiles * a.nchunks) return;
+    const int64_t chunk = w / ntiles, t = w % ntiles;
     int64_t bi, bj;
     tri_decode(t, bi, bj);
     const int64_t row0 = bi * BM, col0 = bj * BM;
@@ -36,11 +57,19 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
     const bool active = r_lo < a.n_v && c_lo < a.n_v && r_lo + 1 < c_hi;
     const int64_t ldb = a.ld * Ops<DT>::kEsz;
     const int64_t nbytes = a.n_f * Ops<DT>::kEsz;
+    const int64_t kt0 = a.nchunks > 1 ? chunk * a.chunk_tiles : 0;
+    const int64_t kt1 = a.nchunks > 1 ? kt0 + a.chunk_tiles : -1;
     Acc acc[TM][TM];
     run_tile<DT, TM, TM, BKW, BLOCKED, false>((const char*)a.V, ldb, nbytes,
                                               rows_vec_ok<DT>(a.V, a.ld), row0, a.n_v,
-                                              col0, a.n_v, nullptr, active, As, Bs, acc);
-    if (active) epilogue2<DT, TM, TM>(acc, row0, col0, a.n_v, a.s, a.c2, a.n2);
+                                              col0, a.n_v, nullptr, active, As, Bs, acc,
+                                              kt0, kt1);
+    if (!active) return;
+    if (a.nchunks > 1)
+        store_pairs_raw<DT, TM, TM>(acc, row0, col0, a.n_v,
+                                    (uint32_t*)a.partial + chunk * (a.n_v * (a.n_v - 1) / 2));
+    else
+        epilogue2<DT, TM, TM>(acc, row0, col0, a.n_v, a.s, a.c2, a.n2);
 }
 
 // ---------------------------------------------------------------------------
@@ -57,11 +86,10 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
 template <int DT, int TM, int TN>
 __device__ __forceinline__ void store_slice(const typename Ops<DT>::Acc (&acc)[TM][TN],
                                             int64_t row0, int64_t col0, int64_t j,
-                                            const Mg3Launch& a) {
+                                            const Mg3Launch& a, uint32_t* out) {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int lx = lane % 8, ly = lane / 8;
     const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin);
-    uint32_t* out = (uint32_t*)a.c3;
 #pragma unroll
     for (int r = 0; r < TM; ++r) {
         const int64_t i = row0 + lane_row<TM>(wave, lx, r);
@@ -81,8 +109,9 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
     constexpr int BM = 16 * TM;
     __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
     __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t >= a.ntiles) return;
+    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+    if (w >= a.ntiles * a.nchunks) return;
+    const int64_t chunk = w / a.ntiles, t = w % a.ntiles;
     // slice j: largest jj with prefix[jj] <= t (every slice has >= 1 tile)
     int64_t lo = 0, hi = a.j_end - a.j_begin;
     while (hi - lo > 1) {
@@ -102,10 +131,18 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
     const int64_t nbytes = a.n_f * Ops<DT>::kEsz;
     const char* Vb = (const char*)a.V;
     Acc acc[TM][TM];
+    const int64_t kt0 = a.nchunks > 1 ? chunk * a.chunk_tiles : 0;
+    const int64_t kt1 = a.nchunks > 1 ? kt0 + a.chunk_tiles : -1;
     run_tile<DT, TM, TM, BKW, BLOCKED, true>(Vb, ldb, nbytes, rows_vec_ok<DT>(a.V, a.ld),
                                              row0, j, col0, a.n_v, Vb + j * ldb, active,
-                                             As, Bs, acc);
-    if (active) store_slice<DT, TM, TM>(acc, row0, col0, j, a);
+                                             As, Bs, acc, kt0, kt1);
+    if (active) {
+        uint32_t* dst = a.nchunks > 1
+                            ? (uint32_t*)a.partial +
+                                  chunk * (slab_offset(a.n_v, a.j_end) - slab_offset(a.n_v, a.j_begin))
+                            : (uint32_t*)a.c3;
+        store_slice<DT, TM, TM>(acc, row0, col0, j, a, dst);
+    }
 }
 
 // 3-way, second half of the epilogue (Eq. 1, Section 2.2): one workgroup per
@@ -124,9 +161,10 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
     const double sj = a.s[j];
     const int64_t nj = j * (j - 1) / 2;
     uint32_t* io = (uint32_t*)a.c3;
+    const int64_t stage = slab_offset(n_v, a.j_end) - slab_offset(n_v, a.j_begin);
     for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
         const int64_t k = j + 1 + t / j, i = t % j;
-        const uint32_t raw = io[base + t];
+        const uint32_t raw = a.nchunks > 1 ? 0u : io[base + t];
         const double nij = (double)N2[nj + i];
         const double nik = (double)N2[k * (k - 1) / 2 + i];
         const double njk = (double)N2[k * (k - 1) / 2 + j];
@@ -136,6 +174,9 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
             // sum_q min(x, v_k) = (sum x + s_k - sum |x - v_k|) / 2 with
             // x = min(v_i, v_j), so sum x = n2(i, j)
             n3p = (double)(((int64_t)nij + (int64_t)sk - (int64_t)raw) / 2);
+        } else if (a.nchunks > 1) {  // chunks of the field split, in FP64
+            n3p = 0.0;
+            for (int c = 0; c < a.nchunks; ++c) n3p += (double)a.partial[c * stage + base + t];
         } else {
             n3p = (double)__builtin_bit_cast(float, raw);
         }
@@ -197,16 +238,17 @@ template <int DT, int TM, int BKW, bool BL>
 hipError_t go_mg2(const Mg2Launch& a, hipStream_t st) {
     const int64_t T = tri_tiles(a.n_v, 16 * TM);
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL((ps_mg2_kernel<DT, TM, BKW, BL>), dim3((unsigned)round_up_xcd(T)),
-                       dim3(kThreads), 0, st, a, T);
+    hipLaunchKernelGGL((ps_mg2_kernel<DT, TM, BKW, BL>),
+                       dim3((unsigned)round_up_xcd(T * a.nchunks)), dim3(kThreads), 0, st, a, T);
     return hipGetLastError();
 }
 
 template <int DT, int TM, int BKW, bool BL>
 hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW, BL>), dim3((unsigned)round_up_xcd(a.ntiles)),
-                       dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW, BL>),
+                       dim3((unsigned)round_up_xcd(a.ntiles * a.nchunks)), dim3(kThreads), 0, st,
+                       a);
     return hipGetLastError();
 }
 

@@ -74,7 +74,19 @@ static int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_
 static int choose_acc(int64_t n_f, const ps_opts* o) {
     const int a = o ? o->acc : PS_ACC_AUTO;
     if (a == PS_ACC_PLAIN || a == PS_ACC_BLOCKED) return a;
-    return n_f > 2048 ? PS_ACC_BLOCKED : PS_ACC_PLAIN;
+    return n_f > kChunkFields ? PS_ACC_BLOCKED : PS_ACC_PLAIN;
+}
+
+// Number of field chunks of the blocked (split) accumulation; 1 = no split.
+// kChunkFields is a multiple of every configuration's field-tile depth.
+static int32_t split_chunks(int32_t dt, int64_t n_f, int acc) {
+    if (dt == PS_U8 || acc != PS_ACC_BLOCKED) return 1;
+    const int64_t n = ceil_div(n_f, kChunkFields);
+    return n > 1 ? (int32_t)n : 1;
+}
+
+static int64_t chunk_tiles(int32_t dt, int cfg) {
+    return kChunkFields / ((int64_t)kValuCfgs[cfg].bkw * (4 / elem_size(dt)));
 }
 
 static int choose_path(int32_t dt, const ps_opts* o) {
@@ -155,15 +167,20 @@ static hipError_t launch_mgb(int32_t dt, const MgBatchLaunch& a, hipStream_t st)
 
 // Sizes of the 2-way workspace regions.  Returns total bytes.
 static size_t ws2_layout(int32_t dt, int64_t n_f, int64_t n_v, int32_t s_given, int path,
-                         int levels, void* ws, double** s_ws, int8_t** planes) {
+                         int levels, int32_t nchunks, void* ws, double** s_ws,
+                         int8_t** planes, float** partial) {
     Carver c(ws);
     double* s = nullptr;
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
     int8_t* pl = nullptr;
+    float* part = nullptr;
     if (path == PS_PATH_MFMA && dt == PS_U8)
         pl = (int8_t*)c.take(mfma_workspace_bytes(n_f, n_v, levels));
+    else if (nchunks > 1)
+        part = (float*)c.take((size_t)nchunks * (size_t)(n_v * (n_v - 1) / 2) * sizeof(float));
     if (s_ws) *s_ws = s;
     if (planes) *planes = pl;
+    if (partial) *partial = part;
     return c.used;
 }
 
@@ -204,7 +221,8 @@ size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
                           const ps_opts* opts) {
     if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
     const int path = choose_path(dtype, opts);
-    return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0, nullptr,
+    return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0,
+                      split_chunks(dtype, n_f, choose_acc(n_f, opts)), nullptr, nullptr,
                       nullptr, nullptr);
 }
 
@@ -226,8 +244,11 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         return fail(PS_ERR_ARG, "the MFMA path needs opts.levels >= max(V) >= 1");
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
-    const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, workspace,
-                                   &s_ws, &planes);
+    float* partial = nullptr;
+    const int acc = choose_acc(n_f, opts);
+    const int32_t nchunks = split_chunks(dtype, n_f, acc);
+    const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, nchunks,
+                                   workspace, &s_ws, &planes, &partial);
     if (ws_bytes < need || (need && !workspace))
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
     if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
@@ -244,31 +265,47 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");
         return e == hipSuccess ? PS_OK : hip_fail(e, "mfma launch");
     }
-    Mg2Launch a{V, n_f, n_v, ld, s, c2, n2, choose_acc(n_f, opts),
-                choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts)};
+    const int cfg = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
+    Mg2Launch a{V, n_f, n_v, ld, s, c2, n2, PS_ACC_PLAIN, cfg,
+                nchunks, chunk_tiles(dtype, cfg), partial};
     e = launch_mg2(dtype, a, stream);
+    if (e == hipSuccess && nchunks > 1) e = launch_finish2(dtype, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "2-way launch");
 }
 
-static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, void* ws,
-                         double** s_ws, void** n2_ws, int64_t** prefix) {
+// The field-split partials of the pair prepass and of the slices run one
+// after the other on the stream and share one region.
+static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t nchunks,
+                         int64_t stage, void* ws, double** s_ws, void** n2_ws,
+                         int64_t** prefix, float** partial) {
     Carver c(ws);
     double* s = nullptr;
     void* n2 = nullptr;
+    float* part = nullptr;
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
     if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * 4);
     int64_t* pre = (int64_t*)c.take((size_t)(n_v + 1) * sizeof(int64_t));
+    if (nchunks > 1) {
+        const int64_t pairs = n2_given ? 0 : n_v * (n_v - 1) / 2;
+        part = (float*)c.take((size_t)nchunks * (size_t)(pairs > stage ? pairs : stage) *
+                              sizeof(float));
+    }
     if (s_ws) *s_ws = s;
     if (n2_ws) *n2_ws = n2;
     if (prefix) *prefix = pre;
+    if (partial) *partial = part;
     return c.used;
 }
 
 size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_given,
-                          int32_t n2_given, const ps_opts* opts) {
-    (void)opts;
+                          int32_t n2_given, int64_t j_begin, int64_t j_end,
+                          const ps_opts* opts) {
     if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
-    return ws3_layout(n_v, s_given, n2_given, nullptr, nullptr, nullptr, nullptr);
+    if (j_begin < 1) j_begin = 1;
+    if (j_end > n_v - 1) j_end = n_v - 1;
+    const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
+    return ws3_layout(n_v, s_given, n2_given, split_chunks(dtype, n_f, choose_acc(n_f, opts)),
+                      stage, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end) {
@@ -296,8 +333,12 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     double* s_ws = nullptr;
     void* n2_ws = nullptr;
     int64_t* prefix = nullptr;
-    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, workspace, &s_ws, &n2_ws,
-                                   &prefix);
+    float* partial = nullptr;
+    const int acc = choose_acc(n_f, opts);
+    const int32_t nchunks = split_chunks(dtype, n_f, acc);
+    const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
+    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, nchunks, stage, workspace,
+                                   &s_ws, &n2_ws, &prefix, &partial);
     if (ws_bytes < need || !workspace)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
     if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
@@ -307,18 +348,20 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         if (e != hipSuccess) return hip_fail(e, "sums launch");
         s = s_ws;
     }
-    const int acc = choose_acc(n_f, opts);
     if (!n2) {  // the pair numerators of Eq. 1 (the 2-way mGEMM prepass)
-        Mg2Launch a{V, n_f, n_v, ld, s, nullptr, n2_ws, acc,
-                    choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts)};
+        const int cfg2 = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
+        Mg2Launch a{V, n_f, n_v, ld, s, nullptr, n2_ws, PS_ACC_PLAIN, cfg2,
+                    nchunks, chunk_tiles(dtype, cfg2), partial};
         e = launch_mg2(dtype, a, stream);
+        if (e == hipSuccess && nchunks > 1) e = launch_finish2(dtype, a, stream);
         if (e != hipSuccess) return hip_fail(e, "3-way numerator prepass launch");
         n2 = n2_ws;
     }
     const int cfg = choose_cfg(dtype, 3, PS_PATH_VALU, n_f, n_v, opts);
     const int bm = kValuCfgs[cfg].bm();
     Mg3Launch a{V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, prefix,
-                slab_tiles(n_v, j_begin, j_end, bm, bm), acc, cfg};
+                slab_tiles(n_v, j_begin, j_end, bm, bm), PS_ACC_PLAIN, cfg,
+                nchunks, chunk_tiles(dtype, cfg), partial};
     e = launch_mg3_prefix(a, stream);
     if (e == hipSuccess) e = launch_mg3(dtype, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");

@@ -44,6 +44,9 @@ struct TileCfg {
     int bn() const { return 16 * tn; }
 };
 
+// Fields per chunk of the field-chunk split (PS_ACC_BLOCKED).
+constexpr int64_t kChunkFields = 4096;
+
 // Compiled configurations, indexed by ps_opts.tile - 1.
 constexpr int kNumValuCfgs = 3;
 extern const TileCfg kValuCfgs[kNumValuCfgs];
@@ -55,8 +58,14 @@ struct Mg2Launch {
     const double* s;
     float* c2;                   // may be null
     void* n2;                    // may be null
-    int acc;                     // PS_ACC_PLAIN / PS_ACC_BLOCKED
+    int acc;                     // PS_ACC_PLAIN / PS_ACC_BLOCKED (in-register)
     int cfg;                     // index into kValuCfgs
+    // field-chunk split: nchunks > 1 sums chunks of chunk_tiles field tiles
+    // in separate workgroups into partial[chunk * npairs + pair] (FP32), then
+    // a finish kernel adds the chunks in FP64
+    int32_t nchunks;
+    int64_t chunk_tiles;
+    float* partial;
 };
 
 // Arguments of one 3-way launch over the tiles of middle indices
@@ -72,6 +81,9 @@ struct Mg3Launch {
     int64_t ntiles;
     int acc;
     int cfg;
+    int32_t nchunks;             // field-chunk split as for Mg2Launch; partial
+    int64_t chunk_tiles;         // holds nchunks * stage-size FP32 values
+    float* partial;
 };
 
 // Device problem record of a batched launch.
@@ -117,6 +129,7 @@ hipError_t launch_mg3_f32(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_f16(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st);
+hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st);
 hipError_t launch_mgb_f32(const MgBatchLaunch& a, hipStream_t st);
 hipError_t launch_mgb_f16(const MgBatchLaunch& a, hipStream_t st);
 hipError_t launch_mgb_u8(const MgBatchLaunch& a, hipStream_t st);

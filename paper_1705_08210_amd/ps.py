@@ -59,7 +59,7 @@ _sig("ps_vector_sums", ctypes.c_int, [P, I32, I64, I64, I64, P, P, P])
 _sig("ps2_workspace_size", SZ, [I32, I64, I64, I32, ctypes.POINTER(Opts)])
 _sig("ps2_compute", ctypes.c_int,
      [P, I32, I64, I64, I64, P, P, P, P, SZ, ctypes.POINTER(Opts), P])
-_sig("ps3_workspace_size", SZ, [I32, I64, I64, I32, I32, ctypes.POINTER(Opts)])
+_sig("ps3_workspace_size", SZ, [I32, I64, I64, I32, I32, I64, I64, ctypes.POINTER(Opts)])
 _sig("ps3_compute", ctypes.c_int,
      [P, I32, I64, I64, I64, P, P, I64, I64, P, P, SZ, ctypes.POINTER(Opts), P])
 _sig("ps3_stage_size", I64, [I64, I64, I64])
@@ -182,7 +182,7 @@ def ps3(V: torch.Tensor, s: torch.Tensor | None = None, n2: torch.Tensor | None 
         c3 = torch.empty(m, dtype=torch.float32, device=V.device)
     o = _opts(acc, "auto", 0, tile)
     ws_n = lib.ps3_workspace_size(dt, n_f, n_v, int(s is not None), int(n2 is not None),
-                                  ctypes.byref(o))
+                                  j_begin, j_end, ctypes.byref(o))
     ws = _workspace(ws_n, V.device)
     _check(lib.ps3_compute(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(n2), j_begin, j_end,
                            c3.data_ptr() if m > 0 else None, ws.data_ptr(), ws.numel(),
@@ -282,3 +282,11 @@ def tune_register(dtype, way, path, nf_range, nv_range, idx) -> None:
 
 def tune_clear() -> None:
     lib.ps_tune_clear()
+
+
+# The C ABI's names (include/ps.h) for the same calls.
+ps_vector_sums = vector_sums
+ps2_compute = ps2
+ps3_compute = ps3
+ps2_compute_batched = ps2_batched
+ps3_stage_size = stage_size

@@ -110,8 +110,14 @@ def test_workspace_sizes():
     pairs = n * (n - 1) // 2
     expect = (math.ceil(n * 8 / 256) * 256 + math.ceil(pairs * 4 / 256) * 256
               + math.ceil((n + 1) * 8 / 256) * 256)
-    assert g(0, 10, n, 0, 0, None) == expect
-    assert g(0, 10, n, 1, 1, None) == math.ceil((n + 1) * 8 / 256) * 256
+    assert g(0, 10, n, 0, 0, 1, n - 1, None) == expect
+    assert g(0, 10, n, 1, 1, 1, n - 1, None) == math.ceil((n + 1) * 8 / 256) * 256
+    # blocked accumulation beyond 4096 fields: FP32 partials of each field chunk
+    stage = math.comb(n, 3)
+    assert g(0, 9000, n, 1, 1, 1, n - 1, None) == (math.ceil((n + 1) * 8 / 256) * 256
+                                                  + math.ceil(3 * stage * 4 / 256) * 256)
+    assert f(0, 9000, 1000, 1, None) == math.ceil(3 * (1000 * 999 // 2) * 4 / 256) * 256
+    assert f(2, 9000, 1000, 1, None) == 0          # integer data: no split
 
 
 @pytest.mark.parametrize("n_v", [3, 4, 7, 20])

@@ -249,3 +249,31 @@ def test_mfma_auto_path_and_unaligned_rows():
     Vd = to_dev(big)[:, :511]
     c2, _ = ps.ps2(Vd, levels=3)
     check_exact_f32(host(c2), oracle.c2_all(V), "c2")
+
+
+# ------------------------------------------ blocked (field-chunk) split ----
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_blocked_split_over_field_chunks(tile):
+    """n_f = 9001 > 4096: three field chunks (the last one ragged) summed in
+    separate workgroups and combined in FP64; deterministic."""
+    V = workloads.uniform(150, 9001, seed=61)          # dense: the accuracy case
+    announce(f"2-way blocked split tile={tile}")
+    c2, n2 = run2(V, acc="blocked", tile=tile)
+    ref, rn2 = oracle.c2_all(V, with_n2=True)
+    ea, er = check_rel(c2, ref, FP32_TOL, "c2")
+    check_rel(n2, rn2, FP32_TOL, "n2")
+    again, _ = run2(V, acc="blocked", tile=tile)
+    assert np.array_equal(c2.view(np.uint32), again.view(np.uint32))
+    plain, _ = run2(V, acc="plain", tile=tile)
+    _, er_plain = check_rel(plain, ref, 1e-4, "c2 plain")
+    print(f"dense 9001 fields: blocked max rel {er:.2e}, plain max rel {er_plain:.2e}")
+
+
+def test_blocked_split_fp16():
+    V32 = workloads.sparse_uniform(100, 8500, seed=62)
+    V16 = workloads.to_f16(V32)
+    announce("2-way blocked split fp16")
+    c2, _ = run2(V16, acc="blocked")
+    check_rel(c2, oracle.c2_all(V16), FP32_TOL, "c2 vs fp16 values")
+    check_rel(c2, oracle.c2_all(V32), FP16_TOL, "c2 vs fp32 source")

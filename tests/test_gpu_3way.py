@@ -128,3 +128,17 @@ def test_nested_support_family_exact(storage):
     d = a[i] * L[i] + a[j] * L[j] + a[k] * L[k]
     ref = np.where(d > 0, (3 * n3) / (2 * np.where(d > 0, d, 1)), 0.0)
     check_exact_f32(c3, ref, "c3")
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_blocked_split_over_field_chunks(tile):
+    """n_f = 8200: two field chunks for both the pair prepass and the slices."""
+    from paper_1705_08210_amd import ps
+    V = workloads.uniform(70, 8200, seed=39)
+    announce(f"3-way blocked split tile={tile}")
+    Vd = to_dev(V)
+    c3 = host(ps.ps3(Vd, acc="blocked", tile=tile))
+    check_rel(c3, oracle.c3_all(V), FP32_TOL, "c3")
+    part = np.concatenate([host(ps.ps3(Vd, j_begin=a, j_end=b, acc="blocked", tile=tile))
+                           for a, b in [(1, 30), (30, 69)]])
+    assert np.array_equal(part.view(np.uint32), c3.view(np.uint32))
