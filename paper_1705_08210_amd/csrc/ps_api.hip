@@ -51,11 +51,11 @@ static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
 
 static int default_cfg(int32_t way, int64_t n_v) {
-    if (way == 2) {
-        // 128x128 tiles once they fill every workgroup slot a few times over
-        return tri_tiles(n_v, 128) >= 1024 ? 0 : 1;
-    }
-    return 0;
+    // 128x128 output tiles with 16-word field tiles (measured fastest on the
+    // large problems: 126 registers, 4 waves per SIMD) once the tiles fill
+    // the chip a few times over; 64x64 tiles below that
+    if (way == 2) return tri_tiles(n_v, 128) >= 1024 ? 2 : 1;
+    return n_v >= 256 ? 2 : 1;
 }
 
 static int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
@@ -421,7 +421,7 @@ static int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* 
     for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
         if (it->dt == dt && it->way == 0 && nf >= it->nf_lo && nf < it->nf_hi)
             return it->idx;
-    return 0;
+    return 2;
 }
 
 static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, const ps_opts* o) {
