@@ -87,9 +87,13 @@ typedef enum {
 typedef enum {
     PS_PATH_AUTO = 0,    /* U8 with 1 <= levels <= 15: MFMA; otherwise VALU */
     PS_PATH_VALU = 1,    /* register-blocked min/add on the vector ALUs */
-    PS_PATH_MFMA = 2     /* U8 only: min(a,b) = sum_{t=1..levels} [a>=t][b>=t],
+    PS_PATH_MFMA = 2,    /* U8 only: min(a,b) = sum_{t=1..levels} [a>=t][b>=t],
                             an exact int8 matrix-core contraction with int32
                             accumulation; needs levels >= max(V) */
+    PS_PATH_MFMA_FP4 = 3 /* U8 only: the same 0/1 planes as FP4 (e2m1) operands
+                            of the scaled matrix-core instruction, FP32
+                            accumulation (exact: sums are integers < 2^24,
+                            needs levels * n_f < 2^24); needs levels >= max(V) */
 } ps_path;
 
 typedef struct {

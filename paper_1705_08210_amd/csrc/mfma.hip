@@ -8,27 +8,44 @@
 // paper's min-product (Section 3.1) recast so that the matrix cores can run
 // it.
 //
-// Two kernels:
-//   ps_thermo_expand_kernel  V (uint8, n_v x ld) -> planes P (int8,
-//                            n_v x L*kpad), kpad = n_f rounded up to 64;
-//                            HBM-bound, one pass.
-//   ps_mfma2_kernel          upper-triangle tiles of P P^T with
-//                            v_mfma_i32_32x32x32_i8, FP64 epilogue.
+// Two operand formats, one kernel structure:
+//   int8: one plane value per byte, v_mfma_i32_32x32x32_i8, int32 sums;
+//   fp4 : two plane values per byte (e2m1: 0 -> 0x0, 1 -> 0x2),
+//         v_mfma_scale_f32_32x32x64_f8f6f4 with unit scales, FP32 sums
+//         (exact: every partial sum is an integer below 2^24).
+// Kernels:
+//   ps_thermo_expand_kernel  V (uint8, n_v x ld) -> planes P, row length
+//                            L * kpad fields, kpad = n_f rounded up to one
+//                            64-byte field tile; HBM-bound, one pass.
+//   ps_mfma2_kernel          upper-triangle tiles of P P^T, FP64 epilogue.
+#include <type_traits>
+
 #include "ps_internal.h"
 
 namespace ps {
 
 typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v8i_t __attribute__((ext_vector_type(8)));
 typedef int v16i_t __attribute__((ext_vector_type(16)));
+typedef float v16f_t __attribute__((ext_vector_type(16)));
+
+enum { kFmtI8 = 0, kFmtF4 = 1 };
+__host__ __device__ constexpr int fields_per_byte(int fmt) { return fmt == kFmtF4 ? 2 : 1; }
 
 constexpr int kMB = 256;      // output tile rows and columns
 constexpr int kMK = 64;       // field-tile depth in plane bytes
 constexpr int kPitch = 80;    // LDS bytes per tile row (64 + 16: conflict-free b128 reads)
 constexpr int kGroup = 8;     // tile columns per L2-sharing group
 
-size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels) {
-    const int64_t kpad = (n_f + kMK - 1) / kMK * kMK;
-    return (size_t)n_v * (size_t)levels * (size_t)(kpad > 0 ? kpad : kMK);
+// Fields of one plane row, padded to whole 64-byte field tiles (>= 1 tile).
+static int64_t plane_fields(int64_t n_f, int fmt) {
+    const int64_t q = (int64_t)kMK * fields_per_byte(fmt);
+    const int64_t kpad = (n_f + q - 1) / q * q;
+    return kpad > 0 ? kpad : q;
+}
+
+size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt) {
+    return (size_t)n_v * (size_t)levels * (size_t)(plane_fields(n_f, fmt) / fields_per_byte(fmt));
 }
 
 // ---------------------------------------------------------------------------
@@ -40,34 +57,56 @@ __device__ __forceinline__ uint32_t ge_bytes(uint32_t x, uint32_t t) {
     return (((x | 0x80808080u) - t * 0x01010101u) >> 7) & 0x01010101u;
 }
 
+// fp4 packing of four 0/1 bytes (one word of ge_bytes) into four nibbles
+__device__ __forceinline__ uint32_t nibbles_e2m1(uint32_t m) {
+    return ((m & 0x1u) << 1) | ((m & 0x100u) >> 3) | ((m & 0x10000u) >> 7) |
+           ((m & 0x1000000u) >> 11);
+}
+
+// One thread per 32 fields of one vector; kpad is a multiple of 64.
+template <int FMT>
 __global__ __launch_bounds__(256) void ps_thermo_expand_kernel(const uint8_t* V, int64_t n_f,
                                                                int64_t n_v, int64_t ld,
                                                                int levels, int64_t kpad,
                                                                int8_t* P) {
-    const int64_t nch = kpad / 16;
+    constexpr int FPB = fields_per_byte(FMT);
+    const int64_t nch = kpad / 32;
     const int64_t total = n_v * nch;
+    const int64_t plane_bytes = kpad / FPB;
     const bool vec = ((uintptr_t)V % 16 == 0) && (ld % 16 == 0);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t row = t / nch, ch = t % nch;
-        const int64_t q0 = ch * 16;
+        const int64_t q0 = ch * 32;
         const uint8_t* src = V + row * ld + q0;
-        union { uint4 v; uint8_t b[16]; } u;
-        if (vec && q0 + 16 <= n_f) {
-            u.v = *(const uint4*)src;
+        union { uint4 v[2]; uint32_t w[8]; uint8_t b[32]; } u;
+        if (vec && q0 + 32 <= n_f) {
+            u.v[0] = *(const uint4*)src;
+            u.v[1] = *(const uint4*)(src + 16);
         } else {
-            u.v = make_uint4(0, 0, 0, 0);
-            for (int e = 0; e < 16; ++e)
+            u.v[0] = u.v[1] = make_uint4(0, 0, 0, 0);
+            for (int e = 0; e < 32; ++e)
                 if (q0 + e < n_f) u.b[e] = src[e];
         }
-        int8_t* dst = P + row * (int64_t)levels * kpad + q0;
+        int8_t* dst = P + row * (int64_t)levels * plane_bytes + q0 / FPB;
         for (int lev = 1; lev <= levels; ++lev) {
-            uint4 o;
-            o.x = ge_bytes(u.v.x, lev);
-            o.y = ge_bytes(u.v.y, lev);
-            o.z = ge_bytes(u.v.z, lev);
-            o.w = ge_bytes(u.v.w, lev);
-            *(uint4*)(dst + (int64_t)(lev - 1) * kpad) = o;
+            int8_t* d = dst + (int64_t)(lev - 1) * plane_bytes;
+            if constexpr (FMT == kFmtI8) {
+                uint4 o0, o1;
+                o0.x = ge_bytes(u.w[0], lev); o0.y = ge_bytes(u.w[1], lev);
+                o0.z = ge_bytes(u.w[2], lev); o0.w = ge_bytes(u.w[3], lev);
+                o1.x = ge_bytes(u.w[4], lev); o1.y = ge_bytes(u.w[5], lev);
+                o1.z = ge_bytes(u.w[6], lev); o1.w = ge_bytes(u.w[7], lev);
+                *(uint4*)d = o0;
+                *(uint4*)(d + 16) = o1;
+            } else {
+                uint4 o;
+                o.x = nibbles_e2m1(ge_bytes(u.w[0], lev)) | (nibbles_e2m1(ge_bytes(u.w[1], lev)) << 16);
+                o.y = nibbles_e2m1(ge_bytes(u.w[2], lev)) | (nibbles_e2m1(ge_bytes(u.w[3], lev)) << 16);
+                o.z = nibbles_e2m1(ge_bytes(u.w[4], lev)) | (nibbles_e2m1(ge_bytes(u.w[5], lev)) << 16);
+                o.w = nibbles_e2m1(ge_bytes(u.w[6], lev)) | (nibbles_e2m1(ge_bytes(u.w[7], lev)) << 16);
+                *(uint4*)d = o;
+            }
         }
     }
 }
@@ -116,7 +155,9 @@ struct MfmaArgs {
 // [(w/2)*64, +64) of the 256 x 256 tile: 4 x 2 blocks of 32 x 32.
 constexpr int kMThreads = 512;
 
+template <int FMT>
 __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
+    using AccT = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
     __shared__ __attribute__((aligned(16))) int8_t As[kMB * kPitch];   // j rows
     __shared__ __attribute__((aligned(16))) int8_t Bs[kMB * kPitch];   // i rows
     const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
@@ -130,11 +171,11 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
     // some i < j with both < n_v among rows j0+wr.. and columns i0+wc..?
     const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
 
-    v16i_t acc[4][2];
+    AccT acc[4][2];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) acc[m][n] = (v16i_t){};
+        for (int n = 0; n < 2; ++n) acc[m][n] = (AccT){};
 
     // staging: 256 rows x 64 bytes per operand = 1024 16-byte chunks; 2 + 2
     // per thread, four threads per row
@@ -182,9 +223,17 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n], acc[m][n],
-                                                                      0, 0, 0);
+                for (int n = 0; n < 2; ++n) {
+                    if constexpr (FMT == kFmtI8) {
+                        acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n],
+                                                                          acc[m][n], 0, 0, 0);
+                    } else {  // 64 e2m1 values per row per k-step, unit (2^0) scales
+                        const v8i_t xa = {fa[m].x, fa[m].y, fa[m].z, fa[m].w, 0, 0, 0, 0};
+                        const v8i_t xb = {fb[n].x, fb[n].y, fb[n].z, fb[n].w, 0, 0, 0, 0};
+                        acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            xa, xb, acc[m][n], 4, 4, 0, 127, 0, 127);
+                    }
+                }
         }
     }
     if (!active) return;
@@ -204,7 +253,7 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
             for (int n = 0; n < 2; ++n) {
                 const int64_t i = ib + n * 32;
                 if (i >= j) continue;
-                const int32_t num = acc[m][n][r];
+                const int32_t num = (int32_t)acc[m][n][r];   // exact in either format
                 if (a.n2) a.n2[base + i] = num;
                 if (a.c2) {
                     const double d = a.s[i] + sj;
@@ -215,24 +264,28 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
     }
 }
 
-hipError_t launch_mfma2(const MfmaLaunch& m, hipStream_t st) {
-    if (m.n_v < 2) return hipSuccess;
-    const int64_t kpad = (m.n_f + kMK - 1) / kMK * kMK;
-    const int64_t kp = (int64_t)m.levels * (kpad > 0 ? kpad : kMK);
-    const int64_t total = m.n_v * ((kpad > 0 ? kpad : kMK) / 16);
+template <int FMT>
+static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
+    const int64_t kpad = plane_fields(m.n_f, FMT);
+    const int64_t kp = (int64_t)m.levels * kpad / fields_per_byte(FMT);
+    const int64_t total = m.n_v * (kpad / 32);
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(ps_thermo_expand_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
-                       (const uint8_t*)m.V, m.n_f, m.n_v, m.ld, m.levels,
-                       kpad > 0 ? kpad : (int64_t)kMK, m.planes);
+    hipLaunchKernelGGL(ps_thermo_expand_kernel<FMT>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const uint8_t*)m.V, m.n_f, m.n_v, m.ld, m.levels, kpad, m.planes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nb = (m.n_v + kMB - 1) / kMB;
     const int64_t T = nb * (nb + 1) / 2;
     MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T};
     const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(ps_mfma2_kernel, dim3((unsigned)grid), dim3(kMThreads), 0, st, a);
+    hipLaunchKernelGGL(ps_mfma2_kernel<FMT>, dim3((unsigned)grid), dim3(kMThreads), 0, st, a);
     return hipGetLastError();
+}
+
+hipError_t launch_mfma2(const MfmaLaunch& m, hipStream_t st) {
+    if (m.n_v < 2) return hipSuccess;
+    return m.fmt == kFmtF4 ? go_mfma2<kFmtF4>(m, st) : go_mfma2<kFmtI8>(m, st);
 }
 
 }  // namespace ps

@@ -89,9 +89,11 @@ static int64_t chunk_tiles(int32_t dt, int cfg) {
     return kChunkFields / ((int64_t)kValuCfgs[cfg].bkw * (4 / elem_size(dt)));
 }
 
+static bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4; }
+
 static int choose_path(int32_t dt, const ps_opts* o) {
     const int p = o ? o->path : PS_PATH_AUTO;
-    if (p == PS_PATH_VALU || p == PS_PATH_MFMA) return p;
+    if (p == PS_PATH_VALU || p == PS_PATH_MFMA || p == PS_PATH_MFMA_FP4) return p;
     if (dt == PS_U8 && o && o->levels >= 1 && o->levels <= 15) return PS_PATH_MFMA;
     return PS_PATH_VALU;
 }
@@ -103,7 +105,7 @@ static ps_status check_opts(const ps_opts* o) {
     if (!o) return PS_OK;
     if (o->acc < PS_ACC_AUTO || o->acc > PS_ACC_BLOCKED)
         return fail(PS_ERR_ARG, "opts.acc = %d is not a ps_acc value", o->acc);
-    if (o->path < PS_PATH_AUTO || o->path > PS_PATH_MFMA)
+    if (o->path < PS_PATH_AUTO || o->path > PS_PATH_MFMA_FP4)
         return fail(PS_ERR_ARG, "opts.path = %d is not a ps_path value", o->path);
     if (o->tile < 0 || o->tile > kNumValuCfgs)
         return fail(PS_ERR_ARG, "opts.tile = %d out of range [0, %d]", o->tile, kNumValuCfgs);
@@ -174,8 +176,9 @@ static size_t ws2_layout(int32_t dt, int64_t n_f, int64_t n_v, int32_t s_given, 
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
     int8_t* pl = nullptr;
     float* part = nullptr;
-    if (path == PS_PATH_MFMA && dt == PS_U8)
-        pl = (int8_t*)c.take(mfma_workspace_bytes(n_f, n_v, levels));
+    if (is_mfma(path) && dt == PS_U8)
+        pl = (int8_t*)c.take(
+            mfma_workspace_bytes(n_f, n_v, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0));
     else if (nchunks > 1)
         part = (float*)c.take((size_t)nchunks * (size_t)(n_v * (n_v - 1) / 2) * sizeof(float));
     if (s_ws) *s_ws = s;
@@ -237,11 +240,18 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (!aligned(c2, 4) || !aligned(n2, 4) || !aligned(s, 8))
         return fail(PS_ERR_ARG, "misaligned output or sums pointer");
     const int path = choose_path(dtype, opts);
-    if (path == PS_PATH_MFMA && dtype != PS_U8)
+    if (is_mfma(path) && dtype != PS_U8)
         return fail(PS_ERR_UNSUPPORTED, "the MFMA path needs PS_U8 data");
     const int levels = opts ? opts->levels : 0;
-    if (path == PS_PATH_MFMA && levels < 1)
+    if (is_mfma(path) && levels < 1)
         return fail(PS_ERR_ARG, "the MFMA path needs opts.levels >= max(V) >= 1");
+    // exactness of the accumulators: every pair sum is at most levels * n_f
+    if (path == PS_PATH_MFMA_FP4 && (int64_t)levels * n_f >= ((int64_t)1 << 24))
+        return fail(PS_ERR_ARG, "fp4 path: levels * n_f = %lld exceeds the exact FP32 range",
+                    (long long)levels * n_f);
+    if (path == PS_PATH_MFMA && (int64_t)levels * n_f >= ((int64_t)1 << 31))
+        return fail(PS_ERR_ARG, "int8 path: levels * n_f = %lld exceeds int32",
+                    (long long)levels * n_f);
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
     float* partial = nullptr;
@@ -258,8 +268,9 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         if (e != hipSuccess) return hip_fail(e, "sums launch");
         s = s_ws;
     }
-    if (path == PS_PATH_MFMA) {
-        MfmaLaunch m{V, n_f, n_v, ld, levels, s, c2, n2, planes, 0};
+    if (is_mfma(path)) {
+        MfmaLaunch m{V, n_f, n_v, ld, levels, s, c2, n2, planes,
+                     path == PS_PATH_MFMA_FP4 ? 1 : 0};
         e = launch_mfma2(m, stream);
         if (e == hipErrorNotSupported)
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");
@@ -320,7 +331,7 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     ps_status st = check_matrix(V, dtype, n_f, n_v, ld);
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
-    if (opts && opts->path == PS_PATH_MFMA)
+    if (opts && is_mfma(opts->path))
         return fail(PS_ERR_UNSUPPORTED, "3-way runs on the VALU path only");
     if (n_v < 3) return PS_OK;
     if (j_begin < 1 || j_end > n_v - 1 || j_begin > j_end)
@@ -429,7 +440,7 @@ static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, con
     if (n > 0 && !probs) return fail(PS_ERR_ARG, "probs is NULL");
     ps_status st = check_opts(o);
     if (st != PS_OK) return st;
-    if (o && o->path == PS_PATH_MFMA)
+    if (o && is_mfma(o->path))
         return fail(PS_ERR_UNSUPPORTED, "batched runs on the VALU path only");
     for (int32_t i = 0; i < n; ++i) {
         const ps_problem& p = probs[i];
@@ -617,7 +628,7 @@ void ps_plan_destroy(ps_plan* plan) {
 
 int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx, int32_t* bm,
                        int32_t* bn, int32_t* bk) {
-    if (elem_size(dtype) == 0 || (way != 2 && way != 3) || path == PS_PATH_MFMA) return 0;
+    if (elem_size(dtype) == 0 || (way != 2 && way != 3) || is_mfma(path)) return 0;
     if (idx >= 0 && idx < kNumValuCfgs) {
         const int fpw = 4 / elem_size(dtype);  // fields per 32-bit word
         if (bm) *bm = kValuCfgs[idx].bm();

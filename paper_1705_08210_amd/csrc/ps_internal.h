@@ -145,10 +145,10 @@ struct MfmaLaunch {
     const double* s;
     float* c2;
     void* n2;
-    int8_t* planes;              // workspace: levels * n_v * kpad bytes
-    int64_t kpad;                // padded field count of one plane row
+    int8_t* planes;              // workspace: mfma_workspace_bytes()
+    int fmt;                     // 0: int8 planes, 1: fp4 (e2m1) planes
 };
-size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels);
+size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt);
 hipError_t launch_mfma2(const MfmaLaunch& a, hipStream_t st);
 
 }  // namespace ps

@@ -32,7 +32,7 @@ SZ = ctypes.c_size_t
 
 PS_F32, PS_F16, PS_U8 = 0, 1, 2
 ACC = {"auto": 0, "plain": 1, "blocked": 2}
-PATH = {"auto": 0, "valu": 1, "mfma": 2}
+PATH = {"auto": 0, "valu": 1, "mfma": 2, "mfma_fp4": 3}
 DTYPES = {torch.float32: PS_F32, torch.float16: PS_F16, torch.uint8: PS_U8}
 
 

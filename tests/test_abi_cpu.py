@@ -57,6 +57,9 @@ def call2(V=FAKE, dt=0, n_f=10, n_v=5, ld=10, s=None, c2=FAKE, n2=None, ws=FAKE,
     (dict(o=opts(levels=200)), ARG),
     (dict(o=opts(path=2)), UNSUP),                     # MFMA needs uint8 data
     (dict(dt=2, o=opts(path=2, levels=0)), ARG),       # MFMA needs levels
+    (dict(o=opts(path=3, levels=3)), UNSUP),           # fp4 MFMA needs uint8 data
+    (dict(dt=2, n_f=6_000_000, ld=6_000_000, o=opts(path=3, levels=3)), ARG),  # > 2^24
+    (dict(o=opts(path=4)), ARG),
 ])
 def test_ps2_argument_errors(kw, status):
     assert call2(**kw) == status

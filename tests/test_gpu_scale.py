@@ -41,7 +41,7 @@ def test_gwas_20000x16384_sampled():
     assert c2.shape[0] == V.shape[0] * (V.shape[0] - 1) // 2
 
 
-@pytest.mark.parametrize("path", ["valu", "mfma"])
+@pytest.mark.parametrize("path", ["valu", "mfma", "mfma_fp4"])
 def test_levels_8192x32768_sampled_exact(path):
     from paper_1705_08210_amd import ps
     V = workloads.levels_8192x32768()
