@@ -151,12 +151,17 @@ struct MfmaArgs {
     int64_t nb, ntiles;
 };
 
-// 512 threads = 8 waves; wave w owns j rows [(w%2)*128, +128) and i columns
-// [(w/2)*64, +64) of the 256 x 256 tile: 4 x 2 blocks of 32 x 32.
-constexpr int kMThreads = 512;
+// Wave w owns j rows [(w%2)*128, +128) and i columns [(w/2)*32*WN, +32*WN)
+// of the 256 x 256 tile: 4 x WN blocks of 32 x 32.  WN = 2: 8 waves, 128
+// accumulator registers, 2 waves per SIMD; WN = 4: 4 waves, 256 accumulator
+// registers (AGPRs), one wave per SIMD, a third less LDS traffic per MAC.
+template <int WN>
+__host__ __device__ constexpr int mfma_threads() { return 64 * 2 * (kMB / (32 * WN)); }
 
-template <int FMT>
-__global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
+template <int FMT, int WN>
+__global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArgs a) {
+    constexpr int kMThreads = mfma_threads<WN>();
+    constexpr int kStage = kMB * 4 / kMThreads;   // 16-byte chunks per thread per operand
     using AccT = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
     __shared__ __attribute__((aligned(16))) int8_t As[kMB * kPitch];   // j rows
     __shared__ __attribute__((aligned(16))) int8_t Bs[kMB * kPitch];   // i rows
@@ -167,22 +172,22 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
     const int64_t i0 = bi * kMB, j0 = bj * kMB;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int wr = (wave % 2) * 128;        // j offset of the wave's block
-    const int wc = (wave / 2) * 64;         // i offset
+    const int wc = (wave / 2) * 32 * WN;    // i offset
     // some i < j with both < n_v among rows j0+wr.. and columns i0+wc..?
     const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
 
-    AccT acc[4][2];
+    AccT acc[4][WN];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) acc[m][n] = (AccT){};
+        for (int n = 0; n < WN; ++n) acc[m][n] = (AccT){};
 
-    // staging: 256 rows x 64 bytes per operand = 1024 16-byte chunks; 2 + 2
-    // per thread, four threads per row
-    uint4 ra[2], rb[2];
+    // staging: 256 rows x 64 bytes per operand = 1024 16-byte chunks, four
+    // threads per row
+    uint4 ra[kStage], rb[kStage];
     auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < kStage; ++c) {
             const int idx = threadIdx.x + c * kMThreads;
             const int row = idx / 4, ch = idx % 4;
             const int64_t gj = j0 + row, gi = i0 + row;
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
     };
     auto store = [&]() {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < kStage; ++c) {
             const int idx = threadIdx.x + c * kMThreads;
             const int row = idx / 4, ch = idx % 4;
             *(uint4*)(As + row * kPitch + ch * 16) = ra[c];
@@ -205,38 +210,50 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
     const int64_t nk = a.kp / kMK;
     load(0);
     const int fr = lane % 32, fk = (lane / 32) * 16;
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        __syncthreads();
-        store();
-        __syncthreads();
-        if (kt + 1 < nk) load((kt + 1) * kMK);
-        if (!active) continue;
+    // Active and idle waves run separate loops with the same barriers: a
+    // branch around the MFMAs inside one loop makes the compiler copy every
+    // accumulator at the join on each iteration.
+    if (active) {
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            __syncthreads();
+            store();
+            __syncthreads();
+            if (kt + 1 < nk) load((kt + 1) * kMK);
 #pragma unroll
-        for (int ks = 0; ks < kMK / 32; ++ks) {
-            v4i_t fa[4], fb[2];
+            for (int ks = 0; ks < kMK / 32; ++ks) {
+                v4i_t fa[4], fb[WN];
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                fa[m] = *(const v4i_t*)(As + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
+                for (int m = 0; m < 4; ++m)
+                    fa[m] = *(const v4i_t*)(As + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
 #pragma unroll
-            for (int n = 0; n < 2; ++n)
-                fb[n] = *(const v4i_t*)(Bs + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
+                for (int n = 0; n < WN; ++n)
+                    fb[n] = *(const v4i_t*)(Bs + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+                for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 2; ++n) {
-                    if constexpr (FMT == kFmtI8) {
-                        acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n],
-                                                                          acc[m][n], 0, 0, 0);
-                    } else {  // 64 e2m1 values per row per k-step, unit (2^0) scales
-                        const v8i_t xa = {fa[m].x, fa[m].y, fa[m].z, fa[m].w, 0, 0, 0, 0};
-                        const v8i_t xb = {fb[n].x, fb[n].y, fb[n].z, fb[n].w, 0, 0, 0, 0};
-                        acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            xa, xb, acc[m][n], 4, 4, 0, 127, 0, 127);
+                    for (int n = 0; n < WN; ++n) {
+                        if constexpr (FMT == kFmtI8) {
+                            acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n],
+                                                                              acc[m][n], 0, 0, 0);
+                        } else {  // 64 e2m1 values per row per k-step, unit (2^0) scales
+                            const v8i_t xa = {fa[m].x, fa[m].y, fa[m].z, fa[m].w, 0, 0, 0, 0};
+                            const v8i_t xb = {fb[n].x, fb[n].y, fb[n].z, fb[n].w, 0, 0, 0, 0};
+                            acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                xa, xb, acc[m][n], 4, 4, 0, 127, 0, 127);
+                        }
                     }
-                }
+            }
         }
+    } else {
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            __syncthreads();
+            store();
+            __syncthreads();
+            if (kt + 1 < nk) load((kt + 1) * kMK);
+        }
+        return;
     }
-    if (!active) return;
+
 
     // D[row][col] of a 32x32 block: col = lane % 32, row = (r/4)*8 + (lane/32)*4 + r%4;
     // rows are j, columns are i, so 32 lanes store 32 consecutive i of one j
@@ -250,7 +267,7 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
             const double sj = a.s[j];
             const int64_t base = j * (j - 1) / 2;
 #pragma unroll
-            for (int n = 0; n < 2; ++n) {
+            for (int n = 0; n < WN; ++n) {
                 const int64_t i = ib + n * 32;
                 if (i >= j) continue;
                 const int32_t num = (int32_t)acc[m][n][r];   // exact in either format
@@ -264,7 +281,7 @@ __global__ __launch_bounds__(kMThreads, 1) void ps_mfma2_kernel(MfmaArgs a) {
     }
 }
 
-template <int FMT>
+template <int FMT, int WN>
 static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
     const int64_t kpad = plane_fields(m.n_f, FMT);
     const int64_t kp = (int64_t)m.levels * kpad / fields_per_byte(FMT);
@@ -279,13 +296,16 @@ static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
     const int64_t T = nb * (nb + 1) / 2;
     MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T};
     const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(ps_mfma2_kernel<FMT>, dim3((unsigned)grid), dim3(kMThreads), 0, st, a);
+    hipLaunchKernelGGL((ps_mfma2_kernel<FMT, WN>), dim3((unsigned)grid),
+                       dim3(mfma_threads<WN>()), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma2(const MfmaLaunch& m, hipStream_t st) {
     if (m.n_v < 2) return hipSuccess;
-    return m.fmt == kFmtF4 ? go_mfma2<kFmtF4>(m, st) : go_mfma2<kFmtI8>(m, st);
+    if (m.wide)
+        return m.fmt == kFmtF4 ? go_mfma2<kFmtF4, 4>(m, st) : go_mfma2<kFmtI8, 4>(m, st);
+    return m.fmt == kFmtF4 ? go_mfma2<kFmtF4, 2>(m, st) : go_mfma2<kFmtI8, 2>(m, st);
 }
 
 }  // namespace ps

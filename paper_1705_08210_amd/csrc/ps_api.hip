@@ -269,8 +269,9 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         s = s_ws;
     }
     if (is_mfma(path)) {
+        // opts.tile: 0 or 1 -> 4x2 blocks per wave, 2 -> 4x4 blocks per wave
         MfmaLaunch m{V, n_f, n_v, ld, levels, s, c2, n2, planes,
-                     path == PS_PATH_MFMA_FP4 ? 1 : 0};
+                     path == PS_PATH_MFMA_FP4 ? 1 : 0, (opts && opts->tile == 2) ? 1 : 0};
         e = launch_mfma2(m, stream);
         if (e == hipErrorNotSupported)
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");

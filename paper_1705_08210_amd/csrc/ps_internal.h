@@ -147,6 +147,7 @@ struct MfmaLaunch {
     void* n2;
     int8_t* planes;              // workspace: mfma_workspace_bytes()
     int fmt;                     // 0: int8 planes, 1: fp4 (e2m1) planes
+    int wide;                    // 0: 4x2 MFMA blocks per wave, 1: 4x4
 };
 size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt);
 hipError_t launch_mfma2(const MfmaLaunch& a, hipStream_t st);

@@ -222,16 +222,17 @@ def test_sampled_pairs_match_listed_oracle():
 
 # ------------------------------------------------ thermometer MFMA path ----
 
+@pytest.mark.parametrize("wide", [0, 2])
 @pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
 @pytest.mark.parametrize("n_v,n_f,L", [(300, 1001, 3), (257, 64, 1), (513, 333, 7),
                                        (2, 5, 3), (256, 128, 3), (40, 3000, 15)])
-def test_mfma_thermometer_bit_exact(n_v, n_f, L, path):
+def test_mfma_thermometer_bit_exact(n_v, n_f, L, path, wide):
     """min(a,b) = sum_t [a>=t][b>=t] on integer levels: the int8 matrix-core
     path must equal the oracle (and the VALU path) bit for bit."""
     probs = np.full(L + 1, 1.0 / (L + 1))
     V = workloads.levels(n_v, n_f, seed=n_v + L, probs=probs)
-    announce(f"2-way {path} n_v={n_v} n_f={n_f} L={L}")
-    c2, n2 = run2(V, path=path, levels=L)
+    announce(f"2-way {path} n_v={n_v} n_f={n_f} L={L} tile={wide}")
+    c2, n2 = run2(V, path=path, levels=L, tile=wide)
     ref, rn2 = oracle.c2_all(V, with_n2=True)
     check_exact_f32(c2, ref, "c2")
     assert np.array_equal(n2.astype(np.float64), rn2)
