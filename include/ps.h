@@ -192,9 +192,11 @@ size_t ps2_batched_workspace_size(const ps_problem* probs, int32_t n,
                                   int32_t dtype, const ps_opts* opts);
 
 /*
- * Many independent uneven 2-way problems in one persistent launch over a
- * combined tile list ordered longest-first (the load-balancing idea of
- * Section 4.1 applied to tiles of one GPU).  Uploads the problem table and
+ * Many independent uneven 2-way problems in one launch over a combined list
+ * of (problem, tile, field chunk) work items ordered longest first (the
+ * load-balancing idea of Section 4.1 applied to the tiles of one GPU); the
+ * hardware hands items to free slots in list order, a greedy longest-first
+ * schedule.  A finish pass forms every problem's c2 (and n2).  Uploads the problem table and
  * tile list into the workspace from host memory on `stream` and, as the one
  * exception to the no-synchronisation rule, waits for `stream` once so that
  * the upload has completed before returning; then launches.  Use the plan
@@ -206,7 +208,7 @@ ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype,
                               const ps_opts* opts, hipStream_t stream);
 
 /* A captured batch: the upload is done once at creation and the launches
- * (sums, counter reset, persistent compute) are captured in a HIP graph. */
+ * (sums, tile sums, finish) are captured in a HIP graph. */
 typedef struct ps_plan ps_plan;
 
 /* Builds the tile list, uploads it (synchronously, once) and captures the

@@ -186,24 +186,66 @@ __global__ __launch_bounds__(1024) void ps_prefix3_kernel(int64_t n_v, int64_t j
     if (nj == 0 && threadIdx.x == 0) prefix[0] = 0;
 }
 
-// Field-chunk split, 2-way finish: n2 = sum over chunks in FP64 (fixed order),
-// then the Section 2.1 ratio.  One thread per pair, colex order.
-__global__ __launch_bounds__(256) void ps_finish2_kernel(Mg2Launch a) {
-    const int64_t np = a.n_v * (a.n_v - 1) / 2;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < np;
-         idx += (int64_t)gridDim.x * blockDim.x) {
+// 2-way finish from raw tile sums: for floating storage the FP32 sums of the
+// field chunks are added in FP64 in a fixed order (the field-chunk split);
+// for uint8 the single raw sum is sum |a - b| and n2 = (s_i + s_j - sum) / 2.
+// Then the Section 2.1 ratio.  One thread per pair, colex order.
+template <int DT>
+__device__ __forceinline__ void finish_pairs(int64_t n_v, int32_t nchunks, const float* partial,
+                                             const double* s, float* c2, void* n2,
+                                             int64_t first, int64_t stride) {
+    const int64_t np = n_v * (n_v - 1) / 2;
+    for (int64_t idx = first; idx < np; idx += stride) {
         int64_t j = (int64_t)((1.0 + __builtin_sqrt(1.0 + 8.0 * (double)idx)) * 0.5);
         while (j * (j - 1) / 2 > idx) --j;
         while ((j + 1) * j / 2 <= idx) ++j;
         const int64_t i = idx - j * (j - 1) / 2;
-        double num = 0.0;
-        for (int c = 0; c < a.nchunks; ++c) num += (double)a.partial[c * np + idx];
-        if (a.n2) ((float*)a.n2)[idx] = (float)num;
-        if (a.c2) {
-            const double d = a.s[i] + a.s[j];
-            a.c2[idx] = d > 0.0 ? (float)((2.0 * num) / d) : 0.0f;
+        double num;
+        if constexpr (DT == PS_U8) {
+            const uint32_t sad = ((const uint32_t*)partial)[idx];
+            const int64_t v = ((int64_t)s[i] + (int64_t)s[j] - (int64_t)sad) / 2;
+            num = (double)v;
+            if (n2) ((int32_t*)n2)[idx] = (int32_t)v;
+        } else {
+            num = 0.0;
+            for (int c = 0; c < nchunks; ++c) num += (double)partial[c * np + idx];
+            if (n2) ((float*)n2)[idx] = (float)num;
+        }
+        if (c2) {
+            const double d = s[i] + s[j];
+            c2[idx] = d > 0.0 ? (float)((2.0 * num) / d) : 0.0f;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void ps_finish2_kernel(Mg2Launch a) {
+    finish_pairs<PS_F32>(a.n_v, a.nchunks, a.partial, a.s, a.c2, a.n2,
+                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                         (int64_t)gridDim.x * blockDim.x);
+}
+
+// Every problem of a batch (blockIdx.y = problem).
+template <int DT>
+__global__ __launch_bounds__(256) void ps_finish2_batched_kernel(const DevProblem* probs) {
+    const DevProblem p = probs[blockIdx.y];
+    if (p.n_v < 2) return;
+    finish_pairs<DT>(p.n_v, p.nchunks, p.partial, p.s, p.c2, p.n2,
+                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                     (int64_t)gridDim.x * blockDim.x);
+}
+
+hipError_t launch_finish2_batched(int32_t dt, const DevProblem* probs, int32_t n,
+                                  int64_t max_pairs, hipStream_t st) {
+    if (n <= 0 || max_pairs <= 0) return hipSuccess;
+    int64_t blocks = (max_pairs + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    const dim3 grid((unsigned)blocks, (unsigned)n);
+    switch (dt) {
+    case PS_F32: hipLaunchKernelGGL(ps_finish2_batched_kernel<PS_F32>, grid, dim3(256), 0, st, probs); break;
+    case PS_F16: hipLaunchKernelGGL(ps_finish2_batched_kernel<PS_F16>, grid, dim3(256), 0, st, probs); break;
+    default:     hipLaunchKernelGGL(ps_finish2_batched_kernel<PS_U8>, grid, dim3(256), 0, st, probs); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {

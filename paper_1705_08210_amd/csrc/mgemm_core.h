@@ -18,9 +18,6 @@
 
 #include "ps_internal.h"
 
-#ifndef PS_UNROLL_BLOCKED
-#define PS_UNROLL_BLOCKED 1
-#endif
 #ifndef PS_UNROLL_PLAIN
 #define PS_UNROLL_PLAIN 4
 #endif
@@ -45,17 +42,8 @@ template <int DT> struct Ops;
 template <> struct Ops<PS_F32> {
     using Acc = float;
     static constexpr int kEsz = 4;
-    __device__ __forceinline__ static float first(uint32_t a, uint32_t b) {
-        return __builtin_fminf(as_f32(a), as_f32(b));
-    }
     __device__ __forceinline__ static float step(float acc, uint32_t a, uint32_t b) {
         return acc + __builtin_fminf(as_f32(a), as_f32(b));
-    }
-    __device__ __forceinline__ static uint32_t term(uint32_t a, uint32_t b) {
-        return as_u32(__builtin_fminf(as_f32(a), as_f32(b)));
-    }
-    __device__ __forceinline__ static float accum(float acc, uint32_t t) {
-        return acc + as_f32(t);
     }
     __device__ __forceinline__ static uint32_t xmin(uint32_t a, uint32_t b) {
         return as_u32(__builtin_fminf(as_f32(a), as_f32(b)));
@@ -65,22 +53,10 @@ template <> struct Ops<PS_F32> {
 template <> struct Ops<PS_F16> {
     using Acc = float;
     static constexpr int kEsz = 2;
-    __device__ __forceinline__ static float first(uint32_t a, uint32_t b) {
-        const h2_t one = {(_Float16)1.0f, (_Float16)1.0f};
-        return __builtin_amdgcn_fdot2(__builtin_elementwise_min(as_h2(a), as_h2(b)),
-                                      one, 0.0f, false);
-    }
     __device__ __forceinline__ static float step(float acc, uint32_t a, uint32_t b) {
         const h2_t one = {(_Float16)1.0f, (_Float16)1.0f};
         return __builtin_amdgcn_fdot2(__builtin_elementwise_min(as_h2(a), as_h2(b)),
                                       one, acc, false);
-    }
-    __device__ __forceinline__ static uint32_t term(uint32_t a, uint32_t b) {
-        return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(as_h2(a), as_h2(b)));
-    }
-    __device__ __forceinline__ static float accum(float acc, uint32_t t) {
-        const h2_t one = {(_Float16)1.0f, (_Float16)1.0f};
-        return __builtin_amdgcn_fdot2(as_h2(t), one, acc, false);
     }
     __device__ __forceinline__ static uint32_t xmin(uint32_t a, uint32_t b) {
         return __builtin_bit_cast(uint32_t,
@@ -91,9 +67,6 @@ template <> struct Ops<PS_F16> {
 template <> struct Ops<PS_U8> {
     using Acc = uint32_t;
     static constexpr int kEsz = 1;
-    __device__ __forceinline__ static uint32_t first(uint32_t a, uint32_t b) {
-        return __builtin_amdgcn_sad_u8(a, b, 0u);
-    }
     __device__ __forceinline__ static uint32_t step(uint32_t acc, uint32_t a, uint32_t b) {
         return __builtin_amdgcn_sad_u8(a, b, acc);
     }
@@ -206,7 +179,7 @@ __device__ __forceinline__ int lane_col(int wave, int ly, int c) {
 //   active: whether this wave does the arithmetic.
 //   [kt0, kt1): the field tiles summed (kt1 < 0: all of them).
 // ---------------------------------------------------------------------------
-template <int DT, int TM, int TN, int BKW, bool BLOCKED, bool XJ>
+template <int DT, int TM, int TN, int BKW, bool XJ>
 __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nbytes,
                                          bool vec, int64_t a_row0, int64_t a_end,
                                          int64_t b_row0, int64_t b_end, const char* xrow,
@@ -231,11 +204,11 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
     const int64_t tile_bytes = (int64_t)BKW * 4;
     const int64_t nk_all = (nbytes + tile_bytes - 1) / tile_bytes;
     const int64_t nk = kt1 < 0 || kt1 > nk_all ? nk_all : kt1;
-    // The plain 2-way variant prefetches the next field tile into registers
-    // while computing; the blocked variant (twice the accumulators) and the
-    // 3-way slices (which also stage v_j) load each tile just before staging
-    // it and rely on the other resident workgroups to cover the latency.
-    constexpr bool kPrefetch = !BLOCKED && !XJ;
+    // 2-way tiles prefetch the next field tile into registers while
+    // computing; the 3-way slices (which also stage v_j) load each tile just
+    // before staging it and rely on the other resident workgroups to cover
+    // the latency.
+    constexpr bool kPrefetch = !XJ;
     SA sa;
     SB sb;
     if (kPrefetch && kt0 < nk) {
@@ -259,56 +232,21 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
             sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
         }
         if (!active) continue;
-        if constexpr (BLOCKED) {
-            Acc p[TM][TN];
-            {
-                uint32_t a[TM], b[TN];
+        constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
+#pragma unroll kUnroll
+        for (int w = 0; w < BKW; ++w) {
+            uint32_t a[TM], b[TN];
 #pragma unroll
-                for (int g = 0; g < TM / 4; ++g)
-                    *(uint4*)&a[4 * g] = *(const uint4*)&As[ar + g * 32];
+            for (int g = 0; g < TM / 4; ++g)
+                *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
 #pragma unroll
-                for (int g = 0; g < TN / 4; ++g)
-                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[bc + g * 32];
-#pragma unroll
-                for (int r = 0; r < TM; ++r)
-#pragma unroll
-                    for (int c = 0; c < TN; ++c) p[r][c] = Ops<DT>::first(a[r], b[c]);
-            }
-#pragma unroll PS_UNROLL_BLOCKED
-            for (int w = 1; w < BKW; ++w) {
-                uint32_t a[TM], b[TN];
-#pragma unroll
-                for (int g = 0; g < TM / 4; ++g)
-                    *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
-#pragma unroll
-                for (int g = 0; g < TN / 4; ++g)
-                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
-#pragma unroll
-                for (int r = 0; r < TM; ++r)
-#pragma unroll
-                    for (int c = 0; c < TN; ++c) p[r][c] = Ops<DT>::step(p[r][c], a[r], b[c]);
-            }
+            for (int g = 0; g < TN / 4; ++g)
+                *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
 #pragma unroll
             for (int r = 0; r < TM; ++r)
 #pragma unroll
-                for (int c = 0; c < TN; ++c) acc[r][c] += p[r][c];
-        } else {
-            constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
-#pragma unroll kUnroll
-            for (int w = 0; w < BKW; ++w) {
-                uint32_t a[TM], b[TN];
-#pragma unroll
-                for (int g = 0; g < TM / 4; ++g)
-                    *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
-#pragma unroll
-                for (int g = 0; g < TN / 4; ++g)
-                    *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
-#pragma unroll
-                for (int r = 0; r < TM; ++r)
-#pragma unroll
-                    for (int c = 0; c < TN; ++c)
-                        acc[r][c] = Ops<DT>::step(acc[r][c], a[r], b[c]);
-            }
+                for (int c = 0; c < TN; ++c)
+                    acc[r][c] = Ops<DT>::step(acc[r][c], a[r], b[c]);
         }
     }
 }

@@ -89,6 +89,32 @@ static int64_t chunk_tiles(int32_t dt, int cfg) {
     return kChunkFields / ((int64_t)kValuCfgs[cfg].bkw * (4 / elem_size(dt)));
 }
 
+// Field-chunk plan of a 2-way launch.  Blocked accumulation splits at
+// kChunkFields; with opts.acc = AUTO a small triangle (fewer work items than
+// kMinItems) is split further, down to kMinChunkTiles field tiles per chunk,
+// so that enough workgroups run.
+struct Split {
+    int32_t nchunks;
+    int64_t chunk_tiles;
+};
+constexpr int64_t kMinItems = 2048;      // ~8 workgroups per CU
+constexpr int64_t kMinChunkTiles = 4;
+
+static Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o) {
+    Split sp{split_chunks(dt, n_f, choose_acc(n_f, o)), chunk_tiles(dt, cfg)};
+    const int acc_req = o ? o->acc : PS_ACC_AUTO;
+    if (dt == PS_U8 || acc_req != PS_ACC_AUTO || n_v < 2) return sp;
+    const int64_t ftiles = ceil_div(n_f * elem_size(dt), (int64_t)kValuCfgs[cfg].bkw * 4);
+    const int64_t tiles = tri_tiles(n_v, kValuCfgs[cfg].bm());
+    if (tiles * sp.nchunks >= kMinItems) return sp;
+    const int64_t want = std::min(ceil_div(kMinItems, tiles), ftiles / kMinChunkTiles);
+    if (want > sp.nchunks) {
+        sp.chunk_tiles = ceil_div(ftiles, want);
+        sp.nchunks = (int32_t)ceil_div(ftiles, sp.chunk_tiles);
+    }
+    return sp;
+}
+
 static bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4; }
 
 static int choose_path(int32_t dt, const ps_opts* o) {
@@ -224,9 +250,10 @@ size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
                           const ps_opts* opts) {
     if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
     const int path = choose_path(dtype, opts);
-    return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0,
-                      split_chunks(dtype, n_f, choose_acc(n_f, opts)), nullptr, nullptr,
-                      nullptr, nullptr);
+    const Split sp = plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts),
+                                opts);
+    return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0, sp.nchunks,
+                      nullptr, nullptr, nullptr, nullptr);
 }
 
 ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
@@ -255,9 +282,9 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
     float* partial = nullptr;
-    const int acc = choose_acc(n_f, opts);
-    const int32_t nchunks = split_chunks(dtype, n_f, acc);
-    const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, nchunks,
+    const int cfg = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
+    const Split sp = plan_split(dtype, n_f, n_v, cfg, opts);
+    const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, sp.nchunks,
                                    workspace, &s_ws, &planes, &partial);
     if (ws_bytes < need || (need && !workspace))
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
@@ -277,19 +304,17 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");
         return e == hipSuccess ? PS_OK : hip_fail(e, "mfma launch");
     }
-    const int cfg = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
-    Mg2Launch a{V, n_f, n_v, ld, s, c2, n2, PS_ACC_PLAIN, cfg,
-                nchunks, chunk_tiles(dtype, cfg), partial};
+    Mg2Launch a{V, n_f, n_v, ld, s, c2, n2, cfg, sp.nchunks, sp.chunk_tiles, partial};
     e = launch_mg2(dtype, a, stream);
-    if (e == hipSuccess && nchunks > 1) e = launch_finish2(dtype, a, stream);
+    if (e == hipSuccess && sp.nchunks > 1) e = launch_finish2(dtype, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "2-way launch");
 }
 
 // The field-split partials of the pair prepass and of the slices run one
 // after the other on the stream and share one region.
-static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t nchunks,
-                         int64_t stage, void* ws, double** s_ws, void** n2_ws,
-                         int64_t** prefix, float** partial) {
+static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t nchunks2,
+                         int32_t nchunks3, int64_t stage, void* ws, double** s_ws,
+                         void** n2_ws, int64_t** prefix, float** partial) {
     Carver c(ws);
     double* s = nullptr;
     void* n2 = nullptr;
@@ -297,11 +322,10 @@ static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
     if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * 4);
     int64_t* pre = (int64_t*)c.take((size_t)(n_v + 1) * sizeof(int64_t));
-    if (nchunks > 1) {
-        const int64_t pairs = n2_given ? 0 : n_v * (n_v - 1) / 2;
-        part = (float*)c.take((size_t)nchunks * (size_t)(pairs > stage ? pairs : stage) *
-                              sizeof(float));
-    }
+    const int64_t need2 = (!n2_given && nchunks2 > 1) ? nchunks2 * (n_v * (n_v - 1) / 2) : 0;
+    const int64_t need3 = nchunks3 > 1 ? nchunks3 * stage : 0;
+    if (need2 > 0 || need3 > 0)
+        part = (float*)c.take((size_t)(need2 > need3 ? need2 : need3) * sizeof(float));
     if (s_ws) *s_ws = s;
     if (n2_ws) *n2_ws = n2;
     if (prefix) *prefix = pre;
@@ -316,8 +340,11 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (j_begin < 1) j_begin = 1;
     if (j_end > n_v - 1) j_end = n_v - 1;
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
-    return ws3_layout(n_v, s_given, n2_given, split_chunks(dtype, n_f, choose_acc(n_f, opts)),
-                      stage, nullptr, nullptr, nullptr, nullptr, nullptr);
+    const Split sp2 =
+        plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
+    return ws3_layout(n_v, s_given, n2_given, sp2.nchunks,
+                      split_chunks(dtype, n_f, choose_acc(n_f, opts)), stage, nullptr, nullptr,
+                      nullptr, nullptr, nullptr);
 }
 
 int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end) {
@@ -346,11 +373,12 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     void* n2_ws = nullptr;
     int64_t* prefix = nullptr;
     float* partial = nullptr;
-    const int acc = choose_acc(n_f, opts);
-    const int32_t nchunks = split_chunks(dtype, n_f, acc);
+    const int cfg2 = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
+    const Split sp2 = plan_split(dtype, n_f, n_v, cfg2, opts);   // as ps2_compute would
+    const int32_t nchunks = split_chunks(dtype, n_f, choose_acc(n_f, opts));
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
-    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, nchunks, stage, workspace,
-                                   &s_ws, &n2_ws, &prefix, &partial);
+    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, sp2.nchunks, nchunks, stage,
+                                   workspace, &s_ws, &n2_ws, &prefix, &partial);
     if (ws_bytes < need || !workspace)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
     if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
@@ -361,19 +389,18 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         s = s_ws;
     }
     if (!n2) {  // the pair numerators of Eq. 1 (the 2-way mGEMM prepass)
-        const int cfg2 = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
-        Mg2Launch a{V, n_f, n_v, ld, s, nullptr, n2_ws, PS_ACC_PLAIN, cfg2,
-                    nchunks, chunk_tiles(dtype, cfg2), partial};
+        Mg2Launch a{V, n_f, n_v, ld, s, nullptr, n2_ws, cfg2, sp2.nchunks, sp2.chunk_tiles,
+                    partial};
         e = launch_mg2(dtype, a, stream);
-        if (e == hipSuccess && nchunks > 1) e = launch_finish2(dtype, a, stream);
+        if (e == hipSuccess && sp2.nchunks > 1) e = launch_finish2(dtype, a, stream);
         if (e != hipSuccess) return hip_fail(e, "3-way numerator prepass launch");
         n2 = n2_ws;
     }
     const int cfg = choose_cfg(dtype, 3, PS_PATH_VALU, n_f, n_v, opts);
     const int bm = kValuCfgs[cfg].bm();
     Mg3Launch a{V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, prefix,
-                slab_tiles(n_v, j_begin, j_end, bm, bm), PS_ACC_PLAIN, cfg,
-                nchunks, chunk_tiles(dtype, cfg), partial};
+                slab_tiles(n_v, j_begin, j_end, bm, bm), cfg, nchunks, chunk_tiles(dtype, cfg),
+                partial};
     e = launch_mg3_prefix(a, stream);
     if (e == hipSuccess) e = launch_mg3(dtype, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");
@@ -390,8 +417,8 @@ struct BatchLayout {
     DevProblem* probs = nullptr;
     int32_t* need_s = nullptr;
     BatchTile* tiles = nullptr;
-    int32_t* counter = nullptr;
     double* s = nullptr;
+    float* partial = nullptr;    // all split problems' chunk partials, back to back
     size_t bytes = 0;
 };
 
@@ -402,20 +429,40 @@ static int64_t batch_sums_len(const ps_problem* p, int32_t n) {
     return t;
 }
 
-static int64_t batch_tiles(const ps_problem* p, int32_t n, int bm) {
+static int64_t pairs_of(int64_t n_v) { return n_v * (n_v - 1) / 2; }
+
+// Field chunks of problem p of a batch (each problem takes its own
+// accumulation choice from its n_f).
+static int32_t batch_chunks(const ps_problem& p, int32_t dt, const ps_opts* o) {
+    return split_chunks(dt, p.n_f, choose_acc(p.n_f, o));
+}
+
+static int64_t batch_items(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o,
+                           int bm) {
     int64_t t = 0;
-    for (int32_t i = 0; i < n; ++i) t += p[i].n_v >= 2 ? tri_tiles(p[i].n_v, bm) : 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (p[i].n_v >= 2) t += tri_tiles(p[i].n_v, bm) * batch_chunks(p[i], dt, o);
     return t;
 }
 
-static BatchLayout batch_layout(const ps_problem* p, int32_t n, int bm, void* ws) {
+// Raw tile sums of every problem (all problems, split or not, go through the
+// batched finish kernel).
+static int64_t batch_partial_len(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o) {
+    int64_t t = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (p[i].n_v >= 2) t += (int64_t)batch_chunks(p[i], dt, o) * pairs_of(p[i].n_v);
+    return t;
+}
+
+static BatchLayout batch_layout(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o,
+                                int bm, void* ws) {
     Carver c(ws);
     BatchLayout L;
     L.probs = (DevProblem*)c.take(sizeof(DevProblem) * (size_t)(n > 0 ? n : 1));
     L.need_s = (int32_t*)c.take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    L.counter = (int32_t*)c.take(sizeof(int32_t));
-    L.tiles = (BatchTile*)c.take(sizeof(BatchTile) * (size_t)batch_tiles(p, n, bm));
+    L.tiles = (BatchTile*)c.take(sizeof(BatchTile) * (size_t)batch_items(p, n, dt, o, bm));
     L.s = (double*)c.take(sizeof(double) * (size_t)batch_sums_len(p, n));
+    L.partial = (float*)c.take(sizeof(float) * (size_t)batch_partial_len(p, n, dt, o));
     L.bytes = c.used;
     return L;
 }
@@ -457,56 +504,64 @@ static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, con
 }
 
 // Host-side tables of a batch: device problem records (with workspace sums
-// where the caller gave none) and the tile list, longest problems first.
-static void batch_tables(const ps_problem* probs, int32_t n, int bm, const BatchLayout& L,
-                         std::vector<DevProblem>& dp, std::vector<int32_t>& need,
-                         std::vector<BatchTile>& tiles, int64_t& max_nv) {
+// and chunk partials where needed) and the work list, longest items first.
+static void batch_tables(const ps_problem* probs, int32_t n, int32_t dt, const ps_opts* o,
+                         int bm, const BatchLayout& L, std::vector<DevProblem>& dp,
+                         std::vector<int32_t>& need, std::vector<BatchTile>& tiles,
+                         int64_t& max_nv, int64_t& max_pairs) {
     dp.resize(n);
     need.resize(n);
-    int64_t soff = 0;
+    int64_t soff = 0, poff = 0;
     max_nv = 0;
+    max_pairs = 0;
     for (int32_t i = 0; i < n; ++i) {
         const ps_problem& p = probs[i];
-        dp[i] = DevProblem{p.V, p.n_f, p.n_v, p.ld, p.s, p.c2, p.n2};
+        const int32_t nch = p.n_v >= 2 ? batch_chunks(p, dt, o) : 1;
+        dp[i] = DevProblem{p.V, p.n_f, p.n_v, p.ld, p.s, p.c2, p.n2, nullptr, nch, 0};
         need[i] = p.s ? 0 : 1;
         if (!p.s) {
             dp[i].s = L.s + soff;
             soff += p.n_v;
         }
+        if (p.n_v >= 2) {
+            dp[i].partial = L.partial + poff;
+            poff += (int64_t)nch * pairs_of(p.n_v);
+            max_pairs = std::max(max_pairs, pairs_of(p.n_v));
+        }
         max_nv = std::max(max_nv, p.n_v);
     }
-    std::vector<int32_t> order(n);
-    for (int32_t i = 0; i < n; ++i) order[i] = i;
-    // every tile of a problem costs ~n_f: longest-processing-time first
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return probs[a].n_f > probs[b].n_f;
-    });
-    tiles.clear();
-    for (int32_t pi : order) {
+    // an item's cost is the number of fields its chunk covers
+    struct Item { int64_t cost; BatchTile t; };
+    std::vector<Item> items;
+    for (int32_t pi = 0; pi < n; ++pi) {
         if (probs[pi].n_v < 2) continue;
         const int64_t nb = ceil_div(probs[pi].n_v, bm);
-        for (int64_t bj = 0; bj < nb; ++bj)
-            for (int64_t bi = 0; bi <= bj; ++bi)
-                tiles.push_back(BatchTile{pi, (int32_t)bi, (int32_t)bj, 0});
+        const int32_t nch = dp[pi].nchunks;
+        for (int32_t c = 0; c < nch; ++c) {
+            const int64_t f0 = nch > 1 ? c * kChunkFields : 0;
+            const int64_t f1 = nch > 1 ? std::min(probs[pi].n_f, f0 + kChunkFields) : probs[pi].n_f;
+            for (int64_t bj = 0; bj < nb; ++bj)
+                for (int64_t bi = 0; bi <= bj; ++bi)
+                    items.push_back(Item{f1 - f0, BatchTile{pi, (int32_t)bi, (int32_t)bj, c}});
+        }
     }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    tiles.resize(items.size());
+    for (size_t k = 0; k < items.size(); ++k) tiles[k] = items[k].t;
 }
 
 static ps_status batch_enqueue(const BatchLayout& L, int32_t n, int32_t dt, int64_t ntiles,
-                               int64_t max_nv, int acc, int cfg, hipStream_t st) {
+                               int64_t max_nv, int64_t max_pairs, int cfg, hipStream_t st) {
     hipError_t e = launch_batched_sums(L.probs, L.need_s, n, dt, max_nv, st);
-    if (e == hipSuccess) e = launch_zero_i32(L.counter, 1, st);
     if (e == hipSuccess) {
-        MgBatchLaunch a{L.probs, L.tiles, ntiles, L.counter, 0, acc, cfg};
+        MgBatchLaunch a{L.probs, L.tiles, ntiles, cfg, chunk_tiles(dt, cfg)};
         e = launch_mgb(dt, a, st);
     }
+    if (e == hipSuccess) e = launch_finish2_batched(dt, L.probs, n, max_pairs, st);
     return e == hipSuccess ? PS_OK : hip_fail(e, "batched launch");
 }
 
-static int batch_acc(const ps_problem* p, int32_t n, const ps_opts* o) {
-    int64_t nf = 0;
-    for (int32_t i = 0; i < n; ++i) nf = std::max(nf, p[i].n_f);
-    return choose_acc(nf, o);
-}
 
 }  // namespace ps
 
@@ -517,7 +572,7 @@ size_t ps2_batched_workspace_size(const ps_problem* probs, int32_t n, int32_t dt
     if (n < 0 || (n > 0 && !probs) || elem_size(dtype) == 0) return 0;
     const int cfg = batch_cfg(probs, n, dtype, opts);
     if (cfg < 0 || cfg >= kNumValuCfgs) return 0;
-    return batch_layout(probs, n, kValuCfgs[cfg].bm(), nullptr).bytes;
+    return batch_layout(probs, n, dtype, opts, kValuCfgs[cfg].bm(), nullptr).bytes;
 }
 
 ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype, void* ws,
@@ -527,15 +582,15 @@ ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype,
     if (n == 0) return PS_OK;
     const int cfg = batch_cfg(probs, n, dtype, opts);
     const int bm = kValuCfgs[cfg].bm();
-    const BatchLayout L = batch_layout(probs, n, bm, ws);
+    const BatchLayout L = batch_layout(probs, n, dtype, opts, bm, ws);
     if (ws_bytes < L.bytes || !ws)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.bytes);
     if (!aligned(ws, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
     std::vector<DevProblem> dp;
     std::vector<int32_t> need;
     std::vector<BatchTile> tiles;
-    int64_t max_nv;
-    batch_tables(probs, n, bm, L, dp, need, tiles, max_nv);
+    int64_t max_nv, max_pairs;
+    batch_tables(probs, n, dtype, opts, bm, L, dp, need, tiles, max_nv, max_pairs);
     hipError_t e = hipMemcpyAsync(L.probs, dp.data(), sizeof(DevProblem) * n,
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
@@ -548,8 +603,7 @@ ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype,
     // the host tables die at return: wait until the copies have consumed them
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "batched table upload");
-    return batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv,
-                         batch_acc(probs, n, opts), cfg, stream);
+    return batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv, max_pairs, cfg, stream);
 }
 
 struct ps_plan {
@@ -566,15 +620,15 @@ ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs, int32_
     if (st != PS_OK) return st;
     const int cfg = batch_cfg(probs, n, dtype, opts);
     const int bm = kValuCfgs[cfg].bm();
-    const BatchLayout L = batch_layout(probs, n, bm, ws);
+    const BatchLayout L = batch_layout(probs, n, dtype, opts, bm, ws);
     if (ws_bytes < L.bytes || !ws)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.bytes);
     if (!aligned(ws, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
     std::vector<DevProblem> dp;
     std::vector<int32_t> need;
     std::vector<BatchTile> tiles;
-    int64_t max_nv = 0;
-    batch_tables(probs, n, bm, L, dp, need, tiles, max_nv);
+    int64_t max_nv = 0, max_pairs = 0;
+    batch_tables(probs, n, dtype, opts, bm, L, dp, need, tiles, max_nv, max_pairs);
     hipError_t e = hipSuccess;
     if (n > 0) {
         e = hipStreamSynchronize(stream);
@@ -593,8 +647,7 @@ ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs, int32_
     ps_plan* p = new ps_plan();
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = n > 0 ? batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv,
-                                   batch_acc(probs, n, opts), cfg, cs)
+        st = n > 0 ? batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv, max_pairs, cfg, cs)
                    : PS_OK;
         hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
         if (st == PS_OK && e2 != hipSuccess) st = hip_fail(e2, "plan capture");

@@ -58,7 +58,6 @@ struct Mg2Launch {
     const double* s;
     float* c2;                   // may be null
     void* n2;                    // may be null
-    int acc;                     // PS_ACC_PLAIN / PS_ACC_BLOCKED (in-register)
     int cfg;                     // index into kValuCfgs
     // field-chunk split: nchunks > 1 sums chunks of chunk_tiles field tiles
     // in separate workgroups into partial[chunk * npairs + pair] (FP32), then
@@ -79,7 +78,6 @@ struct Mg3Launch {
     float* c3;
     int64_t* prefix;             // workspace: j_end - j_begin + 1 int64
     int64_t ntiles;
-    int acc;
     int cfg;
     int32_t nchunks;             // field-chunk split as for Mg2Launch; partial
     int64_t chunk_tiles;         // holds nchunks * stage-size FP32 values
@@ -93,21 +91,21 @@ struct DevProblem {
     const double* s;
     float* c2;
     void* n2;
+    float* partial;              // raw tile sums: nchunks * pairs 32-bit values
+    int32_t nchunks, pad;        // field chunks (1: no split)
 };
 
-// One output tile of a batched launch.
+// One work item of a batched launch: a tile of a problem and a field chunk.
 struct BatchTile {
-    int32_t prob, bi, bj, pad;
+    int32_t prob, bi, bj, chunk;
 };
 
 struct MgBatchLaunch {
     const DevProblem* probs;
-    const BatchTile* tiles;
+    const BatchTile* tiles;      // work items, longest first
     int64_t ntiles;
-    int32_t* counter;            // work counter, zeroed by the launch sequence
-    int grid;
-    int acc;
     int cfg;
+    int64_t chunk_tiles;         // field tiles per chunk (same for all problems)
 };
 
 // Tiles of the 2-way upper triangle for n_v vectors and output tile `bm`.
@@ -130,6 +128,8 @@ hipError_t launch_mg3_f16(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st);
+hipError_t launch_finish2_batched(int32_t dt, const DevProblem* probs, int32_t n,
+                                  int64_t max_pairs, hipStream_t st);
 hipError_t launch_mgb_f32(const MgBatchLaunch& a, hipStream_t st);
 hipError_t launch_mgb_f16(const MgBatchLaunch& a, hipStream_t st);
 hipError_t launch_mgb_u8(const MgBatchLaunch& a, hipStream_t st);

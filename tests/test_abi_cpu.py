@@ -119,7 +119,11 @@ def test_workspace_sizes():
     stage = math.comb(n, 3)
     assert g(0, 9000, n, 1, 1, 1, n - 1, None) == (math.ceil((n + 1) * 8 / 256) * 256
                                                   + math.ceil(3 * stage * 4 / 256) * 256)
-    assert f(0, 9000, 1000, 1, None) == math.ceil(3 * (1000 * 999 // 2) * 4 / 256) * 256
+    blocked = opts(acc=2)
+    assert f(0, 9000, 1000, 1, blocked) == math.ceil(3 * (1000 * 999 // 2) * 4 / 256) * 256
+    assert f(0, 9000, 1000, 1, opts(acc=1)) == 0   # plain: one chunk, no partials
+    # auto on a small triangle splits further so that enough workgroups run
+    assert f(0, 9000, 1000, 1, None) > f(0, 9000, 1000, 1, blocked)
     assert f(2, 9000, 1000, 1, None) == 0          # integer data: no split
 
 
