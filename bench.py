@@ -39,6 +39,7 @@ if ROOT not in sys.path:
 FP32_LANE_OPS_TOPS = 256 * 128 * 2.4e9 / 1e12   # 78.64
 HALF_RATE_OPS_TOPS = 256 * 64 * 2.4e9 / 1e12    # 39.32
 INT8_MFMA_PEAK_TOPS = 5000.0                    # dense int8 matrix-core ops / s (2 per MAC)
+FP4_MFMA_PEAK_TOPS = 10100.0                    # dense fp4 matrix-core ops / s
 HBM_PEAK_GBS = 8000.0
 
 
@@ -50,7 +51,7 @@ def parse(argv=None):
     ap.add_argument("--workload", default="gwas_20000x16384")
     ap.add_argument("--storage", default="auto", choices=["auto", "f32", "f16"])
     ap.add_argument("--acc", default="auto", choices=["auto", "plain", "blocked"])
-    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "mfma_fp4"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
@@ -60,6 +61,12 @@ def parse(argv=None):
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel of known "
                          "size, to scale HBM byte counters of a profiler run)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL"),
+                    help="no benchmark: summarise two rocprofv3 --pmc runs (FETCH_SIZE, "
+                         "WRITE_SIZE) of this script for --workload/--storage/--path into "
+                         "the traffic file read by later runs")
+    ap.add_argument("--pmc-command", action="append", default=[],
+                    help="command line recorded in the --pmc-summary output")
     return ap.parse_args(argv)
 
 
@@ -139,15 +146,125 @@ def cpu_baseline_triples(V, n_f, seconds, seed=123):
                       f"(oracle c3 of listed triples, pair terms included, {t:.1f} s)"}
 
 
-def roofline(bound, ops_per_cmp, cmp, kernel_ms, peak):
+# Source files that decide what each kernel does and how it is launched; their
+# digest stamps a recorded HBM-traffic figure, which is reported only while
+# the sources are unchanged.
+CSRC = os.path.join(ROOT, "paper_1705_08210_amd", "csrc")
+_VALU_SOURCES = ["ps_internal.h", "mgemm_core.h", "mgemm_kernels.h", "mg_common.hip",
+                 "mg_f32.hip", "mg_f16.hip", "mg_u8.hip", "ps_api.hip"]
+KERNEL_SOURCES = {
+    "ps_mg2_kernel": _VALU_SOURCES,
+    "ps_mg3_kernel": _VALU_SOURCES,
+    "ps_mgb_kernel": _VALU_SOURCES,
+    "ps_mfma2_kernel": ["ps_internal.h", "mfma.hip", "ps_api.hip"],
+}
+PROFILES = os.path.join(ROOT, "profiles")
+GIB = 1 << 30
+
+
+def source_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_file(kernel, key):
+    return os.path.join(PROFILES, f"traffic_{kernel}_{key}.txt")
+
+
+def recorded_traffic(kernel, key):
+    """HBM bytes per launch from a committed counter summary, or None when
+    there is none or the kernel's sources changed since it was taken."""
+    path = traffic_file(kernel, key)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("sources_sha256") != source_digest(kernel):
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def roofline(bound, ops_per_cmp, cmp, kernel_ms, peak, traffic=None):
     """achieved = algorithmic ops of one launch / its mean duration."""
     achieved = ops_per_cmp * cmp / (kernel_ms * 1e-3) / 1e12
     return {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2),
-            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None}
+            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": traffic}
+
+
+def _counters(d):
+    """Per-dispatch KiB of one rocprofv3 --pmc csv output directory."""
+    import csv
+    import glob
+    out = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                k = (r["Dispatch_Id"], r["Kernel_Name"], int(r["Grid_Size"]))
+                out[k] = out.get(k, 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, kernel, key, commands):
+    """Text summary of a FETCH_SIZE run and a WRITE_SIZE run of this script
+    with --copy-calibration: each counter is scaled by what it reads for the
+    1 GiB device-to-device copy (one copy kernel dispatch of known size)."""
+    fetch, write = _counters(fetch_dir), _counters(write_dir)
+
+    def calib(cnt):
+        # the calibration copy is the copy dispatch with the most bytes
+        cands = [(v, k) for k, v in cnt.items() if "copyBuffer" in k[1]]
+        v, k = max(cands)
+        return GIB / (v * 1024.0), v, k
+
+    ff, fv, fk = calib(fetch)
+    wf, wv, wk = calib(write)
+
+    def mean(cnt):
+        v = [x for k, x in cnt.items()
+             if k[1].startswith(f"void ps::{kernel}<") or k[1].startswith(f"ps::{kernel}(")]
+        return sum(v) / len(v), len(v)
+
+    fm, fn = mean(fetch)
+    wm, wn = mean(write)
+    traffic = fm * 1024.0 * ff + wm * 1024.0 * wf
+    lines = [f"kernel: {kernel}", f"workload: {key}"]
+    lines += [f"command: {c}" for c in commands]
+    lines += [
+        f"calibration fetch: copy dispatch {fk[0]} reads 1 GiB, FETCH_SIZE {fv:.1f} KiB "
+        f"-> factor {ff:.4f}",
+        f"calibration write: copy dispatch {wk[0]} writes 1 GiB, WRITE_SIZE {wv:.1f} KiB "
+        f"-> factor {wf:.4f}",
+        f"FETCH_SIZE per dispatch: {fm:.1f} KiB (mean of {fn}) -> {fm * 1024 * ff / 1e9:.3f} GB",
+        f"WRITE_SIZE per dispatch: {wm:.1f} KiB (mean of {wn}) -> {wm * 1024 * wf / 1e9:.3f} GB",
+        f"traffic_bytes_per_launch: {int(round(traffic))}",
+        f"sources_sha256: {source_digest(kernel)}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def traffic_key(args):
+    """Workload and operand type of a run: names its traffic file."""
+    wl = args.workload
+    if wl == "levels_8192x32768":
+        return wl + ("_fp4" if args.path == "mfma_fp4" else "_u8")
+    return wl + ("_f16" if args.storage == "f16" else "_f32")
 
 
 def main(argv=None):
     args = parse(argv)
+    if args.pmc_summary:
+        fetch_dir, write_dir, kernel = args.pmc_summary
+        sys.stdout.write(pmc_summary(fetch_dir, write_dir, kernel, traffic_key(args),
+                                     args.pmc_command))
+        return 0
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(sharding across GPUs is described in DESIGN.md, not implemented)",
@@ -191,7 +308,10 @@ def main(argv=None):
         cmp = n_f * m
         use_mfma = V.dtype == np.uint8 and (args.path == "mfma" or
                                             (args.path == "auto" and 1 <= levels <= 15))
-        if use_mfma:   # thermometer planes: `levels` int8 MACs (2 ops) per comparison
+        if V.dtype == np.uint8 and args.path == "mfma_fp4":   # e2m1 planes, FP32 sums
+            dtype, bound, ops_per_cmp, peak = "fp4", "mfma", 2.0 * levels, FP4_MFMA_PEAK_TOPS
+            kernel = "ps_mfma2_kernel"
+        elif use_mfma:   # thermometer planes: `levels` int8 MACs (2 ops) per comparison
             dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
             kernel = "ps_mfma2_kernel"
         elif V.dtype == np.uint8:   # v_sad_u8: 4 comparisons per op
@@ -315,8 +435,9 @@ def main(argv=None):
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": dtype, "data": "synthetic (seeded numpy PCG64)",
         "config": config,
-        "roofline": dict(roofline(bound, ops_per_cmp, cmp, kernel_ms, peak), kernel=kernel,
-                         kernel_ms=round(kernel_ms, 4)),
+        "roofline": dict(roofline(bound, ops_per_cmp, cmp, kernel_ms, peak,
+                                  recorded_traffic(kernel, traffic_key(args))),
+                         kernel=kernel, kernel_ms=round(kernel_ms, 4)),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu()

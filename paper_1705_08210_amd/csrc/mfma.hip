@@ -15,8 +15,8 @@
 //         (exact: every partial sum is an integer below 2^24).
 // Kernels:
 //   ps_thermo_expand_kernel  V (uint8, n_v x ld) -> planes P, row length
-//                            L * kpad fields, kpad = n_f rounded up to one
-//                            64-byte field tile; HBM-bound, one pass.
+//                            L * kpad fields, kpad = n_f rounded up to whole
+//                            field tiles; HBM-bound, one pass.
 //   ps_mfma2_kernel          upper-triangle tiles of P P^T, FP64 epilogue.
 #include <type_traits>
 
@@ -33,13 +33,25 @@ enum { kFmtI8 = 0, kFmtF4 = 1 };
 __host__ __device__ constexpr int fields_per_byte(int fmt) { return fmt == kFmtF4 ? 2 : 1; }
 
 constexpr int kMB = 256;      // output tile rows and columns
-constexpr int kMK = 64;       // field-tile depth in plane bytes
-constexpr int kPitch = 80;    // LDS bytes per tile row (64 + 16: conflict-free b128 reads)
-constexpr int kGroup = 8;     // tile columns per L2-sharing group
+constexpr int kPad = 16;      // LDS row padding: b128 reads of 32 rows spread over the banks
+constexpr int kTileFields = 128;   // plane rows are padded to whole multiples of this
 
-// Fields of one plane row, padded to whole 64-byte field tiles (>= 1 tile).
+// Field-tile depth in plane bytes.  A deeper tile gives each staged load
+// more MFMA work to hide behind; int8 with 8 waves fits 128 bytes (two
+// 147 KB LDS buffers, no spills), the fp4 and 4-wave variants run out of
+// registers there and keep 64.
+template <int FMT, int WN>
+__host__ __device__ constexpr int mfma_mk() { return (FMT == kFmtI8 && WN == 2) ? 128 : 64; }
+#ifndef PS_MFMA_GROUP
+#define PS_MFMA_GROUP 8
+#endif
+constexpr int kGroup = PS_MFMA_GROUP;   // tile columns per L2-sharing group (grouped_tri_decode)
+
+// Fields of one plane row, padded to whole field tiles of every variant
+// (kTileFields fields is 128 int8 bytes or 64 fp4 bytes; >= 1 tile).
 static int64_t plane_fields(int64_t n_f, int fmt) {
-    const int64_t q = (int64_t)kMK * fields_per_byte(fmt);
+    (void)fmt;
+    const int64_t q = kTileFields;
     const int64_t kpad = (n_f + q - 1) / q * q;
     return kpad > 0 ? kpad : q;
 }
@@ -63,7 +75,7 @@ __device__ __forceinline__ uint32_t nibbles_e2m1(uint32_t m) {
            ((m & 0x1000000u) >> 11);
 }
 
-// One thread per 32 fields of one vector; kpad is a multiple of 64.
+// One thread per 32 fields of one vector; kpad is a multiple of kTileFields.
 template <int FMT>
 __global__ __launch_bounds__(256) void ps_thermo_expand_kernel(const uint8_t* V, int64_t n_f,
                                                                int64_t n_v, int64_t ld,
@@ -111,39 +123,9 @@ __global__ __launch_bounds__(256) void ps_thermo_expand_kernel(const uint8_t* V,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Tile order: columns of the upper triangle are taken kGroup at a time and,
-// inside a group, row by row, so the tiles that run side by side on one XCD
-// share their row and column blocks in L2.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void grouped_tri_decode(int64_t t, int64_t nb, int64_t& bi,
-                                                   int64_t& bj) {
-    // callers guarantee 0 <= t < nb (nb + 1) / 2; every loop below is bounded
-    bi = bj = 0;
-    for (int64_t g0 = 0; g0 < nb; g0 += kGroup) {  // group of columns [g0, g1)
-        const int64_t g1 = g0 + kGroup < nb ? g0 + kGroup : nb;
-        const int64_t cnt = (g1 * (g1 + 1) - g0 * (g0 + 1)) / 2;
-        if (t >= cnt) {
-            t -= cnt;
-            continue;
-        }
-        for (int64_t r = 0; r < g1; ++r) {  // row r covers columns max(r, g0) .. g1-1
-            const int64_t c0 = r > g0 ? r : g0;
-            const int64_t w = g1 - c0;
-            if (t < w) {
-                bi = r;
-                bj = c0 + t;
-                return;
-            }
-            t -= w;
-        }
-        return;
-    }
-}
-
 struct MfmaArgs {
     const int8_t* P;
-    int64_t kp;           // plane-row length in bytes (levels * kpad), multiple of kMK
+    int64_t kp;           // plane-row length in bytes (levels * kpad), multiple of the tile depth
     int64_t n_v;
     const double* s;
     float* c2;
@@ -161,14 +143,19 @@ __host__ __device__ constexpr int mfma_threads() { return 64 * 2 * (kMB / (32 * 
 template <int FMT, int WN>
 __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArgs a) {
     constexpr int kMThreads = mfma_threads<WN>();
-    constexpr int kStage = kMB * 4 / kMThreads;   // 16-byte chunks per thread per operand
+    constexpr int kMK = mfma_mk<FMT, WN>();
+    constexpr int kPitch = kMK + kPad;
+    constexpr int kRowChunks = kMK / 16;           // 16-byte chunks per tile row
+    constexpr int kStage = kMB * kRowChunks / kMThreads;   // 16-byte chunks per thread per operand
+    static_assert(kMB * kRowChunks % kMThreads == 0, "staging must divide evenly");
     using AccT = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
-    __shared__ __attribute__((aligned(16))) int8_t As[kMB * kPitch];   // j rows
-    __shared__ __attribute__((aligned(16))) int8_t Bs[kMB * kPitch];   // i rows
+    // two buffers per operand: field tile kt+1 is staged while kt is consumed
+    __shared__ __attribute__((aligned(16))) int8_t As[2][kMB * kPitch];   // j rows
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][kMB * kPitch];   // i rows
     const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
     if (t >= a.ntiles) return;
     int64_t bi, bj;
-    grouped_tri_decode(t, a.nb, bi, bj);
+    grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
     const int64_t i0 = bi * kMB, j0 = bj * kMB;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int wr = (wave % 2) * 128;        // j offset of the wave's block
@@ -182,14 +169,13 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArg
 #pragma unroll
         for (int n = 0; n < WN; ++n) acc[m][n] = (AccT){};
 
-    // staging: 256 rows x 64 bytes per operand = 1024 16-byte chunks, four
-    // threads per row
+    // staging: 256 rows x kMK bytes per operand, kRowChunks threads per row
     uint4 ra[kStage], rb[kStage];
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int c = 0; c < kStage; ++c) {
             const int idx = threadIdx.x + c * kMThreads;
-            const int row = idx / 4, ch = idx % 4;
+            const int row = idx / kRowChunks, ch = idx % kRowChunks;
             const int64_t gj = j0 + row, gi = i0 + row;
             ra[c] = gj < a.n_v ? *(const uint4*)(a.P + gj * a.kp + k0 + ch * 16)
                                : make_uint4(0, 0, 0, 0);
@@ -197,37 +183,40 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArg
                                : make_uint4(0, 0, 0, 0);
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
         for (int c = 0; c < kStage; ++c) {
             const int idx = threadIdx.x + c * kMThreads;
-            const int row = idx / 4, ch = idx % 4;
-            *(uint4*)(As + row * kPitch + ch * 16) = ra[c];
-            *(uint4*)(Bs + row * kPitch + ch * 16) = rb[c];
+            const int row = idx / kRowChunks, ch = idx % kRowChunks;
+            *(uint4*)(As[buf] + row * kPitch + ch * 16) = ra[c];
+            *(uint4*)(Bs[buf] + row * kPitch + ch * 16) = rb[c];
         }
     };
 
     const int64_t nk = a.kp / kMK;
+    // prologue: tile 0 staged, tile 1 in registers
     load(0);
+    store(0);
+    __syncthreads();
+    if (nk > 1) load(kMK);
     const int fr = lane % 32, fk = (lane / 32) * 16;
     // Active and idle waves run separate loops with the same barriers: a
     // branch around the MFMAs inside one loop makes the compiler copy every
     // accumulator at the join on each iteration.
     if (active) {
         for (int64_t kt = 0; kt < nk; ++kt) {
-            __syncthreads();
-            store();
-            __syncthreads();
-            if (kt + 1 < nk) load((kt + 1) * kMK);
+            const int cur = (int)(kt & 1);
+            const int8_t* A = As[cur];
+            const int8_t* B = Bs[cur];
 #pragma unroll
             for (int ks = 0; ks < kMK / 32; ++ks) {
                 v4i_t fa[4], fb[WN];
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
-                    fa[m] = *(const v4i_t*)(As + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
+                    fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
 #pragma unroll
                 for (int n = 0; n < WN; ++n)
-                    fb[n] = *(const v4i_t*)(Bs + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
+                    fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -243,13 +232,15 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArg
                         }
                     }
             }
+            if (kt + 1 < nk) store(cur ^ 1);   // tile kt+1 into the other buffer
+            __syncthreads();   // kt+1 visible; everyone is done reading kt
+            if (kt + 2 < nk) load((kt + 2) * kMK);
         }
     } else {
         for (int64_t kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) store((int)(kt & 1) ^ 1);
             __syncthreads();
-            store();
-            __syncthreads();
-            if (kt + 1 < nk) load((kt + 1) * kMK);
+            if (kt + 2 < nk) load((kt + 2) * kMK);
         }
         return;
     }

@@ -31,6 +31,38 @@ __host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
     return (n - 1) * (j * (j - 1) / 2) - ((j - 1) * j * (2 * j - 1)) / 6;
 }
 
+// Upper-triangle block (bi <= bj) number t of an nb x nb block triangle in
+// grouped order: block columns are taken G at a time and, inside a group,
+// row by row, so the tiles that run side by side on one XCD share their row
+// and column blocks in L2.  The group is found from the column-major
+// position of t; the search inside a group is bounded by G rows.
+template <int G>
+__device__ __forceinline__ void grouped_tri_decode(int64_t t, int64_t nb, int64_t& bi,
+                                                   int64_t& bj) {
+    int64_t j = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (j * (j + 1) / 2 > t) --j;
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    const int64_t g0 = j / G * G;                    // group of columns [g0, g1)
+    const int64_t g1 = g0 + G < nb ? g0 + G : nb;
+    const int64_t w = g1 - g0;
+    int64_t u = t - g0 * (g0 + 1) / 2;
+    if (u < g0 * w) {                                // rows above the group's diagonal
+        bi = u / w;
+        bj = g0 + u % w;
+        return;
+    }
+    u -= g0 * w;
+    for (int64_t r = g0; r < g1; ++r) {              // row r: columns r .. g1-1
+        if (u < g1 - r) {
+            bi = r;
+            bj = r + u;
+            return;
+        }
+        u -= g1 - r;
+    }
+    bi = bj = 0;   // not reached for 0 <= t < nb (nb + 1) / 2
+}
+
 // ---------------------------------------------------------------------------
 // Tile configurations of the VALU min-product kernels.
 // A workgroup is 2x2 waves; lane (lx, ly) of a wave owns a TM x TN micro-tile
