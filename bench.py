@@ -65,6 +65,9 @@ def parse(argv=None):
                     help="no benchmark: summarise two rocprofv3 --pmc runs (FETCH_SIZE, "
                          "WRITE_SIZE) of this script for --workload/--storage/--path into "
                          "the traffic file read by later runs")
+    ap.add_argument("--counter-summary", nargs=2, metavar=("PMC_DIR", "KERNEL"),
+                    help="no benchmark: per-dispatch means of every counter of one "
+                         "rocprofv3 --pmc run for KERNEL, with busy fractions")
     ap.add_argument("--pmc-command", action="append", default=[],
                     help="command line recorded in the --pmc-summary output")
     return ap.parse_args(argv)
@@ -157,6 +160,7 @@ KERNEL_SOURCES = {
     "ps_mg3_kernel": _VALU_SOURCES,
     "ps_mgb_kernel": _VALU_SOURCES,
     "ps_mfma2_kernel": ["ps_internal.h", "mfma.hip", "ps_api.hip"],
+    "ps_mfma2_dma_kernel": ["ps_internal.h", "mfma.hip", "ps_api.hip"],
 }
 PROFILES = os.path.join(ROOT, "profiles")
 GIB = 1 << 30
@@ -250,6 +254,50 @@ def pmc_summary(fetch_dir, write_dir, kernel, key, commands):
     return "\n".join(lines) + "\n"
 
 
+def counter_summary(d, kernel, commands):
+    """Means per dispatch of the counters of one rocprofv3 --pmc run and what
+    they give.  GRBM_GUI_ACTIVE counts GPU cycles on each of the 8 XCDs, so
+    cycles = GRBM_GUI_ACTIVE / 8 and the clock = cycles / dispatch duration.
+    MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles); VALU issue
+    = SQ_INSTS_VALU / (256 CUs x cycles), wave instructions per CU per cycle
+    (FP32 min/add issue up to 2, packed FP16 and v_sad_u8 up to 1)."""
+    import csv
+    import glob
+    per, dur = {}, {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                n = r["Kernel_Name"]
+                if not (n.startswith(f"void ps::{kernel}<") or n.startswith(f"ps::{kernel}(")):
+                    continue
+                key = (r["Dispatch_Id"], r["Counter_Name"])
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+                dur[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    sums = {}
+    for (disp, c), v in per.items():
+        sums.setdefault(c, []).append(v)
+    m = {c: sum(v) / len(v) for c, v in sums.items()}
+    lines = [f"kernel: {kernel}"] + [f"command: {c}" for c in commands]
+    lines += [f"{c} per dispatch: {m[c]:.6g}" for c in sorted(m)]
+    if dur:
+        ns = sum(dur.values()) / len(dur)
+        lines.append(f"dispatch duration: {ns / 1e6:.3f} ms (mean of {len(dur)})")
+    if "GRBM_GUI_ACTIVE" in m:
+        cyc = m["GRBM_GUI_ACTIVE"] / 8.0
+        if dur:
+            lines.append(f"GPU clock: {cyc / ns:.3f} GHz (GRBM_GUI_ACTIVE / 8 / duration)")
+        if m.get("SQ_VALU_MFMA_BUSY_CYCLES"):
+            lines.append(f"MFMA busy: {m['SQ_VALU_MFMA_BUSY_CYCLES'] / (1024 * cyc):.3f} "
+                         "of SIMD cycles")
+        if "SQ_INSTS_VALU" in m:
+            lines.append(f"VALU issue: {m['SQ_INSTS_VALU'] / (256 * cyc):.3f} wave instructions "
+                         "per CU per cycle")
+    if "SQ_WAIT_INST_LDS" in m and "SQ_WAVE_CYCLES" in m:
+        lines.append(f"LDS instruction wait: {m['SQ_WAIT_INST_LDS'] / m['SQ_WAVE_CYCLES']:.3f}"
+                     " of wave cycles")
+    return "\n".join(lines) + "\n"
+
+
 def traffic_key(args):
     """Workload and operand type of a run: names its traffic file."""
     wl = args.workload
@@ -260,6 +308,10 @@ def traffic_key(args):
 
 def main(argv=None):
     args = parse(argv)
+    if args.counter_summary:
+        sys.stdout.write(counter_summary(args.counter_summary[0], args.counter_summary[1],
+                                         args.pmc_command))
+        return 0
     if args.pmc_summary:
         fetch_dir, write_dir, kernel = args.pmc_summary
         sys.stdout.write(pmc_summary(fetch_dir, write_dir, kernel, traffic_key(args),
@@ -310,7 +362,7 @@ def main(argv=None):
                                             (args.path == "auto" and 1 <= levels <= 15))
         if V.dtype == np.uint8 and args.path == "mfma_fp4":   # e2m1 planes, FP32 sums
             dtype, bound, ops_per_cmp, peak = "fp4", "mfma", 2.0 * levels, FP4_MFMA_PEAK_TOPS
-            kernel = "ps_mfma2_kernel"
+            kernel = "ps_mfma2_dma_kernel"
         elif use_mfma:   # thermometer planes: `levels` int8 MACs (2 ops) per comparison
             dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
             kernel = "ps_mfma2_kernel"

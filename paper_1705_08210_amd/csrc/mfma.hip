@@ -17,7 +17,10 @@
 //   ps_thermo_expand_kernel  V (uint8, n_v x ld) -> planes P, row length
 //                            L * kpad fields, kpad = n_f rounded up to whole
 //                            field tiles; HBM-bound, one pass.
-//   ps_mfma2_kernel          upper-triangle tiles of P P^T, FP64 epilogue.
+//   ps_mfma2_kernel          upper-triangle tiles of P P^T, FP64 epilogue
+//                            (int8: operands staged through registers);
+//   ps_mfma2_dma_kernel      the same with operands loaded straight into LDS
+//                            (fp4).
 #include <type_traits>
 
 #include "ps_internal.h"
@@ -34,7 +37,7 @@ __host__ __device__ constexpr int fields_per_byte(int fmt) { return fmt == kFmtF
 
 constexpr int kMB = 256;      // output tile rows and columns
 constexpr int kPad = 16;      // LDS row padding: b128 reads of 32 rows spread over the banks
-constexpr int kTileFields = 128;   // plane rows are padded to whole multiples of this
+constexpr int kTileBytes = 128;   // plane rows are padded to whole multiples of this
 
 // Field-tile depth in plane bytes.  A deeper tile gives each staged load
 // more MFMA work to hide behind; int8 with 8 waves fits 128 bytes (two
@@ -47,11 +50,10 @@ __host__ __device__ constexpr int mfma_mk() { return (FMT == kFmtI8 && WN == 2) 
 #endif
 constexpr int kGroup = PS_MFMA_GROUP;   // tile columns per L2-sharing group (grouped_tri_decode)
 
-// Fields of one plane row, padded to whole field tiles of every variant
-// (kTileFields fields is 128 int8 bytes or 64 fp4 bytes; >= 1 tile).
+// Fields of one plane row, padded to whole kTileBytes-byte field tiles
+// (a multiple of every variant's tile depth; >= 1 tile).
 static int64_t plane_fields(int64_t n_f, int fmt) {
-    (void)fmt;
-    const int64_t q = kTileFields;
+    const int64_t q = (int64_t)kTileBytes * fields_per_byte(fmt);
     const int64_t kpad = (n_f + q - 1) / q * q;
     return kpad > 0 ? kpad : q;
 }
@@ -75,7 +77,7 @@ __device__ __forceinline__ uint32_t nibbles_e2m1(uint32_t m) {
            ((m & 0x1000000u) >> 11);
 }
 
-// One thread per 32 fields of one vector; kpad is a multiple of kTileFields.
+// One thread per 32 fields of one vector; kpad is a multiple of 128.
 template <int FMT>
 __global__ __launch_bounds__(256) void ps_thermo_expand_kernel(const uint8_t* V, int64_t n_f,
                                                                int64_t n_v, int64_t ld,
@@ -139,6 +141,38 @@ struct MfmaArgs {
 // registers (AGPRs), one wave per SIMD, a third less LDS traffic per MAC.
 template <int WN>
 __host__ __device__ constexpr int mfma_threads() { return 64 * 2 * (kMB / (32 * WN)); }
+
+// Epilogue of one wave's 4 x WN blocks of 32 x 32 (Section 2.1): n2 exact,
+// c2 = 2 n2 / (s_i + s_j) in FP64, rounded once to FP32, d = 0 gives 0.
+template <int WN, typename AccT>
+__device__ __forceinline__ void mfma_epilogue(const AccT (&acc)[4][WN], const MfmaArgs& a,
+                                              int64_t i0, int64_t j0, int wr, int wc,
+                                              int lane) {
+    // D[row][col] of a 32x32 block: col = lane % 32, row = (r/4)*8 + (lane/32)*4 + r%4;
+    // rows are j, columns are i, so 32 lanes store 32 consecutive i of one j
+    const int64_t ib = i0 + wc + (lane % 32);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t j = j0 + wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
+            if (j >= a.n_v) continue;
+            const double sj = a.s[j];
+            const int64_t base = j * (j - 1) / 2;
+#pragma unroll
+            for (int n = 0; n < WN; ++n) {
+                const int64_t i = ib + n * 32;
+                if (i >= j) continue;
+                const int32_t num = (int32_t)acc[m][n][r];   // exact in either format
+                if (a.n2) a.n2[base + i] = num;
+                if (a.c2) {
+                    const double d = a.s[i] + sj;
+                    a.c2[base + i] = d > 0.0 ? (float)((2.0 * (double)num) / d) : 0.0f;
+                }
+            }
+        }
+    }
+}
 
 template <int FMT, int WN>
 __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArgs a) {
@@ -246,30 +280,138 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArg
     }
 
 
-    // D[row][col] of a 32x32 block: col = lane % 32, row = (r/4)*8 + (lane/32)*4 + r%4;
-    // rows are j, columns are i, so 32 lanes store 32 consecutive i of one j
-    const int64_t ib = i0 + wc + (lane % 32);
+    mfma_epilogue<WN>(acc, a, i0, j0, wr, wc, lane);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-direct variant (used for fp4): field tiles go from global memory
+// straight into LDS (global_load_lds_dwordx4: one wave instruction fills
+// 1 KB of LDS, lane l at byte 16 l), so no registers hold staged data and
+// the 128-byte tile fits the fp4 kernel without spills.  Two buffers: tile
+// kt+1 loads while tile kt is consumed.  Rows are kDmaMK bytes, unpadded;
+// 16-byte chunk c of row r sits at chunk position c ^ dma_swz(r).  Rows past
+// n_v load row n_v - 1 (their outputs are never stored).
+// Measured on the int8 planes the register-staged kernel above is faster
+// (it is kept for int8); on fp4 this one is.
+// ---------------------------------------------------------------------------
+constexpr int kDmaMK = 128;
+
+// Chunk swizzle of row r: for every chunk c, the 16-byte slots of any 8
+// consecutive rows are distinct modulo 128 bytes and those of any 16
+// consecutive rows distinct modulo 256 bytes, so fragment reads are free of
+// bank conflicts whether the LDS serves 8 or 16 lanes of a b128 read at once.
+// Rows r and r + 32 share a swizzle.
+__device__ __forceinline__ int dma_swz(int r) { return (r % 8) ^ ((r / 8) % 2); }
+
+// Tile hand-over between the waves of a workgroup: this wave's LDS reads are
+// done and all of its tile loads have landed, then the barrier.  The empty
+// asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void tile_sync() {
+    // vmcnt 0, expcnt unconstrained (7), lgkmcnt 0
+    __builtin_amdgcn_s_waitcnt(0x7 << 4);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int FMT, int WN>
+__global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_dma_kernel(MfmaArgs a) {
+    constexpr int MK = kDmaMK;
+    constexpr int kWaves = mfma_threads<WN>() / 64;
+    constexpr int R = MK / 16;                 // chunks per row
+    constexpr int RB = 1024 / MK;              // rows per wave instruction
+    constexpr int NBW = kMB / RB / kWaves;     // instructions per wave per operand per tile
+    constexpr int kStageBytes = kMB * MK;
+    static_assert(NBW >= 1 && kMB % (RB * kWaves) == 0, "stage split");
+    using AccT = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
+    __shared__ __attribute__((aligned(1024))) int8_t As[2 * kStageBytes];   // j rows
+    __shared__ __attribute__((aligned(1024))) int8_t Bs[2 * kStageBytes];   // i rows
+    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    if (t >= a.ntiles) return;
+    int64_t bi, bj;
+    grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
+    const int64_t i0 = bi * kMB, j0 = bj * kMB;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wr = (wave % 2) * 128;
+    const int wc = (wave / 2) * 32 * WN;
+    const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
+
+    AccT acc[4][WN];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t j = j0 + wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
-            if (j >= a.n_v) continue;
-            const double sj = a.s[j];
-            const int64_t base = j * (j - 1) / 2;
+        for (int n = 0; n < WN; ++n) acc[m][n] = (AccT){};
+
+    // per-lane source rows and chunk offsets of this wave's loads
+    const int8_t* srcA[NBW];
+    const int8_t* srcB[NBW];
 #pragma unroll
-            for (int n = 0; n < WN; ++n) {
-                const int64_t i = ib + n * 32;
-                if (i >= j) continue;
-                const int32_t num = (int32_t)acc[m][n][r];   // exact in either format
-                if (a.n2) a.n2[base + i] = num;
-                if (a.c2) {
-                    const double d = a.s[i] + sj;
-                    a.c2[base + i] = d > 0.0 ? (float)((2.0 * (double)num) / d) : 0.0f;
-                }
+    for (int u = 0; u < NBW; ++u) {
+        const int row = (wave + kWaves * u) * RB + lane / R;
+        const int c = (lane % R) ^ dma_swz(row);
+        const int64_t gj = j0 + row < a.n_v ? j0 + row : a.n_v - 1;
+        const int64_t gi = i0 + row < a.n_v ? i0 + row : a.n_v - 1;
+        srcA[u] = a.P + gj * a.kp + c * 16;
+        srcB[u] = a.P + gi * a.kp + c * 16;
+    }
+    auto issue = [&](int64_t kt, int buf) {
+        const int64_t k0 = kt * MK;
+#pragma unroll
+        for (int u = 0; u < NBW; ++u) {
+            const int blk = (wave + kWaves * u) * 1024;
+            __builtin_amdgcn_global_load_lds((const void*)(srcA[u] + k0),
+                                             (void*)(As + buf * kStageBytes + blk), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(srcB[u] + k0),
+                                             (void*)(Bs + buf * kStageBytes + blk), 16, 0, 0);
+        }
+    };
+
+    const int64_t nk = a.kp / MK;
+    issue(0, 0);
+    const int fr = lane % 32, hk = lane / 32;
+    const int sw = dma_swz(fr);   // swizzle of rows wr + m*32 + fr and wc + n*32 + fr
+    if (active) {
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int cur = (int)(kt & 1);
+            tile_sync();   // tile kt in LDS everywhere; tile kt-1 no longer read
+            if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
+            const int8_t* A = As + cur * kStageBytes;
+            const int8_t* B = Bs + cur * kStageBytes;
+#pragma unroll
+            for (int ks = 0; ks < MK / 32; ++ks) {
+                const int co = ((ks * 2 + hk) ^ sw) * 16;
+                v4i_t fa[4], fb[WN];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * MK + co);
+#pragma unroll
+                for (int n = 0; n < WN; ++n)
+                    fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * MK + co);
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < WN; ++n) {
+                        if constexpr (FMT == kFmtI8) {
+                            acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n],
+                                                                              acc[m][n], 0, 0, 0);
+                        } else {
+                            const v8i_t xa = {fa[m].x, fa[m].y, fa[m].z, fa[m].w, 0, 0, 0, 0};
+                            const v8i_t xb = {fb[n].x, fb[n].y, fb[n].z, fb[n].w, 0, 0, 0, 0};
+                            acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                xa, xb, acc[m][n], 4, 4, 0, 127, 0, 127);
+                        }
+                    }
             }
         }
+    } else {
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            tile_sync();
+            if (kt + 1 < nk) issue(kt + 1, (int)(kt & 1) ^ 1);
+        }
+        return;   // the last tile_sync waited for every load of this wave
     }
+
+    mfma_epilogue<WN>(acc, a, i0, j0, wr, wc, lane);
 }
 
 template <int FMT, int WN>
@@ -287,8 +429,12 @@ static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
     const int64_t T = nb * (nb + 1) / 2;
     MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T};
     const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL((ps_mfma2_kernel<FMT, WN>), dim3((unsigned)grid),
-                       dim3(mfma_threads<WN>()), 0, st, a);
+    if constexpr (FMT == kFmtF4 && WN == 2)
+        hipLaunchKernelGGL((ps_mfma2_dma_kernel<FMT, WN>), dim3((unsigned)grid),
+                           dim3(mfma_threads<WN>()), 0, st, a);
+    else
+        hipLaunchKernelGGL((ps_mfma2_kernel<FMT, WN>), dim3((unsigned)grid),
+                           dim3(mfma_threads<WN>()), 0, st, a);
     return hipGetLastError();
 }
 
