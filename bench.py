@@ -154,13 +154,13 @@ def cpu_baseline_triples(V, n_f, seconds, seed=123):
 # the sources are unchanged.
 CSRC = os.path.join(ROOT, "paper_1705_08210_amd", "csrc")
 _VALU_SOURCES = ["ps_internal.h", "mgemm_core.h", "mgemm_kernels.h", "mg_common.hip",
-                 "mg_f32.hip", "mg_f16.hip", "mg_u8.hip", "ps_api.hip"]
+                 "mg_f32.hip", "mg_f16.hip", "mg_u8.hip", "policy.hip"]
 KERNEL_SOURCES = {
     "ps_mg2_kernel": _VALU_SOURCES,
     "ps_mg3_kernel": _VALU_SOURCES,
     "ps_mgb_kernel": _VALU_SOURCES,
-    "ps_mfma2_kernel": ["ps_internal.h", "mfma.hip", "ps_api.hip"],
-    "ps_mfma2_dma_kernel": ["ps_internal.h", "mfma.hip", "ps_api.hip"],
+    "ps_mfma2_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
+    "ps_mfma2_dma_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
 }
 PROFILES = os.path.join(ROOT, "profiles")
 GIB = 1 << 30

@@ -25,9 +25,9 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libps.so")
 
-SOURCES = ["ps_api.hip", "mg_common.hip", "mg_f32.hip", "mg_f16.hip", "mg_u8.hip",
+SOURCES = ["ps_api.hip", "policy.hip", "mg_common.hip", "mg_f32.hip", "mg_f16.hip", "mg_u8.hip",
            "mfma.hip"]
-HEADERS = ["ps_internal.h", "mgemm_core.h", "mgemm_kernels.h", "mfma_core.h"]
+HEADERS = ["ps_internal.h", "mgemm_core.h", "mgemm_kernels.h"]
 
 ARCH = os.environ.get("PS_OFFLOAD_ARCH", "gfx950")
 

@@ -1,0 +1,146 @@
+// policy.hip -- launch policy of the tile kernels: the tile configurations,
+// the tuning table that overrides the defaults, the accumulation mode and
+// field-chunk split, and the path choice.  The kernels' work and traffic
+// follow from these choices and from the kernel sources alone.
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "ps_internal.h"
+
+namespace ps {
+
+const TileCfg kValuCfgs[kNumValuCfgs] = {
+    {8, 8, 32},   // 128 x 128 output tile, 32-word field tile
+    {4, 4, 32},   // 64 x 64
+    {8, 8, 16},   // 128 x 128, 16-word field tile
+};
+
+// ---------------------------------------------------------------------------
+// Tuning table.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    int32_t dt, way, path;
+    int64_t nf_lo, nf_hi, nv_lo, nv_hi;
+    int32_t idx;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+
+static int default_cfg(int32_t way, int64_t n_v) {
+    // 128x128 output tiles with 16-word field tiles (measured fastest on the
+    // large problems: 126 registers, 4 waves per SIMD) once the tiles fill
+    // the chip a few times over; 64x64 tiles below that
+    if (way == 2) return tri_tiles(n_v, 128) >= 1024 ? 2 : 1;
+    return n_v >= 256 ? 2 : 1;
+}
+
+int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
+                      const ps_opts* o) {
+    if (o && o->tile > 0) return o->tile - 1;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+            if (it->dt == dt && it->way == way && it->path == path && n_f >= it->nf_lo &&
+                n_f < it->nf_hi && n_v >= it->nv_lo && n_v < it->nv_hi)
+                return it->idx;
+    }
+    return default_cfg(way, n_v);
+}
+
+int choose_acc(int64_t n_f, const ps_opts* o) {
+    const int a = o ? o->acc : PS_ACC_AUTO;
+    if (a == PS_ACC_PLAIN || a == PS_ACC_BLOCKED) return a;
+    return n_f > kChunkFields ? PS_ACC_BLOCKED : PS_ACC_PLAIN;
+}
+
+// Number of field chunks of the blocked (split) accumulation; 1 = no split.
+// kChunkFields is a multiple of every configuration's field-tile depth.
+int32_t split_chunks(int32_t dt, int64_t n_f, int acc) {
+    if (dt == PS_U8 || acc != PS_ACC_BLOCKED) return 1;
+    const int64_t n = ceil_div(n_f, kChunkFields);
+    return n > 1 ? (int32_t)n : 1;
+}
+
+int64_t chunk_tiles(int32_t dt, int cfg) {
+    return kChunkFields / ((int64_t)kValuCfgs[cfg].bkw * (4 / elem_size(dt)));
+}
+
+// Field-chunk plan of a 2-way launch (see Split in ps_internal.h).
+Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o) {
+    Split sp{split_chunks(dt, n_f, choose_acc(n_f, o)), chunk_tiles(dt, cfg)};
+    const int acc_req = o ? o->acc : PS_ACC_AUTO;
+    if (dt == PS_U8 || acc_req != PS_ACC_AUTO || n_v < 2) return sp;
+    const int64_t ftiles = ceil_div(n_f * elem_size(dt), (int64_t)kValuCfgs[cfg].bkw * 4);
+    const int64_t tiles = tri_tiles(n_v, kValuCfgs[cfg].bm());
+    if (tiles * sp.nchunks >= kMinItems) return sp;
+    const int64_t want = std::min(ceil_div(kMinItems, tiles), ftiles / kMinChunkTiles);
+    if (want > sp.nchunks) {
+        sp.chunk_tiles = ceil_div(ftiles, want);
+        sp.nchunks = (int32_t)ceil_div(ftiles, sp.chunk_tiles);
+    }
+    return sp;
+}
+
+// Tile configuration of a batched launch: a tuning entry registered for
+// way 0 and the field count of the largest problem, else 128x128 tiles with
+// 16-word field tiles.
+int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o) {
+    if (o && o->tile > 0) return o->tile - 1;
+    // representative shape: the field count of the largest problem by work
+    int64_t best = -1, nf = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t w = p[i].n_f * p[i].n_v * p[i].n_v;
+        if (w > best) best = w, nf = p[i].n_f;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+        if (it->dt == dt && it->way == 0 && nf >= it->nf_lo && nf < it->nf_hi)
+            return it->idx;
+    return 2;
+}
+
+bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4; }
+
+int choose_path(int32_t dt, const ps_opts* o) {
+    const int p = o ? o->path : PS_PATH_AUTO;
+    if (p == PS_PATH_VALU || p == PS_PATH_MFMA || p == PS_PATH_MFMA_FP4) return p;
+    if (dt == PS_U8 && o && o->levels >= 1 && o->levels <= 15) return PS_PATH_MFMA;
+    return PS_PATH_VALU;
+}
+
+}  // namespace ps
+
+using namespace ps;
+
+extern "C" {
+
+int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx, int32_t* bm,
+                       int32_t* bn, int32_t* bk) {
+    if (elem_size(dtype) == 0 || (way != 2 && way != 3) || is_mfma(path)) return 0;
+    if (idx >= 0 && idx < kNumValuCfgs) {
+        const int fpw = 4 / elem_size(dtype);  // fields per 32-bit word
+        if (bm) *bm = kValuCfgs[idx].bm();
+        if (bn) *bn = kValuCfgs[idx].bn();
+        if (bk) *bk = kValuCfgs[idx].bkw * fpw;
+    }
+    return kNumValuCfgs;
+}
+
+ps_status ps_tune_register(int32_t dtype, int32_t way, int32_t path, int64_t nf_lo,
+                           int64_t nf_hi, int64_t nv_lo, int64_t nv_hi, int32_t idx) {
+    if (elem_size(dtype) == 0) return fail(PS_ERR_DTYPE, "unknown dtype %d", dtype);
+    if (way != 0 && way != 2 && way != 3)
+        return fail(PS_ERR_ARG, "way must be 2, 3 (or 0 for batched)");
+    if (idx < 0 || idx >= kNumValuCfgs) return fail(PS_ERR_ARG, "tile index %d out of range", idx);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.push_back(TuneEntry{dtype, way, path, nf_lo, nf_hi, nv_lo, nv_hi, idx});
+    return PS_OK;
+}
+
+void ps_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+}  // extern "C"

@@ -83,6 +83,27 @@ constexpr int64_t kChunkFields = 4096;
 constexpr int kNumValuCfgs = 3;
 extern const TileCfg kValuCfgs[kNumValuCfgs];
 
+// Launch policy (policy.hip).
+// Field-chunk plan of a 2-way launch.  Blocked accumulation splits at
+// kChunkFields; with opts.acc = AUTO a small triangle (fewer work items than
+// kMinItems) is split further, down to kMinChunkTiles field tiles per chunk,
+// so that enough workgroups run.
+struct Split {
+    int32_t nchunks;
+    int64_t chunk_tiles;
+};
+constexpr int64_t kMinItems = 2048;      // ~8 workgroups per CU
+constexpr int64_t kMinChunkTiles = 4;
+int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
+               const ps_opts* o);
+int choose_acc(int64_t n_f, const ps_opts* o);
+int32_t split_chunks(int32_t dt, int64_t n_f, int acc);
+int64_t chunk_tiles(int32_t dt, int cfg);
+Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o);
+bool is_mfma(int path);
+int choose_path(int32_t dt, const ps_opts* o);
+int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o);
+
 // Arguments of one 2-way launch over the upper-triangle tile list.
 struct Mg2Launch {
     const void* V;
