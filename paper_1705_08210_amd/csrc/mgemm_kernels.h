@@ -202,13 +202,24 @@ hipError_t go_c3_finish(const Mg3Launch& a, hipStream_t st) {
 // a persistent loop over an atomic work counter measured the same schedule
 // but needed ~70 more registers (2 instead of 4 waves per SIMD).
 // ---------------------------------------------------------------------------
+// Block index -> position in an ordered work list, for a grid that is a
+// multiple of kXcds * kRun: blocks are dealt to the XCDs round-robin, so
+// XCD x receives positions in runs of kRun consecutive entries while all
+// XCDs advance through the list together (its order is kept to within
+// kXcds * kRun entries).
+constexpr int64_t kRun = 16;   // measured: 1.5x less L2-miss traffic than kRun = 1
+__device__ __forceinline__ int64_t run_remap(int64_t b) {
+    const int64_t x = b % kXcds, r = b / kXcds;
+    return (r / kRun) * (kXcds * kRun) + x * kRun + r % kRun;
+}
+
 template <int DT, int TM, int BKW>
 __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchLaunch a) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
     __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
-    const int64_t t = blockIdx.x;
+    const int64_t t = run_remap(blockIdx.x);
     if (t >= a.ntiles) return;
     const int wave = threadIdx.x / 64;
     const BatchTile bt = a.tiles[t];
@@ -257,7 +268,8 @@ hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
 template <int DT, int TM, int BKW>
 hipError_t go_mgb(const MgBatchLaunch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((ps_mgb_kernel<DT, TM, BKW>), dim3((unsigned)a.ntiles), dim3(kThreads), 0,
+    const int64_t grid = ceil_div(a.ntiles, kXcds * kRun) * (kXcds * kRun);
+    hipLaunchKernelGGL((ps_mgb_kernel<DT, TM, BKW>), dim3((unsigned)grid), dim3(kThreads), 0,
                        st, a);
     return hipGetLastError();
 }

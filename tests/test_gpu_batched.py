@@ -35,8 +35,8 @@ def test_batched_matches_per_problem_and_oracle(tile):
     Vs = small_batch(1)
     announce(f"batched 12 problems tile={tile}")
     Vd = [to_dev(V) for V in Vs]
-    # same accumulation on both sides (blocked means an in-register partial
-    # in the batched kernel but a field-chunk split in ps2_compute)
+    # same accumulation on both sides (with acc=auto a small single problem
+    # may be split over field chunks for parallelism, which the batch is not)
     outs = ps.ps2_batched(Vd, tile=tile, want_n2=True, acc="plain")
     for V, Vx, (c2, n2, _) in zip(Vs, Vd, outs):
         a, an2 = ps.ps2(Vx, tile=tile, want_n2=True, acc="plain")
