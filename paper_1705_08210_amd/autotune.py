@@ -32,7 +32,7 @@ NV_BUCKETS = [(0, 1024), (1024, 4096), (4096, 1 << 40)]
 REPS = {
     2: {(0, 0): (1024, 512), (0, 1): (1024, 2048), (0, 2): (1024, 8192),
         (1, 0): (4096, 512), (1, 1): (4096, 2048), (1, 2): (4096, 8192),
-        (2, 0): (16384, 512), (2, 1): (16384, 2048), (2, 2): (16384, 6144)},
+        (2, 0): (16384, 512), (2, 1): (16384, 2048), (2, 2): (16384, 8192)},
     3: {(0, 0): (1024, 256), (1, 0): (4096, 384), (2, 0): (12000, 256),
         (0, 1): (1024, 1024), (1, 1): (4096, 1024), (2, 1): (12000, 1024)},
 }
@@ -63,12 +63,45 @@ def _time(fn, reps):
     return best
 
 
-def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3), reps=3, quick=False, log=print):
+def _batch_inputs(dt, count=24, seed=0):
+    """A representative uneven batch: shapes log-uniform like the batched
+    workload (n_v in [500, 8000], n_f in [1000, 20000]), scaled down in count."""
+    g = np.random.default_rng(seed)
+    Vs = []
+    for p in range(count):
+        n_v = int(math.exp(g.uniform(math.log(500), math.log(8000))))
+        n_f = int(math.exp(g.uniform(math.log(1000), math.log(20000))))
+        Vs.append(_input(n_v, n_f, dt, seed=seed + p))
+    return Vs
+
+
+def tune_batched(dname, reps=3, log=print):
+    """One entry for batched launches (way 0, any shape): the configuration
+    that runs a representative uneven batch fastest as one launch."""
+    dt = DTYPES[dname]
+    Vs = _batch_inputs(dt)
+    outs = ps._batch_outputs(Vs)
+    ncfg = len(ps.tile_configs(dt, 2))
+    times = [_time(lambda i=idx: ps.ps2_batched(Vs, outs=outs, tile=i + 1), reps)
+             for idx in range(ncfg)]
+    best = int(np.argmin(times))
+    rec = {"dtype": dname, "way": 0, "nf": [0, 1 << 40], "nv": [0, 1 << 40],
+           "shape": [len(Vs), "uneven"], "tile": best, "ms": [round(t, 4) for t in times]}
+    log(json.dumps(rec))
+    del Vs, outs
+    torch.cuda.empty_cache()
+    return rec
+
+
+def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3, 0), reps=3, quick=False, log=print):
     out = []
+    for dname in dtypes:
+        if 0 in ways:
+            out.append(tune_batched(dname, reps, log))
     for dname in dtypes:
         dt = DTYPES[dname]
         ncfg = len(ps.tile_configs(dt, 2))
-        for way in ways:
+        for way in (w for w in ways if w != 0):
             for (fb, vb), (n_f, n_v) in REPS[way].items():
                 if quick and (fb, vb) not in ((1, 1), (2, 2), (1, 0)):
                     continue
