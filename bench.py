@@ -12,6 +12,7 @@ Workloads (seeded, synthetic; shapes of the paper's problems):
                      nonzeros Exponential(mean 2)            (default)
   uniform_1024x256   2-way, FP32 U[0,1)
   levels_8192x32768  2-way, uint8 levels {0..3}
+  binary_8192x32768  2-way, uint8 {0, 1} (the Sorensen case; --path bits)
   sparse_4096x1024   3-way, FP32 U[0,1) with 50% zeros
   batched_64_uneven  64 independent 2-way problems in one captured launch
 
@@ -34,8 +35,9 @@ if ROOT not in sys.path:
 
 # MI355X: 256 CUs at 2.4 GHz.  FP32 vector 157.3 TFLOP/s = 128 FP32 lanes per
 # clock per CU (an FMA, a min or an add is one lane-op); measured: v_min_f32 and
-# v_add_f32 issue at that rate, while v_pk_min_f16, v_dot2c_f32_f16 and
-# v_sad_u8 issue at 64 lanes per clock per CU.
+# v_add_f32 issue at that rate, while v_pk_min_f16, v_dot2c_f32_f16, v_sad_u8
+# and the v_and_b32 + v_bcnt_u32_b32 pair of the bits path issue at 64 lanes
+# per clock per CU.
 FP32_LANE_OPS_TOPS = 256 * 128 * 2.4e9 / 1e12   # 78.64
 HALF_RATE_OPS_TOPS = 256 * 64 * 2.4e9 / 1e12    # 39.32
 INT8_MFMA_PEAK_TOPS = 5000.0                    # dense int8 matrix-core ops / s (2 per MAC)
@@ -51,7 +53,8 @@ def parse(argv=None):
     ap.add_argument("--workload", default="gwas_20000x16384")
     ap.add_argument("--storage", default="auto", choices=["auto", "f32", "f16"])
     ap.add_argument("--acc", default="auto", choices=["auto", "plain", "blocked"])
-    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "mfma_fp4"])
+    ap.add_argument("--path", default="auto",
+                    choices=["auto", "valu", "mfma", "mfma_fp4", "bits"])
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
@@ -301,8 +304,8 @@ def counter_summary(d, kernel, commands):
 def traffic_key(args):
     """Workload and operand type of a run: names its traffic file."""
     wl = args.workload
-    if wl == "levels_8192x32768":
-        return wl + ("_fp4" if args.path == "mfma_fp4" else "_u8")
+    if wl in ("levels_8192x32768", "binary_8192x32768"):
+        return wl + {"mfma_fp4": "_fp4", "bits": "_bits"}.get(args.path, "_u8")
     return wl + ("_f16" if args.storage == "f16" else "_f32")
 
 
@@ -338,7 +341,8 @@ def main(argv=None):
     timer = Timer(torch)
     extra = {}
 
-    if wl in ("gwas_20000x16384", "uniform_1024x256", "levels_8192x32768"):
+    if wl in ("gwas_20000x16384", "uniform_1024x256", "levels_8192x32768",
+              "binary_8192x32768"):
         V = workloads.WORKLOADS[wl](0)
         if args.storage == "f16" and V.dtype == np.float32:
             V = workloads.to_f16(V)
@@ -360,7 +364,10 @@ def main(argv=None):
         cmp = n_f * m
         use_mfma = V.dtype == np.uint8 and (args.path == "mfma" or
                                             (args.path == "auto" and 1 <= levels <= 15))
-        if V.dtype == np.uint8 and args.path == "mfma_fp4":   # e2m1 planes, FP32 sums
+        if V.dtype == np.uint8 and args.path == "bits":   # v_and + v_bcnt per 32 comparisons
+            dtype, bound, ops_per_cmp, peak = "b1", "alu", 2.0 / 32, HALF_RATE_OPS_TOPS
+            kernel = "ps_mg2_kernel"
+        elif V.dtype == np.uint8 and args.path == "mfma_fp4":   # e2m1 planes, FP32 sums
             dtype, bound, ops_per_cmp, peak = "fp4", "mfma", 2.0 * levels, FP4_MFMA_PEAK_TOPS
             kernel = "ps_mfma2_dma_kernel"
         elif use_mfma:   # thermometer planes: `levels` int8 MACs (2 ops) per comparison

@@ -79,8 +79,8 @@ typedef enum {
                             into chunks of 4096, each chunk is summed in FP32
                             and the chunk sums are added in FP64 in a fixed
                             order (deterministic; needs workspace for the
-                            chunk partials).  Batched calls: an FP32 partial
-                            per field tile added to the running FP32 sum. */
+                            chunk partials; batched calls split the same way
+                            per problem). */
 } ps_acc;
 
 /* Compute path for the pair numerators. */
@@ -90,16 +90,24 @@ typedef enum {
     PS_PATH_MFMA = 2,    /* U8 only: min(a,b) = sum_{t=1..levels} [a>=t][b>=t],
                             an exact int8 matrix-core contraction with int32
                             accumulation; needs levels >= max(V) */
-    PS_PATH_MFMA_FP4 = 3 /* U8 only: the same 0/1 planes as FP4 (e2m1) operands
+    PS_PATH_MFMA_FP4 = 3, /* U8 only: the same 0/1 planes as FP4 (e2m1) operands
                             of the scaled matrix-core instruction, FP32
                             accumulation (exact: sums are integers < 2^24,
                             needs levels * n_f < 2^24); needs levels >= max(V) */
+    PS_PATH_BITS = 4     /* U8 binary data, values in {0, 1} (opts.levels = 1):
+                            the Sorensen special case of Section 2.3, where min
+                            is AND.  The fields are packed 32 to a word and a
+                            word pair costs an AND and a population count;
+                            exact integer sums.  2-way and 3-way.  Values above
+                            1 are outside this path's domain (results
+                            unspecified). */
 } ps_path;
 
 typedef struct {
     int32_t acc;      /* ps_acc */
     int32_t path;     /* ps_path */
-    int32_t levels;   /* PS_U8 + MFMA: upper bound on the values of V, 1..127 */
+    int32_t levels;   /* PS_U8 + MFMA: upper bound on the values of V, 1..127;
+                         PS_U8 + BITS: must be 1 */
     int32_t tile;     /* 0 = library choice (tuning table); else 1 + index
                          into the tile configurations of ps_tile_config */
 } ps_opts;
@@ -136,7 +144,7 @@ size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
  *           into the workspace
  *   c2      device float, n_v(n_v-1)/2, colex layout; may be NULL if n2 given
  *   n2      device, optional raw numerators n2(i,j) in colex layout: float
- *           for PS_F32/PS_F16, int32 for PS_U8; may be NULL
+ *           for PS_F32/PS_F16, int32 for PS_U8 (every path); may be NULL
  *   workspace / ws_bytes   device scratch, at least ps2_workspace_size()
  *   opts    may be NULL (all defaults)
  * Each c2 is formed in FP64 from the numerator and FP64 sums, then rounded
@@ -164,6 +172,8 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
  *   n2     device pair numerators in colex layout (float for F32/F16, int32
  *          for U8, as written by ps2_compute for the same V), or NULL to
  *          compute them into the workspace
+ *   opts   path VALU (default) or BITS (binary U8 data, X_j = V AND v_j);
+ *          the MFMA paths give PS_ERR_UNSUPPORTED
  *   c3     device float; receives the triples of [j_begin, j_end) packed in
  *          j-slab order starting at offset 0 (i.e. at global index
  *          off(j_begin))

@@ -6,6 +6,7 @@
 //   PS_F16: op = packed FP16 min, summed by a dot product with (1, 1) into FP32
 //   PS_U8 : op = |a - b| summed four bytes at a time (v_sad_u8); the pair
 //           numerator follows from min(a,b) = (a + b - |a-b|) / 2.
+//   PS_B1 : binary fields, 32 per word; op = popcount(a AND b).
 // For the 3-way slices (Section 3.2) the A operand is X_j = min(V, v_j),
 // formed while the field tile is staged into LDS.
 //
@@ -79,6 +80,17 @@ template <> struct Ops<PS_U8> {
                                                __builtin_bit_cast(u16x2_t, (b >> 8) & m));
         return __builtin_bit_cast(uint32_t, lo) | (__builtin_bit_cast(uint32_t, hi) << 8);
     }
+};
+
+// Binary fields packed 32 to a word (the BITS path): min is AND, and a word
+// pair contributes the population count of its AND (v_and + v_bcnt).
+template <> struct Ops<PS_B1> {
+    using Acc = uint32_t;
+    static constexpr int kEsz = 4;   // the kernels' "element" is one packed word
+    __device__ __forceinline__ static uint32_t step(uint32_t acc, uint32_t a, uint32_t b) {
+        return acc + (uint32_t)__builtin_popcount(a & b);
+    }
+    __device__ __forceinline__ static uint32_t xmin(uint32_t a, uint32_t b) { return a & b; }
 };
 
 // ---------------------------------------------------------------------------
@@ -302,6 +314,9 @@ __device__ __forceinline__ void epilogue2(const typename Ops<DT>::Acc (&acc)[TM]
                 const int64_t v = ((int64_t)si + (int64_t)sc[c] - (int64_t)acc[r][c]) / 2;
                 num = (double)v;
                 if (n2) ((int32_t*)n2)[idx] = (int32_t)v;
+            } else if constexpr (DT == PS_B1) {
+                num = (double)acc[r][c];
+                if (n2) ((int32_t*)n2)[idx] = (int32_t)acc[r][c];
             } else {
                 num = (double)acc[r][c];
                 if (n2) ((float*)n2)[idx] = acc[r][c];

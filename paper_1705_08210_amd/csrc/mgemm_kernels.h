@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
 // ---------------------------------------------------------------------------
 
 // 3-way, first half of the epilogue: the raw slice sums (n3' for the
-// floating types, sum |min(v_i,v_j) - v_k| for uint8) are stored as 32-bit
+// floating and binary types, sum |min(v_i,v_j) - v_k| for uint8) are stored as 32-bit
 // patterns at the triple's packed index; ps_c3_finish_kernel turns them into
 // c3 in place.  Keeping Eq. 1 out of the tile kernel keeps its register
 // footprint (and so its occupancy) that of the bare min-product.
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
 // c3 = (3 n3) / (2 d3) in FP64, rounded once to FP32.
 template <int DT>
 __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
-    using N2T = typename std::conditional<DT == PS_U8, int32_t, float>::type;
+    using N2T = typename std::conditional<DT == PS_U8 || DT == PS_B1, int32_t, float>::type;
     const int64_t j = a.j_begin + blockIdx.x;
     if (j >= a.j_end) return;
     const N2T* N2 = (const N2T*)a.n2;
@@ -174,6 +174,8 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
             // sum_q min(x, v_k) = (sum x + s_k - sum |x - v_k|) / 2 with
             // x = min(v_i, v_j), so sum x = n2(i, j)
             n3p = (double)(((int64_t)nij + (int64_t)sk - (int64_t)raw) / 2);
+        } else if constexpr (DT == PS_B1) {
+            n3p = (double)raw;   // popcount(v_i AND v_j AND v_k), never split
         } else if (a.nchunks > 1) {  // chunks of the field split, in FP64
             n3p = 0.0;
             for (int c = 0; c < a.nchunks; ++c) n3p += (double)a.partial[c * stage + base + t];

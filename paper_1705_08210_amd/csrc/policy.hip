@@ -104,7 +104,8 @@ bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4
 
 int choose_path(int32_t dt, const ps_opts* o) {
     const int p = o ? o->path : PS_PATH_AUTO;
-    if (p == PS_PATH_VALU || p == PS_PATH_MFMA || p == PS_PATH_MFMA_FP4) return p;
+    if (p == PS_PATH_VALU || p == PS_PATH_MFMA || p == PS_PATH_MFMA_FP4 || p == PS_PATH_BITS)
+        return p;
     if (dt == PS_U8 && o && o->levels >= 1 && o->levels <= 15) return PS_PATH_MFMA;
     return PS_PATH_VALU;
 }

@@ -40,7 +40,7 @@ static ps_status check_opts(const ps_opts* o) {
     if (!o) return PS_OK;
     if (o->acc < PS_ACC_AUTO || o->acc > PS_ACC_BLOCKED)
         return fail(PS_ERR_ARG, "opts.acc = %d is not a ps_acc value", o->acc);
-    if (o->path < PS_PATH_AUTO || o->path > PS_PATH_MFMA_FP4)
+    if (o->path < PS_PATH_AUTO || o->path > PS_PATH_BITS)
         return fail(PS_ERR_ARG, "opts.path = %d is not a ps_path value", o->path);
     if (o->tile < 0 || o->tile > kNumValuCfgs)
         return fail(PS_ERR_ARG, "opts.tile = %d out of range [0, %d]", o->tile, kNumValuCfgs);
@@ -82,6 +82,7 @@ static hipError_t launch_mg2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
     switch (dt) {
     case PS_F32: return launch_mg2_f32(a, st);
     case PS_F16: return launch_mg2_f16(a, st);
+    case PS_B1: return launch_mg2_b1(a, st);
     default: return launch_mg2_u8(a, st);
     }
 }
@@ -90,8 +91,25 @@ static hipError_t launch_mg3(int32_t dt, const Mg3Launch& a, hipStream_t st) {
     switch (dt) {
     case PS_F32: return launch_mg3_f32(a, st);
     case PS_F16: return launch_mg3_f16(a, st);
+    case PS_B1: return launch_mg3_b1(a, st);
     default: return launch_mg3_u8(a, st);
     }
+}
+
+// The BITS path takes binary uint8 data and says so with opts.levels = 1.
+static ps_status check_bits(int32_t dtype, const ps_opts* o) {
+    if (!o || o->path != PS_PATH_BITS) return PS_OK;
+    if (dtype != PS_U8) return fail(PS_ERR_UNSUPPORTED, "the BITS path needs PS_U8 data");
+    if (o->levels != 1)
+        return fail(PS_ERR_ARG, "the BITS path needs binary data: opts.levels = 1, got %d",
+                    o->levels);
+    return PS_OK;
+}
+
+static bool is_bits(const ps_opts* o) { return o && o->path == PS_PATH_BITS; }
+
+static size_t bits_bytes(int64_t n_f, int64_t n_v) {
+    return (size_t)n_v * (size_t)bits_row_words(n_f) * sizeof(uint32_t);
 }
 
 static hipError_t launch_mgb(int32_t dt, const MgBatchLaunch& a, hipStream_t st) {
@@ -114,6 +132,8 @@ static size_t ws2_layout(int32_t dt, int64_t n_f, int64_t n_v, int32_t s_given, 
     if (is_mfma(path) && dt == PS_U8)
         pl = (int8_t*)c.take(
             mfma_workspace_bytes(n_f, n_v, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0));
+    else if (path == PS_PATH_BITS && dt == PS_U8)   // the packed bits
+        pl = (int8_t*)c.take(bits_bytes(n_f, n_v));
     else if (nchunks > 1)
         part = (float*)c.take((size_t)nchunks * (size_t)(n_v * (n_v - 1) / 2) * sizeof(float));
     if (s_ws) *s_ws = s;
@@ -159,8 +179,10 @@ size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
                           const ps_opts* opts) {
     if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
     const int path = choose_path(dtype, opts);
-    const Split sp = plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts),
-                                opts);
+    const Split sp = path == PS_PATH_BITS
+                         ? Split{1, 0}
+                         : plan_split(dtype, n_f, n_v,
+                                      choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
     return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0, sp.nchunks,
                       nullptr, nullptr, nullptr, nullptr);
 }
@@ -175,6 +197,7 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (!c2 && !n2) return fail(PS_ERR_ARG, "both c2 and n2 are NULL");
     if (!aligned(c2, 4) || !aligned(n2, 4) || !aligned(s, 8))
         return fail(PS_ERR_ARG, "misaligned output or sums pointer");
+    if ((st = check_bits(dtype, opts)) != PS_OK) return st;
     const int path = choose_path(dtype, opts);
     if (is_mfma(path) && dtype != PS_U8)
         return fail(PS_ERR_UNSUPPORTED, "the MFMA path needs PS_U8 data");
@@ -191,8 +214,10 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
     float* partial = nullptr;
-    const int cfg = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
-    const Split sp = plan_split(dtype, n_f, n_v, cfg, opts);
+    const bool bits = path == PS_PATH_BITS;
+    const int cfg = bits ? choose_cfg(PS_B1, 2, PS_PATH_BITS, n_f, n_v, opts)
+                         : choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
+    const Split sp = bits ? Split{1, 0} : plan_split(dtype, n_f, n_v, cfg, opts);
     const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, sp.nchunks,
                                    workspace, &s_ws, &planes, &partial);
     if (ws_bytes < need || (need && !workspace))
@@ -213,6 +238,14 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");
         return e == hipSuccess ? PS_OK : hip_fail(e, "mfma launch");
     }
+    if (bits) {   // pack, then the min-product on words (zero pad words add nothing)
+        const int64_t W = bits_row_words(n_f);
+        e = launch_pack_bits((const uint8_t*)V, n_f, n_v, ld, (uint32_t*)planes, stream);
+        if (e != hipSuccess) return hip_fail(e, "bit packing launch");
+        Mg2Launch a{planes, W, n_v, W, s, c2, n2, cfg, 1, 0, nullptr};
+        e = launch_mg2(PS_B1, a, stream);
+        return e == hipSuccess ? PS_OK : hip_fail(e, "2-way bits launch");
+    }
     Mg2Launch a{V, n_f, n_v, ld, s, c2, n2, cfg, sp.nchunks, sp.chunk_tiles, partial};
     e = launch_mg2(dtype, a, stream);
     if (e == hipSuccess && sp.nchunks > 1) e = launch_finish2(dtype, a, stream);
@@ -222,12 +255,15 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
 // The field-split partials of the pair prepass and of the slices run one
 // after the other on the stream and share one region.
 static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t nchunks2,
-                         int32_t nchunks3, int64_t stage, void* ws, double** s_ws,
-                         void** n2_ws, int64_t** prefix, float** partial) {
+                         int32_t nchunks3, int64_t stage, size_t packed_bytes, void* ws,
+                         double** s_ws, void** n2_ws, int64_t** prefix, float** partial,
+                         uint32_t** packed) {
     Carver c(ws);
     double* s = nullptr;
     void* n2 = nullptr;
     float* part = nullptr;
+    if (packed) *packed = packed_bytes ? (uint32_t*)c.take(packed_bytes) : nullptr;
+    else if (packed_bytes) c.take(packed_bytes);
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
     if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * 4);
     int64_t* pre = (int64_t*)c.take((size_t)(n_v + 1) * sizeof(int64_t));
@@ -249,11 +285,14 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (j_begin < 1) j_begin = 1;
     if (j_end > n_v - 1) j_end = n_v - 1;
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
+    if (is_bits(opts))
+        return ws3_layout(n_v, s_given, n2_given, 1, 1, stage, bits_bytes(n_f, n_v), nullptr,
+                          nullptr, nullptr, nullptr, nullptr, nullptr);
     const Split sp2 =
         plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
     return ws3_layout(n_v, s_given, n2_given, sp2.nchunks,
-                      split_chunks(dtype, n_f, choose_acc(n_f, opts)), stage, nullptr, nullptr,
-                      nullptr, nullptr, nullptr);
+                      split_chunks(dtype, n_f, choose_acc(n_f, opts)), stage, 0, nullptr, nullptr,
+                      nullptr, nullptr, nullptr, nullptr);
 }
 
 int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end) {
@@ -269,7 +308,8 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
     if (opts && is_mfma(opts->path))
-        return fail(PS_ERR_UNSUPPORTED, "3-way runs on the VALU path only");
+        return fail(PS_ERR_UNSUPPORTED, "3-way runs on the VALU and BITS paths only");
+    if ((st = check_bits(dtype, opts)) != PS_OK) return st;
     if (n_v < 3) return PS_OK;
     if (j_begin < 1 || j_end > n_v - 1 || j_begin > j_end)
         return fail(PS_ERR_ARG, "need 1 <= j_begin <= j_end <= n_v-1, got [%lld, %lld)",
@@ -282,12 +322,16 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     void* n2_ws = nullptr;
     int64_t* prefix = nullptr;
     float* partial = nullptr;
-    const int cfg2 = choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
-    const Split sp2 = plan_split(dtype, n_f, n_v, cfg2, opts);   // as ps2_compute would
-    const int32_t nchunks = split_chunks(dtype, n_f, choose_acc(n_f, opts));
+    const bool bits = is_bits(opts);
+    const int32_t kdt = bits ? PS_B1 : dtype;   // operand type of the kernels
+    const int cfg2 = choose_cfg(kdt, 2, bits ? PS_PATH_BITS : PS_PATH_VALU, n_f, n_v, opts);
+    const Split sp2 = bits ? Split{1, 0} : plan_split(dtype, n_f, n_v, cfg2, opts);
+    const int32_t nchunks = bits ? 1 : split_chunks(dtype, n_f, choose_acc(n_f, opts));
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
+    uint32_t* packed = nullptr;
     const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, sp2.nchunks, nchunks, stage,
-                                   workspace, &s_ws, &n2_ws, &prefix, &partial);
+                                   bits ? bits_bytes(n_f, n_v) : 0, workspace, &s_ws, &n2_ws,
+                                   &prefix, &partial, &packed);
     if (ws_bytes < need || !workspace)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
     if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
@@ -297,21 +341,30 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         if (e != hipSuccess) return hip_fail(e, "sums launch");
         s = s_ws;
     }
+    // the kernels' operand: V itself, or its packed bits (words as elements)
+    const void* KV = V;
+    int64_t kn_f = n_f, kld = ld;
+    if (bits) {
+        e = launch_pack_bits((const uint8_t*)V, n_f, n_v, ld, packed, stream);
+        if (e != hipSuccess) return hip_fail(e, "bit packing launch");
+        KV = packed;
+        kn_f = kld = bits_row_words(n_f);
+    }
     if (!n2) {  // the pair numerators of Eq. 1 (the 2-way mGEMM prepass)
-        Mg2Launch a{V, n_f, n_v, ld, s, nullptr, n2_ws, cfg2, sp2.nchunks, sp2.chunk_tiles,
+        Mg2Launch a{KV, kn_f, n_v, kld, s, nullptr, n2_ws, cfg2, sp2.nchunks, sp2.chunk_tiles,
                     partial};
-        e = launch_mg2(dtype, a, stream);
+        e = launch_mg2(kdt, a, stream);
         if (e == hipSuccess && sp2.nchunks > 1) e = launch_finish2(dtype, a, stream);
         if (e != hipSuccess) return hip_fail(e, "3-way numerator prepass launch");
         n2 = n2_ws;
     }
-    const int cfg = choose_cfg(dtype, 3, PS_PATH_VALU, n_f, n_v, opts);
+    const int cfg = choose_cfg(kdt, 3, bits ? PS_PATH_BITS : PS_PATH_VALU, n_f, n_v, opts);
     const int bm = kValuCfgs[cfg].bm();
-    Mg3Launch a{V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, prefix,
-                slab_tiles(n_v, j_begin, j_end, bm, bm), cfg, nchunks, chunk_tiles(dtype, cfg),
-                partial};
+    Mg3Launch a{KV, kn_f, n_v, kld, s, n2, j_begin, j_end, c3, prefix,
+                slab_tiles(n_v, j_begin, j_end, bm, bm), cfg, nchunks,
+                bits ? 0 : chunk_tiles(dtype, cfg), partial};
     e = launch_mg3_prefix(a, stream);
-    if (e == hipSuccess) e = launch_mg3(dtype, a, stream);
+    if (e == hipSuccess) e = launch_mg3(kdt, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");
 }
 

@@ -24,6 +24,13 @@ inline int elem_size(int32_t dt) {
     return dt == PS_F32 ? 4 : dt == PS_F16 ? 2 : dt == PS_U8 ? 1 : 0;
 }
 
+// Internal operand type of the BITS path (never a public ps_dtype): binary
+// data packed 32 fields to a 32-bit word, bit e of word w = field 32 w + e.
+constexpr int32_t PS_B1 = 3;
+constexpr int kBitsPerWord = 32;
+// Packed row length in words: whole 16-byte chunks.
+inline int64_t bits_row_words(int64_t n_f) { return ceil_div(ceil_div(n_f, kBitsPerWord), 4) * 4; }
+
 // Offset of the first triple of slab j in the j-slab layout:
 // sum_{t<j} t (n-1-t) = (n-1) j(j-1)/2 - (j-1) j (2j-1)/6.
 __host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
@@ -179,6 +186,12 @@ hipError_t launch_mg2_u8(const Mg2Launch& a, hipStream_t st);
 hipError_t launch_mg3_f32(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_f16(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st);
+hipError_t launch_mg2_b1(const Mg2Launch& a, hipStream_t st);
+hipError_t launch_mg3_b1(const Mg3Launch& a, hipStream_t st);
+// V (uint8 0/1, n_v rows of ld bytes, n_f fields) -> P (n_v rows of
+// bits_row_words(n_f) words), pad bits zero.
+hipError_t launch_pack_bits(const uint8_t* V, int64_t n_f, int64_t n_v, int64_t ld,
+                            uint32_t* P, hipStream_t st);
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st);
 hipError_t launch_finish2_batched(int32_t dt, const DevProblem* probs, int32_t n,

@@ -32,7 +32,7 @@ SZ = ctypes.c_size_t
 
 PS_F32, PS_F16, PS_U8 = 0, 1, 2
 ACC = {"auto": 0, "plain": 1, "blocked": 2}
-PATH = {"auto": 0, "valu": 1, "mfma": 2, "mfma_fp4": 3}
+PATH = {"auto": 0, "valu": 1, "mfma": 2, "mfma_fp4": 3, "bits": 4}
 DTYPES = {torch.float32: PS_F32, torch.float16: PS_F16, torch.uint8: PS_U8}
 
 
@@ -171,16 +171,17 @@ def stage_size(n_v: int, j_begin: int, j_end: int) -> int:
 
 def ps3(V: torch.Tensor, s: torch.Tensor | None = None, n2: torch.Tensor | None = None,
         j_begin: int = 1, j_end: int | None = None, acc="auto", tile=0,
-        c3: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        c3: torch.Tensor | None = None, stream=None, path="auto",
+        levels=0) -> torch.Tensor:
     """3-way metric of the triples i<j<k with j in [j_begin, j_end), j-slab
-    packed from offset 0."""
+    packed from offset 0.  path "bits" (with levels=1) for binary uint8 data."""
     dt, n_f, n_v, ld = _matrix(V)
     if j_end is None:
         j_end = max(n_v - 1, j_begin)
     m = stage_size(n_v, j_begin, j_end)
     if c3 is None:
         c3 = torch.empty(m, dtype=torch.float32, device=V.device)
-    o = _opts(acc, "auto", 0, tile)
+    o = _opts(acc, path, levels, tile)
     ws_n = lib.ps3_workspace_size(dt, n_f, n_v, int(s is not None), int(n2 is not None),
                                   j_begin, j_end, ctypes.byref(o))
     ws = _workspace(ws_n, V.device)

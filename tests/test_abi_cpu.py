@@ -59,7 +59,10 @@ def call2(V=FAKE, dt=0, n_f=10, n_v=5, ld=10, s=None, c2=FAKE, n2=None, ws=FAKE,
     (dict(dt=2, o=opts(path=2, levels=0)), ARG),       # MFMA needs levels
     (dict(o=opts(path=3, levels=3)), UNSUP),           # fp4 MFMA needs uint8 data
     (dict(dt=2, n_f=6_000_000, ld=6_000_000, o=opts(path=3, levels=3)), ARG),  # > 2^24
-    (dict(o=opts(path=4)), ARG),
+    (dict(o=opts(path=4)), UNSUP),                     # bits need uint8 data
+    (dict(dt=2, o=opts(path=4, levels=0)), ARG),       # bits need levels = 1
+    (dict(dt=2, o=opts(path=4, levels=2)), ARG),
+    (dict(o=opts(path=5)), ARG),
 ])
 def test_ps2_argument_errors(kw, status):
     assert call2(**kw) == status
@@ -94,6 +97,8 @@ def call3(V=FAKE, dt=0, n_f=10, n_v=6, ld=10, s=None, n2=None, jb=1, je=5, c3=FA
     (dict(ws_bytes=100), WS),
     (dict(dt=5), DTYPE),
     (dict(o=opts(path=2)), UNSUP),
+    (dict(o=opts(path=4, levels=1)), UNSUP),           # bits need uint8 data
+    (dict(dt=2, o=opts(path=4, levels=3)), ARG),
 ])
 def test_ps3_argument_errors(kw, status):
     assert call3(**kw) == status
@@ -125,6 +130,9 @@ def test_workspace_sizes():
     # auto on a small triangle splits further so that enough workgroups run
     assert f(0, 9000, 1000, 1, None) > f(0, 9000, 1000, 1, blocked)
     assert f(2, 9000, 1000, 1, None) == 0          # integer data: no split
+    # bits: the packed matrix, 32 fields per word in whole 16-byte chunks
+    words = math.ceil(math.ceil(9000 / 32) / 4) * 4
+    assert f(2, 9000, 1000, 1, opts(path=4, levels=1)) == math.ceil(1000 * words * 4 / 256) * 256
 
 
 @pytest.mark.parametrize("n_v", [3, 4, 7, 20])

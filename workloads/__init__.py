@@ -25,7 +25,7 @@ __all__ = [
     "uniform", "gwas_like", "levels", "sparse_uniform", "exponential",
     "binary", "nested_support", "to_f16", "Problem",
     "uniform_1024x256", "gwas_20000x16384", "levels_8192x32768",
-    "sparse_4096x1024", "batched_64_uneven", "WORKLOADS",
+    "sparse_4096x1024", "batched_64_uneven", "binary_8192x32768", "WORKLOADS",
 ]
 
 _CHUNK = 1 << 22  # rows*fields generated per numpy call, bounds host memory
@@ -190,10 +190,17 @@ def batched_64_uneven(seed: int = 0, count: int = 64, nv_range=(500, 8000),
     return [exponential(p.n_v, p.n_f, p.seed) for p in shapes]
 
 
+def binary_8192x32768(seed: int = 0) -> np.ndarray:
+    """Binary data (the Sorensen case): 8192 fields x 32768 vectors, uint8,
+    one w.p. 0.3."""
+    return binary(32768, 8192, seed, p_one=0.3, dtype=np.uint8)
+
+
 WORKLOADS = {
     "uniform_1024x256": uniform_1024x256,
     "gwas_20000x16384": gwas_20000x16384,
     "levels_8192x32768": levels_8192x32768,
     "sparse_4096x1024": sparse_4096x1024,
     "batched_64_uneven": batched_64_uneven,
+    "binary_8192x32768": binary_8192x32768,
 }
