@@ -14,6 +14,7 @@ Workloads (seeded, synthetic; shapes of the paper's problems):
   levels_8192x32768  2-way, uint8 levels {0..3}
   binary_8192x32768  2-way, uint8 {0, 1} (the Sorensen case; --path bits)
   sparse_4096x1024   3-way, FP32 U[0,1) with 50% zeros
+  levels_4096x1024   3-way, uint8 levels {0..3} (--path mfma | mfma_fp4 | valu)
   batched_64_uneven  64 independent 2-way problems in one captured launch
 
 Comparisons are counted as the paper counts them: one per field and unique
@@ -164,6 +165,7 @@ KERNEL_SOURCES = {
     "ps_mgb_kernel": _VALU_SOURCES,
     "ps_mfma2_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
     "ps_mfma2_dma_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
+    "ps_mfma3_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
 }
 PROFILES = os.path.join(ROOT, "profiles")
 GIB = 1 << 30
@@ -304,7 +306,7 @@ def counter_summary(d, kernel, commands):
 def traffic_key(args):
     """Workload and operand type of a run: names its traffic file."""
     wl = args.workload
-    if wl in ("levels_8192x32768", "binary_8192x32768"):
+    if wl in ("levels_8192x32768", "binary_8192x32768", "levels_4096x1024"):
         return wl + {"mfma_fp4": "_fp4", "bits": "_bits"}.get(args.path, "_u8")
     return wl + ("_f16" if args.storage == "f16" else "_f32")
 
@@ -385,31 +387,45 @@ def main(argv=None):
         config = {"workload": wl, "way": 2, "n_f": n_f, "n_v": n_v}
         cpu = (lambda: cpu_baseline_pairs(V, n_f, args.cpu_seconds))
         parity_fn = ("pairs", V)
-    elif wl == "sparse_4096x1024":
-        V = workloads.sparse_4096x1024(0)
-        if args.storage == "f16":
+    elif wl in ("sparse_4096x1024", "levels_4096x1024"):
+        V = workloads.WORKLOADS[wl](0)
+        if args.storage == "f16" and V.dtype == np.float32:
             V = workloads.to_f16(V)
         n_v, n_f = V.shape
         Vd = torch.from_numpy(V).to(dev)
+        levels = int(V.max()) if V.dtype == np.uint8 else 0
         s = torch.empty(n_v, dtype=torch.float64, device=dev)
-        n2 = torch.empty(n_v * (n_v - 1) // 2, dtype=torch.float32, device=dev)
+        n2 = torch.empty(n_v * (n_v - 1) // 2, dtype=ps.n2_dtype(Vd.dtype), device=dev)
         c3 = torch.empty(math.comb(n_v, 3), dtype=torch.float32, device=dev)
 
         def step(rec):
             ps.vector_sums(Vd, out=s, want_bad=False)
             ps.ps2(Vd, s=s, want_c2=False, want_n2=True, n2=n2, acc=args.acc,
-                   tile=args.tile)
+                   tile=args.tile, path=args.path, levels=levels)
             a = timer.mark() if rec else None
-            ps.ps3(Vd, s=s, n2=n2, c3=c3, acc=args.acc, tile=args.tile)
+            ps.ps3(Vd, s=s, n2=n2, c3=c3, acc=args.acc, tile=args.tile, path=args.path,
+                   levels=levels)
             if rec:
                 timer.add(a, timer.mark())
 
         cmp = n_f * math.comb(n_v, 3)
-        dtype = "f16" if V.dtype == np.float16 else "f32"
-        bound = "alu"
-        ops_per_cmp, peak = ((1.0, HALF_RATE_OPS_TOPS) if dtype == "f16"
-                             else (2.0, FP32_LANE_OPS_TOPS))
-        kernel = "ps_mg3_kernel"
+        use_mfma = V.dtype == np.uint8 and (args.path in ("mfma", "mfma_fp4") or
+                                            (args.path == "auto" and 1 <= levels <= 15))
+        if use_mfma and args.path == "mfma_fp4":   # e2m1 planes: `levels` MACs per comparison
+            dtype, bound, ops_per_cmp, peak = "fp4", "mfma", 2.0 * levels, FP4_MFMA_PEAK_TOPS
+            kernel = "ps_mfma3_kernel"
+        elif use_mfma:
+            dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
+            kernel = "ps_mfma3_kernel"
+        elif V.dtype == np.uint8:
+            dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
+            kernel = "ps_mg3_kernel"
+        else:
+            dtype = "f16" if V.dtype == np.float16 else "f32"
+            bound = "alu"
+            ops_per_cmp, peak = ((1.0, HALF_RATE_OPS_TOPS) if dtype == "f16"
+                                 else (2.0, FP32_LANE_OPS_TOPS))
+            kernel = "ps_mg3_kernel"
         config = {"workload": wl, "way": 3, "n_f": n_f, "n_v": n_v}
         cpu = (lambda: cpu_baseline_triples(V, n_f, args.cpu_seconds))
         parity_fn = ("triples", V)

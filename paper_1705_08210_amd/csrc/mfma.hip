@@ -20,7 +20,9 @@
 //   ps_mfma2_kernel          upper-triangle tiles of P P^T, FP64 epilogue
 //                            (int8: operands staged through registers);
 //   ps_mfma2_dma_kernel      the same with operands loaded straight into LDS
-//                            (fp4).
+//                            (fp4);
+//   ps_mfma3_kernel          3-way slices: (P_i AND P_j) P_k^T over the
+//                            rectangles i < j < k, raw n3' out.
 #include <type_traits>
 
 #include "ps_internal.h"
@@ -35,7 +37,7 @@ typedef float v16f_t __attribute__((ext_vector_type(16)));
 enum { kFmtI8 = 0, kFmtF4 = 1 };
 __host__ __device__ constexpr int fields_per_byte(int fmt) { return fmt == kFmtF4 ? 2 : 1; }
 
-constexpr int kMB = 256;      // output tile rows and columns
+constexpr int kMB = kMfmaTile;   // output tile rows and columns
 constexpr int kPad = 16;      // LDS row padding: b128 reads of 32 rows spread over the banks
 constexpr int kTileBytes = 128;   // plane rows are padded to whole multiples of this
 
@@ -133,6 +135,10 @@ struct MfmaArgs {
     float* c2;
     int32_t* n2;
     int64_t nb, ntiles;
+    // 3-way
+    int64_t j_begin, j_end;
+    const int64_t* prefix;
+    uint32_t* c3;
 };
 
 // Wave w owns j rows [(w%2)*128, +128) and i columns [(w/2)*32*WN, +32*WN)
@@ -174,56 +180,70 @@ __device__ __forceinline__ void mfma_epilogue(const AccT (&acc)[4][WN], const Mf
     }
 }
 
+// Accumulator type of a format.
+template <int FMT>
+using mfma_acc_t = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
+
+// LDS of the register-staged tile: two buffers for each of the two operands.
 template <int FMT, int WN>
-__global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArgs a) {
+constexpr int mfma_lds_bytes() { return 4 * kMB * (mfma_mk<FMT, WN>() + kPad); }
+
+// Main loop of one register-staged 256 x 256 tile: A rows a0 .. a0+255 and
+// B rows b0 .. b0+255 of the planes (rows at or past n_v read as zero); with
+// MASK every B chunk is ANDed with the same chunk of plane row `mrow` (the
+// 3-way X_j operand: [v_i >= t] AND [v_j >= t] = [min(v_i, v_j) >= t]).
+// Tile kt+1 is staged from registers into the second LDS buffer while tile kt
+// is consumed, one barrier per field tile.  Waves that are not `active` take
+// part in staging and barriers only.
+template <int FMT, int WN, bool MASK>
+__device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t b0,
+                                          const int8_t* mrow, bool active, int wr, int wc,
+                                          mfma_acc_t<FMT> (&acc)[4][WN], int8_t* lds) {
     constexpr int kMThreads = mfma_threads<WN>();
     constexpr int kMK = mfma_mk<FMT, WN>();
     constexpr int kPitch = kMK + kPad;
     constexpr int kRowChunks = kMK / 16;           // 16-byte chunks per tile row
     constexpr int kStage = kMB * kRowChunks / kMThreads;   // 16-byte chunks per thread per operand
     static_assert(kMB * kRowChunks % kMThreads == 0, "staging must divide evenly");
-    using AccT = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
-    // two buffers per operand: field tile kt+1 is staged while kt is consumed
-    __shared__ __attribute__((aligned(16))) int8_t As[2][kMB * kPitch];   // j rows
-    __shared__ __attribute__((aligned(16))) int8_t Bs[2][kMB * kPitch];   // i rows
-    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
-    if (t >= a.ntiles) return;
-    int64_t bi, bj;
-    grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
-    const int64_t i0 = bi * kMB, j0 = bj * kMB;
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int wr = (wave % 2) * 128;        // j offset of the wave's block
-    const int wc = (wave / 2) * 32 * WN;    // i offset
-    // some i < j with both < n_v among rows j0+wr.. and columns i0+wc..?
-    const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
+    static_assert(kMThreads % kRowChunks == 0, "a thread's chunks share one column");
+    // two buffers per operand: [A0 | B0 | A1 | B1], each kMB * kPitch bytes
+    auto As = [&](int buf) { return lds + (2 * buf) * (kMB * kPitch); };
+    auto Bs = [&](int buf) { return lds + (2 * buf + 1) * (kMB * kPitch); };
+    const int lane = threadIdx.x % 64;
 
-    AccT acc[4][WN];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < WN; ++n) acc[m][n] = (AccT){};
+        for (int n = 0; n < WN; ++n) acc[m][n] = (mfma_acc_t<FMT>){};
 
     // staging: 256 rows x kMK bytes per operand, kRowChunks threads per row
     uint4 ra[kStage], rb[kStage];
+    const int ch = threadIdx.x % kRowChunks;   // the same for all of a thread's chunks
     auto load = [&](int64_t k0) {
+        uint4 mk = make_uint4(0, 0, 0, 0);
+        if constexpr (MASK) mk = *(const uint4*)(mrow + k0 + ch * 16);
 #pragma unroll
         for (int c = 0; c < kStage; ++c) {
-            const int idx = threadIdx.x + c * kMThreads;
-            const int row = idx / kRowChunks, ch = idx % kRowChunks;
-            const int64_t gj = j0 + row, gi = i0 + row;
-            ra[c] = gj < a.n_v ? *(const uint4*)(a.P + gj * a.kp + k0 + ch * 16)
+            const int row = (threadIdx.x + c * kMThreads) / kRowChunks;
+            const int64_t ga = a0 + row, gb = b0 + row;
+            ra[c] = ga < a.n_v ? *(const uint4*)(a.P + ga * a.kp + k0 + ch * 16)
                                : make_uint4(0, 0, 0, 0);
-            rb[c] = gi < a.n_v ? *(const uint4*)(a.P + gi * a.kp + k0 + ch * 16)
+            rb[c] = gb < a.n_v ? *(const uint4*)(a.P + gb * a.kp + k0 + ch * 16)
                                : make_uint4(0, 0, 0, 0);
+            if constexpr (MASK) {
+                rb[c].x &= mk.x;
+                rb[c].y &= mk.y;
+                rb[c].z &= mk.z;
+                rb[c].w &= mk.w;
+            }
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int c = 0; c < kStage; ++c) {
-            const int idx = threadIdx.x + c * kMThreads;
-            const int row = idx / kRowChunks, ch = idx % kRowChunks;
-            *(uint4*)(As[buf] + row * kPitch + ch * 16) = ra[c];
-            *(uint4*)(Bs[buf] + row * kPitch + ch * 16) = rb[c];
+            const int row = (threadIdx.x + c * kMThreads) / kRowChunks;
+            *(uint4*)(As(buf) + row * kPitch + ch * 16) = ra[c];
+            *(uint4*)(Bs(buf) + row * kPitch + ch * 16) = rb[c];
         }
     };
 
@@ -240,8 +260,8 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArg
     if (active) {
         for (int64_t kt = 0; kt < nk; ++kt) {
             const int cur = (int)(kt & 1);
-            const int8_t* A = As[cur];
-            const int8_t* B = Bs[cur];
+            const int8_t* A = As(cur);
+            const int8_t* B = Bs(cur);
 #pragma unroll
             for (int ks = 0; ks < kMK / 32; ++ks) {
                 v4i_t fa[4], fb[WN];
@@ -276,11 +296,77 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArg
             __syncthreads();
             if (kt + 2 < nk) load((kt + 2) * kMK);
         }
-        return;
     }
+}
 
-
+template <int FMT, int WN>
+__global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[mfma_lds_bytes<FMT, WN>()];
+    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    if (t >= a.ntiles) return;
+    int64_t bi, bj;
+    grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
+    const int64_t i0 = bi * kMB, j0 = bj * kMB;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wr = (wave % 2) * 128;        // j offset of the wave's block (A rows)
+    const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
+    // some i < j with both < n_v among rows j0+wr.. and columns i0+wc..?
+    const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
+    mfma_acc_t<FMT> acc[4][WN];
+    mfma_tile<FMT, WN, false>(a, j0, i0, nullptr, active, wr, wc, acc, lds);
+    if (!active) return;
     mfma_epilogue<WN>(acc, a, i0, j0, wr, wc, lane);
+}
+
+// ---------------------------------------------------------------------------
+// 3-way slices on the matrix cores (Section 3.2 with the thermometer
+// identity).  For slab j, n3'(i, j, k) = sum over plane bytes of
+// (P_i AND P_j) P_k, since [a >= t][b >= t][c >= t] = [min(a, b, c) >= t].
+// A work item is (slab j, tile of i, tile of k > j), enumerated through the
+// slab prefix of the tile counts.  A rows are k and B rows are i, masked with
+// P_j while staging, so the lane index of the MFMA output runs along i and 32
+// lanes store 32 consecutive entries of the j-slab layout.  The exact integer
+// n3' is stored as int32 bits; the integer 3-way finish applies Eq. 1.
+// ---------------------------------------------------------------------------
+template <int FMT>
+__global__ __launch_bounds__(mfma_threads<2>(), 1) void ps_mfma3_kernel(MfmaArgs a) {
+    constexpr int WN = 2;
+    __shared__ __attribute__((aligned(16))) int8_t lds[mfma_lds_bytes<FMT, WN>()];
+    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    if (t >= a.ntiles) return;
+    // slab j: largest jj with prefix[jj] <= t (every slab has >= 1 tile)
+    int64_t lo = 0, hi = a.j_end - a.j_begin;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (a.prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int64_t j = a.j_begin + lo;
+    const int64_t local = t - a.prefix[lo];
+    const int64_t nbk = (a.n_v - 1 - j + kMB - 1) / kMB;
+    const int64_t i0 = (local / nbk) * kMB, k0 = j + 1 + (local % nbk) * kMB;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wr = (wave % 2) * 128;        // k offset of the wave's block (A rows)
+    const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
+    const bool active = (k0 + wr < a.n_v) && (i0 + wc < j);
+    mfma_acc_t<FMT> acc[4][WN];
+    mfma_tile<FMT, WN, true>(a, k0, i0, a.P + j * a.kp, active, wr, wc, acc, lds);
+    if (!active) return;
+    const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin);
+    const int64_t ib = i0 + wc + (lane % 32);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t k = k0 + wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
+            if (k >= a.n_v) continue;
+            uint32_t* row = a.c3 + base + (k - j - 1) * j;
+#pragma unroll
+            for (int n = 0; n < WN; ++n) {
+                const int64_t i = ib + n * 32;
+                if (i < j) row[i] = (uint32_t)(int32_t)acc[m][n][r];   // exact in either format
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -414,20 +500,29 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_dma_kernel(Mfm
     mfma_epilogue<WN>(acc, a, i0, j0, wr, wc, lane);
 }
 
-template <int FMT, int WN>
-static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
+// Thermometer planes of V into m.planes (when m.expand); returns the plane-row
+// length in bytes through kp.
+template <int FMT>
+static hipError_t expand_planes(const MfmaLaunch& m, int64_t& kp, hipStream_t st) {
     const int64_t kpad = plane_fields(m.n_f, FMT);
-    const int64_t kp = (int64_t)m.levels * kpad / fields_per_byte(FMT);
+    kp = (int64_t)m.levels * kpad / fields_per_byte(FMT);
+    if (!m.expand) return hipSuccess;
     const int64_t total = m.n_v * (kpad / 32);
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(ps_thermo_expand_kernel<FMT>, dim3((unsigned)blocks), dim3(256), 0, st,
                        (const uint8_t*)m.V, m.n_f, m.n_v, m.ld, m.levels, kpad, m.planes);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+template <int FMT, int WN>
+static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
+    int64_t kp = 0;
+    hipError_t e = expand_planes<FMT>(m, kp, st);
     if (e != hipSuccess) return e;
     const int64_t nb = (m.n_v + kMB - 1) / kMB;
     const int64_t T = nb * (nb + 1) / 2;
-    MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T};
+    MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T, 0, 0, nullptr, nullptr};
     const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
     if constexpr (FMT == kFmtF4 && WN == 2)
         hipLaunchKernelGGL((ps_mfma2_dma_kernel<FMT, WN>), dim3((unsigned)grid),
@@ -436,6 +531,28 @@ static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
         hipLaunchKernelGGL((ps_mfma2_kernel<FMT, WN>), dim3((unsigned)grid),
                            dim3(mfma_threads<WN>()), 0, st, a);
     return hipGetLastError();
+}
+
+template <int FMT>
+static hipError_t go_mfma3(const MfmaLaunch& m, hipStream_t st) {
+    int64_t kp = 0;
+    hipError_t e = expand_planes<FMT>(m, kp, st);
+    if (e != hipSuccess) return e;
+    e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kMB, m.prefix, st);
+    if (e != hipSuccess) return e;
+    const int64_t T = slab_tiles(m.n_v, m.j_begin, m.j_end, kMB, kMB);
+    if (T == 0) return hipSuccess;
+    MfmaArgs a{m.planes, kp, m.n_v, m.s, nullptr, nullptr, 0, T, m.j_begin, m.j_end, m.prefix,
+               (uint32_t*)m.c3};
+    const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(ps_mfma3_kernel<FMT>, dim3((unsigned)grid), dim3(mfma_threads<2>()), 0,
+                       st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma3(const MfmaLaunch& m, hipStream_t st) {
+    if (m.n_v < 3 || m.j_end <= m.j_begin) return hipSuccess;
+    return m.fmt == kFmtF4 ? go_mfma3<kFmtF4>(m, st) : go_mfma3<kFmtI8>(m, st);
 }
 
 hipError_t launch_mfma2(const MfmaLaunch& m, hipStream_t st) {

@@ -88,4 +88,8 @@ hipError_t launch_mg3_b1(const Mg3Launch& a, hipStream_t st) {
     return e == hipSuccess ? go_c3_finish<PS_B1>(a, st) : e;
 }
 
+hipError_t launch_c3_finish_int(const Mg3Launch& a, hipStream_t st) {
+    return go_c3_finish<PS_B1>(a, st);
+}
+
 }  // namespace ps

@@ -258,11 +258,14 @@ hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
-    const int bm = kValuCfgs[a.cfg].bm();
-    hipLaunchKernelGGL(ps_prefix3_kernel, dim3(1), dim3(1024), 0, st, a.n_v, a.j_begin,
-                       a.j_end, bm, a.prefix);
+hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(ps_prefix3_kernel, dim3(1), dim3(1024), 0, st, n_v, jb, je, bm, prefix);
     return hipGetLastError();
+}
+
+hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
+    return launch_prefix3(a.n_v, a.j_begin, a.j_end, kValuCfgs[a.cfg].bm(), a.prefix, st);
 }
 
 }  // namespace ps

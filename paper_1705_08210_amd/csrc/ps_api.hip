@@ -108,6 +108,21 @@ static ps_status check_bits(int32_t dtype, const ps_opts* o) {
 
 static bool is_bits(const ps_opts* o) { return o && o->path == PS_PATH_BITS; }
 
+// The thermometer paths take uint8 data with a bound on its values, and every
+// numerator (at most levels * n_f) must be exact in the accumulator.
+static ps_status check_mfma(int path, int32_t dtype, int levels, int64_t n_f) {
+    if (!is_mfma(path)) return PS_OK;
+    if (dtype != PS_U8) return fail(PS_ERR_UNSUPPORTED, "the MFMA path needs PS_U8 data");
+    if (levels < 1) return fail(PS_ERR_ARG, "the MFMA path needs opts.levels >= max(V) >= 1");
+    if (path == PS_PATH_MFMA_FP4 && (int64_t)levels * n_f >= ((int64_t)1 << 24))
+        return fail(PS_ERR_ARG, "fp4 path: levels * n_f = %lld exceeds the exact FP32 range",
+                    (long long)levels * n_f);
+    if (path == PS_PATH_MFMA && (int64_t)levels * n_f >= ((int64_t)1 << 31))
+        return fail(PS_ERR_ARG, "int8 path: levels * n_f = %lld exceeds int32",
+                    (long long)levels * n_f);
+    return PS_OK;
+}
+
 static size_t bits_bytes(int64_t n_f, int64_t n_v) {
     return (size_t)n_v * (size_t)bits_row_words(n_f) * sizeof(uint32_t);
 }
@@ -199,18 +214,8 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         return fail(PS_ERR_ARG, "misaligned output or sums pointer");
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
     const int path = choose_path(dtype, opts);
-    if (is_mfma(path) && dtype != PS_U8)
-        return fail(PS_ERR_UNSUPPORTED, "the MFMA path needs PS_U8 data");
     const int levels = opts ? opts->levels : 0;
-    if (is_mfma(path) && levels < 1)
-        return fail(PS_ERR_ARG, "the MFMA path needs opts.levels >= max(V) >= 1");
-    // exactness of the accumulators: every pair sum is at most levels * n_f
-    if (path == PS_PATH_MFMA_FP4 && (int64_t)levels * n_f >= ((int64_t)1 << 24))
-        return fail(PS_ERR_ARG, "fp4 path: levels * n_f = %lld exceeds the exact FP32 range",
-                    (long long)levels * n_f);
-    if (path == PS_PATH_MFMA && (int64_t)levels * n_f >= ((int64_t)1 << 31))
-        return fail(PS_ERR_ARG, "int8 path: levels * n_f = %lld exceeds int32",
-                    (long long)levels * n_f);
+    if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
     float* partial = nullptr;
@@ -232,7 +237,8 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (is_mfma(path)) {
         // opts.tile: 0 or 1 -> 4x2 blocks per wave, 2 -> 4x4 blocks per wave
         MfmaLaunch m{V, n_f, n_v, ld, levels, s, c2, n2, planes,
-                     path == PS_PATH_MFMA_FP4 ? 1 : 0, (opts && opts->tile == 2) ? 1 : 0};
+                     path == PS_PATH_MFMA_FP4 ? 1 : 0, (opts && opts->tile == 2) ? 1 : 0,
+                     1, 0, 0, nullptr, nullptr};
         e = launch_mfma2(m, stream);
         if (e == hipErrorNotSupported)
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");
@@ -278,6 +284,49 @@ static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t
     return c.used;
 }
 
+// 3-way on the matrix cores (uint8 levels): planes once, the pair
+// numerators by the 2-way MFMA kernel (unless given), the masked slices, then
+// Eq. 1 from exact integers.
+static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, const double* s,
+                          const void* n2, int64_t j_begin, int64_t j_end, float* c3,
+                          void* workspace, size_t ws_bytes, int path, int levels,
+                          hipStream_t stream) {
+    const int fmt = path == PS_PATH_MFMA_FP4 ? 1 : 0;
+    const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
+    double* s_ws = nullptr;
+    void* n2_ws = nullptr;
+    int64_t* prefix = nullptr;
+    float* partial = nullptr;
+    uint32_t* planes = nullptr;
+    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, 1, 1, stage,
+                                   mfma_workspace_bytes(n_f, n_v, levels, fmt), workspace,
+                                   &s_ws, &n2_ws, &prefix, &partial, &planes);
+    if (ws_bytes < need || !workspace)
+        return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
+    hipError_t e;
+    if (!s) {
+        e = launch_sums(V, PS_U8, n_f, n_v, ld, s_ws, nullptr, stream);
+        if (e != hipSuccess) return hip_fail(e, "sums launch");
+        s = s_ws;
+    }
+    MfmaLaunch m{V, n_f, n_v, ld, levels, s, nullptr, nullptr, (int8_t*)planes, fmt, 0,
+                 1, j_begin, j_end, prefix, c3};
+    if (!n2) {   // pair numerators; this launch also writes the planes
+        MfmaLaunch m2 = m;
+        m2.n2 = n2_ws;
+        e = launch_mfma2(m2, stream);
+        if (e != hipSuccess) return hip_fail(e, "3-way numerator prepass launch");
+        n2 = n2_ws;
+        m.expand = 0;
+    }
+    e = launch_mfma3(m, stream);
+    if (e != hipSuccess) return hip_fail(e, "3-way mfma launch");
+    Mg3Launch f{V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, prefix, 0, 0, 1, 0, nullptr};
+    e = launch_c3_finish_int(f, stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "3-way finish launch");
+}
+
 size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_given,
                           int32_t n2_given, int64_t j_begin, int64_t j_end,
                           const ps_opts* opts) {
@@ -288,6 +337,12 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (is_bits(opts))
         return ws3_layout(n_v, s_given, n2_given, 1, 1, stage, bits_bytes(n_f, n_v), nullptr,
                           nullptr, nullptr, nullptr, nullptr, nullptr);
+    const int path = choose_path(dtype, opts);
+    if (is_mfma(path) && dtype == PS_U8)
+        return ws3_layout(n_v, s_given, n2_given, 1, 1, stage,
+                          mfma_workspace_bytes(n_f, n_v, opts ? opts->levels : 0,
+                                               path == PS_PATH_MFMA_FP4 ? 1 : 0),
+                          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     const Split sp2 =
         plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
     return ws3_layout(n_v, s_given, n2_given, sp2.nchunks,
@@ -307,9 +362,10 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     ps_status st = check_matrix(V, dtype, n_f, n_v, ld);
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
-    if (opts && is_mfma(opts->path))
-        return fail(PS_ERR_UNSUPPORTED, "3-way runs on the VALU and BITS paths only");
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
+    const int path = choose_path(dtype, opts);
+    const int levels = opts ? opts->levels : 0;
+    if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
     if (n_v < 3) return PS_OK;
     if (j_begin < 1 || j_end > n_v - 1 || j_begin > j_end)
         return fail(PS_ERR_ARG, "need 1 <= j_begin <= j_end <= n_v-1, got [%lld, %lld)",
@@ -322,6 +378,8 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     void* n2_ws = nullptr;
     int64_t* prefix = nullptr;
     float* partial = nullptr;
+    if (is_mfma(path)) return ps3_mfma(V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, workspace,
+                                       ws_bytes, path, levels, stream);
     const bool bits = is_bits(opts);
     const int32_t kdt = bits ? PS_B1 : dtype;   // operand type of the kernels
     const int cfg2 = choose_cfg(kdt, 2, bits ? PS_PATH_BITS : PS_PATH_VALU, n_f, n_v, opts);

@@ -214,8 +214,20 @@ struct MfmaLaunch {
     int8_t* planes;              // workspace: mfma_workspace_bytes()
     int fmt;                     // 0: int8 planes, 1: fp4 (e2m1) planes
     int wide;                    // 0: 4x2 MFMA blocks per wave, 1: 4x4
+    int expand;                  // 1: write the planes first; 0: planes already hold V's
+    // 3-way slices (launch_mfma3): raw n3' of the stage into c3 (int32 bits)
+    int64_t j_begin, j_end;
+    int64_t* prefix;             // workspace: j_end - j_begin + 1 int64
+    float* c3;
 };
 size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt);
 hipError_t launch_mfma2(const MfmaLaunch& a, hipStream_t st);
+// Output tile edge of the MFMA kernels (the 3-way prefix is over these tiles).
+constexpr int kMfmaTile = 256;
+hipError_t launch_mfma3(const MfmaLaunch& a, hipStream_t st);
+hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
+                          hipStream_t st);
+// Eq. 1 from exact integer raw n3' (int32 bits in c3) and int32 pair numerators.
+hipError_t launch_c3_finish_int(const Mg3Launch& a, hipStream_t st);
 
 }  // namespace ps

@@ -99,6 +99,8 @@ def call3(V=FAKE, dt=0, n_f=10, n_v=6, ld=10, s=None, n2=None, jb=1, je=5, c3=FA
     (dict(o=opts(path=2)), UNSUP),
     (dict(o=opts(path=4, levels=1)), UNSUP),           # bits need uint8 data
     (dict(dt=2, o=opts(path=4, levels=3)), ARG),
+    (dict(dt=2, o=opts(path=2, levels=0)), ARG),       # MFMA needs levels
+    (dict(dt=2, n_f=6_000_000, ld=6_000_000, o=opts(path=3, levels=3)), ARG),  # > 2^24
 ])
 def test_ps3_argument_errors(kw, status):
     assert call3(**kw) == status

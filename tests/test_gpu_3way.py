@@ -142,3 +142,51 @@ def test_blocked_split_over_field_chunks(tile):
     part = np.concatenate([host(ps.ps3(Vd, j_begin=a, j_end=b, acc="blocked", tile=tile))
                            for a, b in [(1, 30), (30, 69)]])
     assert np.array_equal(part.view(np.uint32), c3.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# 3-way on the matrix cores (uint8 levels, thermometer planes): exact.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
+@pytest.mark.parametrize("n_v,n_f", [(140, 603), (300, 200), (3, 1), (4, 2), (259, 5),
+                                     (520, 130)])
+def test_mfma_3way_exact(path, n_v, n_f):
+    from paper_1705_08210_amd import ps
+    V = workloads.levels(n_v, n_f, seed=n_v * 3 + n_f)
+    lev = max(1, int(V.max()))
+    announce(f"3-way {path} {n_v}x{n_f}")
+    c3 = host(ps.ps3(to_dev(V), path=path, levels=lev))
+    check_exact_f32(c3, oracle.c3_all(V), "c3")
+
+
+@pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
+def test_mfma_3way_stages_given_inputs_and_valu(path):
+    """Stages concatenate bit for bit; given s and n2 change nothing; the
+    VALU uint8 path gives the same numbers."""
+    from paper_1705_08210_amd import ps
+    V = workloads.levels(300, 450, seed=51)
+    Vd = to_dev(V)
+    announce(f"3-way {path} stages")
+    full = host(ps.ps3(Vd, path=path, levels=3))
+    parts = [host(ps.ps3(Vd, path=path, levels=3, j_begin=a, j_end=b))
+             for a, b in [(1, 2), (2, 120), (120, 257), (257, 299)]]
+    assert np.array_equal(np.concatenate(parts).view(np.uint32), full.view(np.uint32))
+    s, _ = ps.vector_sums(Vd)
+    _, n2 = ps.ps2(Vd, want_c2=False, want_n2=True, path=path, levels=3)
+    given = host(ps.ps3(Vd, s=s, n2=n2, path=path, levels=3))
+    assert np.array_equal(given.view(np.uint32), full.view(np.uint32))
+    valu = host(ps.ps3(Vd, path="valu"))
+    assert np.array_equal(valu.view(np.uint32), full.view(np.uint32))
+
+
+@pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
+def test_mfma_3way_full_size_sampled(path):
+    """levels_4096x1024 in the bench's launch: sampled triples exact."""
+    from paper_1705_08210_amd import ps
+    from psx import sample_triples
+    V = workloads.levels_4096x1024(0)
+    n_v = V.shape[0]
+    announce(f"3-way {path} 4096x1024 sampled")
+    c3 = host(ps.ps3(to_dev(V), path=path, levels=3))
+    i, j, k = sample_triples(n_v, 4096, seed=52)
+    check_exact_f32(c3[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), "c3 sampled")

@@ -25,7 +25,8 @@ __all__ = [
     "uniform", "gwas_like", "levels", "sparse_uniform", "exponential",
     "binary", "nested_support", "to_f16", "Problem",
     "uniform_1024x256", "gwas_20000x16384", "levels_8192x32768",
-    "sparse_4096x1024", "batched_64_uneven", "binary_8192x32768", "WORKLOADS",
+    "sparse_4096x1024", "batched_64_uneven", "binary_8192x32768", "levels_4096x1024",
+    "WORKLOADS",
 ]
 
 _CHUNK = 1 << 22  # rows*fields generated per numpy call, bounds host memory
@@ -196,6 +197,12 @@ def binary_8192x32768(seed: int = 0) -> np.ndarray:
     return binary(32768, 8192, seed, p_one=0.3, dtype=np.uint8)
 
 
+def levels_4096x1024(seed: int = 0) -> np.ndarray:
+    """3-way on integer levels: 4096 fields x 1024 vectors, uint8 {0,1,2,3}
+    with probabilities .6/.2/.15/.05 (the 3-way shape with the levels mix)."""
+    return levels(1024, 4096, seed)
+
+
 WORKLOADS = {
     "uniform_1024x256": uniform_1024x256,
     "gwas_20000x16384": gwas_20000x16384,
@@ -203,4 +210,5 @@ WORKLOADS = {
     "sparse_4096x1024": sparse_4096x1024,
     "batched_64_uneven": batched_64_uneven,
     "binary_8192x32768": binary_8192x32768,
+    "levels_4096x1024": levels_4096x1024,
 }
