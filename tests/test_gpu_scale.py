@@ -111,3 +111,26 @@ def test_nested_support_3way_full_size_exact():
         check_exact_f32(c3[pos:pos + len(ref)], ref, f"c3 slab {j}")
         pos += len(ref)
     assert pos == c3.shape[0]
+
+
+def test_sparse_4096x1024_3way_full_oracle():
+    """The 3-way bench workload compared in full: every one of the C(1024, 3)
+    triples against the oracle (about half a minute of oracle time on 16
+    host threads)."""
+    from paper_1705_08210_amd import ps
+    V = workloads.sparse_4096x1024()
+    announce("scale 3-way sparse 4096x1024 f32, all triples against the oracle")
+    c3 = host(ps.ps3(to_dev(V)))
+    ea, er = check_rel(c3, oracle.c3_all(V), FP32_TOL, "c3")
+    print(f"3-way full: max abs {ea:.3e} max rel {er:.3e} over {c3.size} triples")
+
+
+@pytest.mark.parametrize("path", ["mfma", "mfma_fp4", "valu"])
+def test_levels_3way_full_oracle_exact(path):
+    """Integer 3-way in full (600 vectors x 4096 fields, several 256-wide
+    tiles per slab): every triple bit-exact against the oracle."""
+    from paper_1705_08210_amd import ps
+    V = workloads.levels(600, 4096, seed=53)
+    announce(f"scale 3-way levels 4096x600 {path}, all triples against the oracle")
+    c3 = host(ps.ps3(to_dev(V), path=path, levels=3))
+    check_exact_f32(c3, oracle.c3_all(V), "c3")
