@@ -249,6 +249,37 @@ ps_status ps_tune_register(int32_t dtype, int32_t way, int32_t path,
 /* Forget all registered choices. */
 void ps_tune_clear(void);
 
+/*
+ * Output reduction on the device (the output handling of Section 6.5, where
+ * each metric is stored as one unsigned byte and thresholding is named as
+ * the way to cut the volume of a campaign's output).
+ */
+
+/* q[i] = round-half-even(255 * clamp(c[i], 0, 1)) for i < n: one byte per
+ * metric (about 2.5 significant figures).  c, q device pointers (any
+ * alignment); n >= 0.  Errors: PS_ERR_ARG for n < 0 or a NULL pointer with
+ * n > 0. */
+ps_status ps_quantize_u8(const float* c, int64_t n, uint8_t* q, hipStream_t stream);
+
+/* Workspace bytes of ps_threshold for n entries. */
+size_t ps_threshold_workspace_size(int64_t n);
+
+/*
+ * Thresholding: the entries i < n with c[i] >= threshold, in increasing i.
+ *   idx, val   device outputs with room for `cap` entries: idx = base + i
+ *              (base turns stage-relative positions into global ones, e.g.
+ *              the packed index of a stage's first triple), val = c[i]
+ *   count      device int64: the number of entries selected; when it
+ *              exceeds cap only the first cap are written
+ *   workspace  device scratch of ps_threshold_workspace_size(n) bytes,
+ *              256-byte aligned
+ * Deterministic.  Errors: PS_ERR_ARG (n < 0, cap < 0, NULL or misaligned
+ * pointers), PS_ERR_WORKSPACE.
+ */
+ps_status ps_threshold(const float* c, int64_t n, float threshold, int64_t base,
+                       int64_t* idx, float* val, int64_t cap, int64_t* count,
+                       void* workspace, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -350,6 +350,45 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
                       nullptr, nullptr, nullptr, nullptr);
 }
 
+ps_status ps_quantize_u8(const float* c, int64_t n, uint8_t* q, hipStream_t stream) {
+    if (n < 0) return fail(PS_ERR_ARG, "n = %lld < 0", (long long)n);
+    if (n > 0 && (!c || !q)) return fail(PS_ERR_ARG, "c or q is NULL");
+    if (!aligned(c, 4)) return fail(PS_ERR_ARG, "c is not 4-byte aligned");
+    hipError_t e = launch_quantize_u8(c, n, q, stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "quantize launch");
+}
+
+// counts (int32 per tile) then offsets (int64 per tile)
+size_t ps_threshold_workspace_size(int64_t n) {
+    if (n < 0) return 0;
+    Carver c(nullptr);
+    c.take((size_t)select_tiles(n) * sizeof(int32_t));
+    c.take((size_t)select_tiles(n) * sizeof(int64_t));
+    return c.used;
+}
+
+ps_status ps_threshold(const float* c, int64_t n, float threshold, int64_t base,
+                       int64_t* idx, float* val, int64_t cap, int64_t* count,
+                       void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || cap < 0) return fail(PS_ERR_ARG, "n = %lld, cap = %lld: need >= 0",
+                                      (long long)n, (long long)cap);
+    if (!count) return fail(PS_ERR_ARG, "count is NULL");
+    if (n > 0 && !c) return fail(PS_ERR_ARG, "c is NULL");
+    if (cap > 0 && (!idx || !val)) return fail(PS_ERR_ARG, "idx or val is NULL");
+    if (!aligned(c, 4) || !aligned(val, 4) || !aligned(idx, 8) || !aligned(count, 8))
+        return fail(PS_ERR_ARG, "misaligned pointer");
+    const size_t need = ps_threshold_workspace_size(n);
+    if (ws_bytes < need || (need && !workspace))
+        return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
+    Carver w(workspace);
+    int32_t* counts = (int32_t*)w.take((size_t)select_tiles(n) * sizeof(int32_t));
+    int64_t* offsets = (int64_t*)w.take((size_t)select_tiles(n) * sizeof(int64_t));
+    hipError_t e = launch_select(c, n, threshold, base, idx, val, cap, count, counts, offsets,
+                                 stream);
+    return e == hipSuccess ? PS_OK : hip_fail(e, "threshold launch");
+}
+
 int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end) {
     if (n_v < 3 || j_end <= j_begin) return 0;
     return slab_offset(n_v, j_end) - slab_offset(n_v, j_begin);

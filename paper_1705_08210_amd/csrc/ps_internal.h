@@ -227,6 +227,12 @@ constexpr int kMfmaTile = 256;
 hipError_t launch_mfma3(const MfmaLaunch& a, hipStream_t st);
 hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
                           hipStream_t st);
+// Output reduction (reduce.hip).
+hipError_t launch_quantize_u8(const float* c, int64_t n, uint8_t* q, hipStream_t st);
+int64_t select_tiles(int64_t n);
+hipError_t launch_select(const float* c, int64_t n, float thr, int64_t base, int64_t* idx,
+                         float* val, int64_t cap, int64_t* count, int32_t* counts,
+                         int64_t* offsets, hipStream_t st);
 // Eq. 1 from exact integer raw n3' (int32 bits in c3) and int32 pair numerators.
 hipError_t launch_c3_finish_int(const Mg3Launch& a, hipStream_t st);
 

@@ -75,6 +75,9 @@ _sig("ps_tile_config", I32, [I32, I32, I32, I32, ctypes.POINTER(I32),
                              ctypes.POINTER(I32), ctypes.POINTER(I32)])
 _sig("ps_tune_register", ctypes.c_int, [I32, I32, I32, I64, I64, I64, I64, I32])
 _sig("ps_tune_clear", None, [])
+_sig("ps_quantize_u8", ctypes.c_int, [P, I64, P, P])
+_sig("ps_threshold_workspace_size", SZ, [I64])
+_sig("ps_threshold", ctypes.c_int, [P, I64, ctypes.c_float, I64, P, P, I64, P, P, SZ, P])
 
 
 def header_functions() -> list[str]:
@@ -283,6 +286,36 @@ def tune_register(dtype, way, path, nf_range, nv_range, idx) -> None:
 
 def tune_clear() -> None:
     lib.ps_tune_clear()
+
+
+def quantize_u8(c: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """One byte per metric: round-half-even(255 * clamp(c, 0, 1))."""
+    if c.dtype != torch.float32 or not c.is_cuda or not c.is_contiguous():
+        raise ValueError("c must be a contiguous float32 GPU tensor")
+    n = c.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=c.device)
+    _check(lib.ps_quantize_u8(c.data_ptr() if n else None, n, out.data_ptr() if n else None,
+                              _stream(stream)))
+    return out
+
+
+def threshold(c: torch.Tensor, thr: float, base: int = 0, cap: int | None = None,
+              stream=None):
+    """Entries with c >= thr in index order: (idx int64, val float32, count)
+    device tensors; idx = base + position; only the first cap are written."""
+    if c.dtype != torch.float32 or not c.is_cuda or not c.is_contiguous():
+        raise ValueError("c must be a contiguous float32 GPU tensor")
+    n = c.numel()
+    cap = n if cap is None else int(cap)
+    idx = torch.empty(max(cap, 1), dtype=torch.int64, device=c.device)
+    val = torch.empty(max(cap, 1), dtype=torch.float32, device=c.device)
+    count = torch.empty(1, dtype=torch.int64, device=c.device)
+    ws = _workspace(lib.ps_threshold_workspace_size(n), c.device)
+    _check(lib.ps_threshold(c.data_ptr() if n else None, n, float(thr), int(base),
+                            idx.data_ptr(), val.data_ptr(), cap, count.data_ptr(),
+                            ws.data_ptr(), ws.numel(), _stream(stream)))
+    return idx, val, count
 
 
 # The C ABI's names (include/ps.h) for the same calls.
