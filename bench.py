@@ -52,7 +52,7 @@ def parse(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gwas_20000x16384")
-    ap.add_argument("--storage", default="auto", choices=["auto", "f32", "f16"])
+    ap.add_argument("--storage", default="auto", choices=["auto", "f32", "f16", "f64"])
     ap.add_argument("--acc", default="auto", choices=["auto", "plain", "blocked"])
     ap.add_argument("--path", default="auto",
                     choices=["auto", "valu", "mfma", "mfma_fp4", "bits"])
@@ -62,6 +62,9 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-problem", action="store_true",
                     help="batched workload: one launch per problem instead of the plan")
+    ap.add_argument("--campaign", type=int, default=0, metavar="STAGES",
+                    help="3-way workloads: run as a staged campaign of STAGES stages, one "
+                         "byte per metric copied to host memory (Section 6.5 output)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel of known "
                          "size, to scale HBM byte counters of a profiler run)")
@@ -308,7 +311,7 @@ def traffic_key(args):
     wl = args.workload
     if wl in ("levels_8192x32768", "binary_8192x32768", "levels_4096x1024"):
         return wl + {"mfma_fp4": "_fp4", "bits": "_bits"}.get(args.path, "_u8")
-    return wl + ("_f16" if args.storage == "f16" else "_f32")
+    return wl + {"f16": "_f16", "f64": "_f64"}.get(args.storage, "_f32")
 
 
 def main(argv=None):
@@ -348,6 +351,8 @@ def main(argv=None):
         V = workloads.WORKLOADS[wl](0)
         if args.storage == "f16" and V.dtype == np.float32:
             V = workloads.to_f16(V)
+        elif args.storage == "f64" and V.dtype == np.float32:
+            V = V.astype(np.float64)
         n_v, n_f = V.shape
         Vd = torch.from_numpy(V).to(dev)
         s = torch.empty(n_v, dtype=torch.float64, device=dev)
@@ -378,6 +383,9 @@ def main(argv=None):
         elif V.dtype == np.uint8:   # v_sad_u8: 4 comparisons per op
             dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
             kernel = "ps_mg2_kernel"
+        elif V.dtype == np.float64:  # v_min_f64 + v_add_f64 at the FP64 rate
+            dtype, bound, ops_per_cmp, peak = "f64", "alu", 2.0, HALF_RATE_OPS_TOPS
+            kernel = "ps_mg2_kernel"
         elif V.dtype == np.float16:  # pk_min + dot2 per 2 comparisons
             dtype, bound, ops_per_cmp, peak = "f16", "alu", 1.0, HALF_RATE_OPS_TOPS
             kernel = "ps_mg2_kernel"
@@ -391,6 +399,8 @@ def main(argv=None):
         V = workloads.WORKLOADS[wl](0)
         if args.storage == "f16" and V.dtype == np.float32:
             V = workloads.to_f16(V)
+        elif args.storage == "f64" and V.dtype == np.float32:
+            V = V.astype(np.float64)
         n_v, n_f = V.shape
         Vd = torch.from_numpy(V).to(dev)
         levels = int(V.max()) if V.dtype == np.uint8 else 0
@@ -408,6 +418,23 @@ def main(argv=None):
             if rec:
                 timer.add(a, timer.mark())
 
+        if args.campaign > 0:   # staged: every stage's bytes end in host memory
+            from paper_1705_08210_amd import campaign
+            host_out = np.empty(math.comb(n_v, 3), dtype=np.uint8)
+
+            def sink(st):
+                host_out[st.first:st.first + st.size] = st.u8.numpy()
+
+            def step(rec):   # noqa: F811 -- the campaign replaces the plain step
+                a = timer.mark() if rec else None
+                campaign.run3(Vd, args.campaign, sink, reduce="u8", acc=args.acc,
+                              tile=args.tile, path=args.path, levels=levels)
+                if rec:
+                    timer.add(a, timer.mark())
+            extra["campaign"] = {"stages": args.campaign, "output": "u8 to host",
+                                 "timed": "whole campaign (sums, pair numerators, stages, "
+                                          "quantize, device-to-host copies, host sink)"}
+
         cmp = n_f * math.comb(n_v, 3)
         use_mfma = V.dtype == np.uint8 and (args.path in ("mfma", "mfma_fp4") or
                                             (args.path == "auto" and 1 <= levels <= 15))
@@ -421,14 +448,15 @@ def main(argv=None):
             dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
             kernel = "ps_mg3_kernel"
         else:
-            dtype = "f16" if V.dtype == np.float16 else "f32"
+            dtype = {np.dtype(np.float16): "f16", np.dtype(np.float64): "f64"}.get(V.dtype, "f32")
             bound = "alu"
-            ops_per_cmp, peak = ((1.0, HALF_RATE_OPS_TOPS) if dtype == "f16"
-                                 else (2.0, FP32_LANE_OPS_TOPS))
+            ops_per_cmp, peak = {"f16": (1.0, HALF_RATE_OPS_TOPS),
+                                 "f64": (2.0, HALF_RATE_OPS_TOPS)}.get(dtype,
+                                                                    (2.0, FP32_LANE_OPS_TOPS))
             kernel = "ps_mg3_kernel"
         config = {"workload": wl, "way": 3, "n_f": n_f, "n_v": n_v}
         cpu = (lambda: cpu_baseline_triples(V, n_f, args.cpu_seconds))
-        parity_fn = ("triples", V)
+        parity_fn = ("triples", V) if args.campaign == 0 else None
     elif wl == "batched_64_uneven":
         Vs_np = workloads.batched_64_uneven(0)
         Vs = [torch.from_numpy(x).to(dev) for x in Vs_np]

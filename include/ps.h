@@ -68,7 +68,11 @@ typedef enum {
 typedef enum {
     PS_F32 = 0,   /* float;   FP32 min, FP32 accumulation                     */
     PS_F16 = 1,   /* _Float16; packed FP16 min, FP32 accumulation             */
-    PS_U8 = 2     /* uint8 integer levels; exact integer arithmetic           */
+    PS_U8 = 2,    /* uint8 integer levels; exact integer arithmetic           */
+    PS_F64 = 3    /* double;  FP64 min, FP64 accumulation (the paper's
+                     double-precision build, Section 5); c2/c3 outputs are
+                     still float, raw numerators (n2) are double.  Not for
+                     the batched calls. */
 } ps_dtype;
 
 /* FP32 accumulation of the numerator sums (floating storage only). */

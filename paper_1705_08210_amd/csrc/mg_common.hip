@@ -28,6 +28,14 @@ __device__ __forceinline__ void sum_word(uint32_t w, double& acc, uint64_t& iacc
     }
 }
 
+// One FP64 element: its value and whether it is outside v >= 0 (negative
+// other than -0, NaN or Inf).
+__device__ __forceinline__ void sum_f64(uint64_t x, double& acc, int& bad) {
+    acc += __builtin_bit_cast(double, x);
+    bad += ((x & 0x7ff0000000000000ull) == 0x7ff0000000000000ull) |
+           (int)((x >> 63) & (x != 0x8000000000000000ull));
+}
+
 template <int DT>
 __device__ __forceinline__ void sum_row(const char* row, int64_t n_f, bool vec,
                                         double& acc, uint64_t& iacc, int& bad) {
@@ -39,19 +47,29 @@ __device__ __forceinline__ void sum_row(const char* row, int64_t n_f, bool vec,
         const int64_t full = nbytes / 16 * 16;
         for (int64_t b = (int64_t)lane * 16; b < full; b += 64 * 16) {
             const uint4 v = *(const uint4*)(row + b);
-            sum_word<DT>(v.x, acc, iacc, bad);
-            sum_word<DT>(v.y, acc, iacc, bad);
-            sum_word<DT>(v.z, acc, iacc, bad);
-            sum_word<DT>(v.w, acc, iacc, bad);
+            if constexpr (DT == PS_F64) {
+                sum_f64(((uint64_t)v.y << 32) | v.x, acc, bad);
+                sum_f64(((uint64_t)v.w << 32) | v.z, acc, bad);
+            } else {
+                sum_word<DT>(v.x, acc, iacc, bad);
+                sum_word<DT>(v.y, acc, iacc, bad);
+                sum_word<DT>(v.z, acc, iacc, bad);
+                sum_word<DT>(v.w, acc, iacc, bad);
+            }
         }
         done = full / ESZ;
     }
-    for (int64_t q = done + lane; q < n_f; q += 64) {
-        uint32_t w;
-        if (ESZ == 4) w = *(const uint32_t*)(row + 4 * q);
-        else if (ESZ == 2) w = *(const unsigned short*)(row + 2 * q);
-        else w = *(const unsigned char*)(row + q);
-        sum_word<DT>(w, acc, iacc, bad);  // zero upper parts contribute 0
+    if constexpr (DT == PS_F64) {   // whole 8-byte elements
+        for (int64_t q = done + lane; q < n_f; q += 64)
+            sum_f64(*(const uint64_t*)(row + 8 * q), acc, bad);
+    } else {
+        for (int64_t q = done + lane; q < n_f; q += 64) {
+            uint32_t w;
+            if (ESZ == 4) w = *(const uint32_t*)(row + 4 * q);
+            else if (ESZ == 2) w = *(const unsigned short*)(row + 2 * q);
+            else w = *(const unsigned char*)(row + q);
+            sum_word<DT>(w, acc, iacc, bad);  // zero upper parts contribute 0
+        }
     }
 }
 
@@ -130,6 +148,7 @@ hipError_t launch_sums(const void* V, int32_t dt, int64_t n_f, int64_t n_v, int6
     case PS_F32: hipLaunchKernelGGL(ps_sums_kernel<PS_F32>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
     case PS_F16: hipLaunchKernelGGL(ps_sums_kernel<PS_F16>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
     case PS_U8:  hipLaunchKernelGGL(ps_sums_kernel<PS_U8>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
+    case PS_F64: hipLaunchKernelGGL(ps_sums_kernel<PS_F64>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

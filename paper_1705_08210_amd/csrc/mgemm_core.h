@@ -7,6 +7,7 @@
 //   PS_U8 : op = |a - b| summed four bytes at a time (v_sad_u8); the pair
 //           numerator follows from min(a,b) = (a + b - |a-b|) / 2.
 //   PS_B1 : binary fields, 32 per word; op = popcount(a AND b).
+//   PS_F64: op = FP64 min, FP64 accumulation, on 64-bit words.
 // For the 3-way slices (Section 3.2) the A operand is X_j = min(V, v_j),
 // formed while the field tile is staged into LDS.
 //
@@ -42,6 +43,7 @@ template <int DT> struct Ops;
 
 template <> struct Ops<PS_F32> {
     using Acc = float;
+    using Word = uint32_t;
     static constexpr int kEsz = 4;
     __device__ __forceinline__ static float step(float acc, uint32_t a, uint32_t b) {
         return acc + __builtin_fminf(as_f32(a), as_f32(b));
@@ -53,6 +55,7 @@ template <> struct Ops<PS_F32> {
 
 template <> struct Ops<PS_F16> {
     using Acc = float;
+    using Word = uint32_t;
     static constexpr int kEsz = 2;
     __device__ __forceinline__ static float step(float acc, uint32_t a, uint32_t b) {
         const h2_t one = {(_Float16)1.0f, (_Float16)1.0f};
@@ -67,6 +70,7 @@ template <> struct Ops<PS_F16> {
 
 template <> struct Ops<PS_U8> {
     using Acc = uint32_t;
+    using Word = uint32_t;
     static constexpr int kEsz = 1;
     __device__ __forceinline__ static uint32_t step(uint32_t acc, uint32_t a, uint32_t b) {
         return __builtin_amdgcn_sad_u8(a, b, acc);
@@ -86,6 +90,7 @@ template <> struct Ops<PS_U8> {
 // pair contributes the population count of its AND (v_and + v_bcnt).
 template <> struct Ops<PS_B1> {
     using Acc = uint32_t;
+    using Word = uint32_t;
     static constexpr int kEsz = 4;   // the kernels' "element" is one packed word
     __device__ __forceinline__ static uint32_t step(uint32_t acc, uint32_t a, uint32_t b) {
         return acc + (uint32_t)__builtin_popcount(a & b);
@@ -93,14 +98,44 @@ template <> struct Ops<PS_B1> {
     __device__ __forceinline__ static uint32_t xmin(uint32_t a, uint32_t b) { return a & b; }
 };
 
+// FP64 data: one element per 64-bit word, FP64 min and add.
+template <> struct Ops<PS_F64> {
+    using Acc = double;
+    using Word = uint64_t;
+    static constexpr int kEsz = 8;
+    __device__ __forceinline__ static double step(double acc, uint64_t a, uint64_t b) {
+        return acc + __builtin_fmin(__builtin_bit_cast(double, a), __builtin_bit_cast(double, b));
+    }
+    __device__ __forceinline__ static uint64_t xmin(uint64_t a, uint64_t b) {
+        return __builtin_bit_cast(uint64_t, __builtin_fmin(__builtin_bit_cast(double, a),
+                                                           __builtin_bit_cast(double, b)));
+    }
+};
+
+// X_j staging of one 16-byte chunk: each word replaced by its min with the
+// matching word of v_j.
+template <int DT>
+__device__ __forceinline__ uint4 xmin_chunk(uint4 v, uint4 x) {
+    if constexpr (sizeof(typename Ops<DT>::Word) == 8) {
+        const uint64_t lo = Ops<DT>::xmin(((uint64_t)v.y << 32) | v.x, ((uint64_t)x.y << 32) | x.x);
+        const uint64_t hi = Ops<DT>::xmin(((uint64_t)v.w << 32) | v.z, ((uint64_t)x.w << 32) | x.z);
+        return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    } else {
+        return make_uint4(Ops<DT>::xmin(v.x, x.x), Ops<DT>::xmin(v.y, x.y),
+                          Ops<DT>::xmin(v.z, x.z), Ops<DT>::xmin(v.w, x.w));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Staging of one field tile of BM rows into registers, then into LDS laid out
-// word-major: S[w * (BM + 4) + row].  Chunks are 16 bytes; chunk index runs
-// row-fastest so the transposing LDS writes of a wave hit distinct banks.
+// word-major: S[w * (BM + 4) + row], words of 4 bytes (8 for FP64).  Chunks
+// are 16 bytes; chunk index runs row-fastest so the transposing LDS writes of
+// a wave hit distinct banks.
 // ---------------------------------------------------------------------------
-template <int BM, int BKW>
+template <int BM, int BKW, typename Word = uint32_t>
 struct Stager {
-    static constexpr int kCpr = BKW / 4;                 // chunks per row
+    static constexpr int kWpc = 16 / (int)sizeof(Word);  // words per chunk
+    static constexpr int kCpr = BKW / kWpc;              // chunks per row
     static constexpr int kCh = BM * kCpr / kThreads;     // chunks per thread
     static constexpr int kLd = BM + 4;                   // LDS row pitch (words)
     static_assert(BM * kCpr % kThreads == 0, "tile not divisible");
@@ -110,12 +145,19 @@ struct Stager {
     // on a row that is not 16-byte aligned, element by element (zero fill).
     template <int ESZ>
     __device__ __forceinline__ static uint4 load_slow(const char* p, int64_t nbytes_left) {
-        union { uint4 v; unsigned char b[16]; unsigned short h[8]; uint32_t w[4]; } u;
+        union {
+            uint4 v;
+            unsigned char b[16];
+            unsigned short h[8];
+            uint32_t w[4];
+            uint64_t d[2];
+        } u;
         u.v = make_uint4(0, 0, 0, 0);
 #pragma unroll
         for (int e = 0; e < 16 / ESZ; ++e) {
             if ((int64_t)e * ESZ < nbytes_left) {
-                if (ESZ == 4) u.w[e] = *(const uint32_t*)(p + 4 * e);
+                if (ESZ == 8) u.d[e] = *(const uint64_t*)(p + 8 * e);
+                else if (ESZ == 4) u.w[e] = *(const uint32_t*)(p + 4 * e);
                 else if (ESZ == 2) u.h[e] = *(const unsigned short*)(p + 2 * e);
                 else u.b[e] = *(const unsigned char*)(p + e);
             }
@@ -148,28 +190,27 @@ struct Stager {
             const int64_t b0 = kb0 + ch * 16;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (grow < row_end) v = load_chunk<ESZ>(Vb + grow * ldb, b0, nbytes, vec);
-            if (XJ) {
-                const uint4 x = load_chunk<ESZ>(xrow, b0, nbytes, vec);
-                v.x = Ops<DT>::xmin(v.x, x.x);
-                v.y = Ops<DT>::xmin(v.y, x.y);
-                v.z = Ops<DT>::xmin(v.z, x.z);
-                v.w = Ops<DT>::xmin(v.w, x.w);
-            }
+            if (XJ) v = xmin_chunk<DT>(v, load_chunk<ESZ>(xrow, b0, nbytes, vec));
             r[c] = v;
         }
     }
 
-    __device__ __forceinline__ void store(uint32_t* S) const {
+    __device__ __forceinline__ void store(Word* S) const {
 #pragma unroll
         for (int c = 0; c < kCh; ++c) {
             const int idx = threadIdx.x + c * kThreads;
             const int row = idx % BM;
             const int ch = idx / BM;
-            uint32_t* w = S + (ch * 4) * kLd + row;
-            w[0] = r[c].x;
-            w[kLd] = r[c].y;
-            w[2 * kLd] = r[c].z;
-            w[3 * kLd] = r[c].w;
+            Word* w = S + (ch * kWpc) * kLd + row;
+            if constexpr (sizeof(Word) == 8) {
+                w[0] = ((uint64_t)r[c].y << 32) | r[c].x;
+                w[kLd] = ((uint64_t)r[c].w << 32) | r[c].z;
+            } else {
+                w[0] = r[c].x;
+                w[kLd] = r[c].y;
+                w[2 * kLd] = r[c].z;
+                w[3 * kLd] = r[c].w;
+            }
         }
     }
 };
@@ -195,13 +236,16 @@ template <int DT, int TM, int TN, int BKW, bool XJ>
 __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nbytes,
                                          bool vec, int64_t a_row0, int64_t a_end,
                                          int64_t b_row0, int64_t b_end, const char* xrow,
-                                         bool active, uint32_t* As, uint32_t* Bs,
+                                         bool active, typename Ops<DT>::Word* As,
+                                         typename Ops<DT>::Word* Bs,
                                          typename Ops<DT>::Acc (&acc)[TM][TN],
                                          int64_t kt0 = 0, int64_t kt1 = -1) {
     using Acc = typename Ops<DT>::Acc;
+    using Word = typename Ops<DT>::Word;
     constexpr int BM = 16 * TM, BN = 16 * TN;
-    using SA = Stager<BM, BKW>;
-    using SB = Stager<BN, BKW>;
+    using SA = Stager<BM, BKW, Word>;
+    using SB = Stager<BN, BKW, Word>;
+    constexpr int kV = (int)sizeof(Word) / 4;   // 16-byte reads per 4 consecutive words
     const int wave = threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
     const int lx = lane % 8, ly = lane / 8;
@@ -213,7 +257,7 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
 #pragma unroll
         for (int c = 0; c < TN; ++c) acc[r][c] = Acc(0);
 
-    const int64_t tile_bytes = (int64_t)BKW * 4;
+    const int64_t tile_bytes = (int64_t)BKW * (int64_t)sizeof(Word);
     const int64_t nk_all = (nbytes + tile_bytes - 1) / tile_bytes;
     const int64_t nk = kt1 < 0 || kt1 > nk_all ? nk_all : kt1;
     // 2-way tiles prefetch the next field tile into registers while
@@ -247,13 +291,17 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
         constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
 #pragma unroll kUnroll
         for (int w = 0; w < BKW; ++w) {
-            uint32_t a[TM], b[TN];
+            Word a[TM], b[TN];
 #pragma unroll
             for (int g = 0; g < TM / 4; ++g)
-                *(uint4*)&a[4 * g] = *(const uint4*)&As[w * SA::kLd + ar + g * 32];
+#pragma unroll
+                for (int h = 0; h < kV; ++h)
+                    ((uint4*)&a[4 * g])[h] = ((const uint4*)&As[w * SA::kLd + ar + g * 32])[h];
 #pragma unroll
             for (int g = 0; g < TN / 4; ++g)
-                *(uint4*)&b[4 * g] = *(const uint4*)&Bs[w * SB::kLd + bc + g * 32];
+#pragma unroll
+                for (int h = 0; h < kV; ++h)
+                    ((uint4*)&b[4 * g])[h] = ((const uint4*)&Bs[w * SB::kLd + bc + g * 32])[h];
 #pragma unroll
             for (int r = 0; r < TM; ++r)
 #pragma unroll
@@ -317,6 +365,9 @@ __device__ __forceinline__ void epilogue2(const typename Ops<DT>::Acc (&acc)[TM]
             } else if constexpr (DT == PS_B1) {
                 num = (double)acc[r][c];
                 if (n2) ((int32_t*)n2)[idx] = (int32_t)acc[r][c];
+            } else if constexpr (DT == PS_F64) {
+                num = acc[r][c];
+                if (n2) ((double*)n2)[idx] = acc[r][c];
             } else {
                 num = (double)acc[r][c];
                 if (n2) ((float*)n2)[idx] = acc[r][c];

@@ -40,8 +40,9 @@ template <int DT, int TM, int BKW>
 __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launch a, int64_t ntiles) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
-    __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
-    __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
+    using Word = typename Ops<DT>::Word;
+    __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
+    __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
     // work item = (field chunk, tile), chunk-major
     const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
     if (w >= ntiles * a.nchunks) return;
@@ -65,11 +66,14 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
                                               col0, a.n_v, nullptr, active, As, Bs, acc,
                                               kt0, kt1);
     if (!active) return;
-    if (a.nchunks > 1)
-        store_pairs_raw<DT, TM, TM>(acc, row0, col0, a.n_v,
-                                    (uint32_t*)a.partial + chunk * (a.n_v * (a.n_v - 1) / 2));
-    else
-        epilogue2<DT, TM, TM>(acc, row0, col0, a.n_v, a.s, a.c2, a.n2);
+    if constexpr (DT != PS_F64) {   // FP64 sums are never split over field chunks
+        if (a.nchunks > 1) {
+            store_pairs_raw<DT, TM, TM>(acc, row0, col0, a.n_v,
+                                        (uint32_t*)a.partial + chunk * (a.n_v * (a.n_v - 1) / 2));
+            return;
+        }
+    }
+    epilogue2<DT, TM, TM>(acc, row0, col0, a.n_v, a.s, a.c2, a.n2);
 }
 
 // ---------------------------------------------------------------------------
@@ -98,7 +102,10 @@ __device__ __forceinline__ void store_slice(const typename Ops<DT>::Acc (&acc)[T
         for (int c = 0; c < TN; ++c) {
             const int64_t k = col0 + lane_col<TN>(wave, ly, c);
             if (k >= a.n_v) continue;
-            out[base + (k - j - 1) * j + i] = __builtin_bit_cast(uint32_t, acc[r][c]);
+            if constexpr (DT == PS_F64)   // FP64 raw sums go to a double array
+                ((double*)out)[base + (k - j - 1) * j + i] = acc[r][c];
+            else
+                out[base + (k - j - 1) * j + i] = __builtin_bit_cast(uint32_t, acc[r][c]);
         }
     }
 }
@@ -107,8 +114,9 @@ template <int DT, int TM, int BKW>
 __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launch a) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
-    __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
-    __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
+    using Word = typename Ops<DT>::Word;
+    __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
+    __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
     const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
     if (w >= a.ntiles * a.nchunks) return;
     const int64_t chunk = w / a.ntiles, t = w % a.ntiles;
@@ -137,7 +145,8 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
                                              row0, j, col0, a.n_v, Vb + j * ldb, active,
                                              As, Bs, acc, kt0, kt1);
     if (active) {
-        uint32_t* dst = a.nchunks > 1
+        uint32_t* dst = DT == PS_F64 ? (uint32_t*)a.partial   // stage doubles, never split
+                        : a.nchunks > 1
                             ? (uint32_t*)a.partial +
                                   chunk * (slab_offset(a.n_v, a.j_end) - slab_offset(a.n_v, a.j_begin))
                             : (uint32_t*)a.c3;
@@ -151,7 +160,9 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
 // c3 = (3 n3) / (2 d3) in FP64, rounded once to FP32.
 template <int DT>
 __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
-    using N2T = typename std::conditional<DT == PS_U8 || DT == PS_B1, int32_t, float>::type;
+    using N2T = typename std::conditional<
+        DT == PS_U8 || DT == PS_B1, int32_t,
+        typename std::conditional<DT == PS_F64, double, float>::type>::type;
     const int64_t j = a.j_begin + blockIdx.x;
     if (j >= a.j_end) return;
     const N2T* N2 = (const N2T*)a.n2;
@@ -164,7 +175,7 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
     const int64_t stage = slab_offset(n_v, a.j_end) - slab_offset(n_v, a.j_begin);
     for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
         const int64_t k = j + 1 + t / j, i = t % j;
-        const uint32_t raw = a.nchunks > 1 ? 0u : io[base + t];
+        const uint32_t raw = (a.nchunks > 1 || DT == PS_F64) ? 0u : io[base + t];
         const double nij = (double)N2[nj + i];
         const double nik = (double)N2[k * (k - 1) / 2 + i];
         const double njk = (double)N2[k * (k - 1) / 2 + j];
@@ -176,6 +187,8 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
             n3p = (double)(((int64_t)nij + (int64_t)sk - (int64_t)raw) / 2);
         } else if constexpr (DT == PS_B1) {
             n3p = (double)raw;   // popcount(v_i AND v_j AND v_k), never split
+        } else if constexpr (DT == PS_F64) {
+            n3p = ((const double*)a.partial)[base + t];   // FP64 raw sums, never split
         } else if (a.nchunks > 1) {  // chunks of the field split, in FP64
             n3p = 0.0;
             for (int c = 0; c < a.nchunks; ++c) n3p += (double)a.partial[c * stage + base + t];
@@ -219,8 +232,9 @@ template <int DT, int TM, int BKW>
 __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchLaunch a) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
-    __shared__ __attribute__((aligned(16))) uint32_t As[BKW * (BM + 4)];
-    __shared__ __attribute__((aligned(16))) uint32_t Bs[BKW * (BM + 4)];
+    using Word = typename Ops<DT>::Word;
+    __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
+    __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
     const int64_t t = run_remap(blockIdx.x);
     if (t >= a.ntiles) return;
     const int wave = threadIdx.x / 64;

@@ -45,6 +45,7 @@ int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
                 n_f < it->nf_hi && n_v >= it->nv_lo && n_v < it->nv_hi)
                 return it->idx;
     }
+    if (dt == PS_F64) return 1;   // 64x64 tiles: the 128x128 FP64 tiles need >= 256 registers
     return default_cfg(way, n_v);
 }
 
@@ -57,20 +58,21 @@ int choose_acc(int64_t n_f, const ps_opts* o) {
 // Number of field chunks of the blocked (split) accumulation; 1 = no split.
 // kChunkFields is a multiple of every configuration's field-tile depth.
 int32_t split_chunks(int32_t dt, int64_t n_f, int acc) {
-    if (dt == PS_U8 || acc != PS_ACC_BLOCKED) return 1;
+    if (dt == PS_U8 || dt == PS_F64 || acc != PS_ACC_BLOCKED) return 1;   // exact or FP64
     const int64_t n = ceil_div(n_f, kChunkFields);
     return n > 1 ? (int32_t)n : 1;
 }
 
+// Field tiles per chunk: a field tile is bkw words of word_bytes(dt) bytes.
 int64_t chunk_tiles(int32_t dt, int cfg) {
-    return kChunkFields / ((int64_t)kValuCfgs[cfg].bkw * (4 / elem_size(dt)));
+    return kChunkFields / ((int64_t)kValuCfgs[cfg].bkw * word_bytes(dt) / elem_size(dt));
 }
 
 // Field-chunk plan of a 2-way launch (see Split in ps_internal.h).
 Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o) {
     Split sp{split_chunks(dt, n_f, choose_acc(n_f, o)), chunk_tiles(dt, cfg)};
     const int acc_req = o ? o->acc : PS_ACC_AUTO;
-    if (dt == PS_U8 || acc_req != PS_ACC_AUTO || n_v < 2) return sp;
+    if (dt == PS_U8 || dt == PS_F64 || acc_req != PS_ACC_AUTO || n_v < 2) return sp;
     const int64_t ftiles = ceil_div(n_f * elem_size(dt), (int64_t)kValuCfgs[cfg].bkw * 4);
     const int64_t tiles = tri_tiles(n_v, kValuCfgs[cfg].bm());
     if (tiles * sp.nchunks >= kMinItems) return sp;
@@ -120,10 +122,9 @@ int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx, in
                        int32_t* bn, int32_t* bk) {
     if (elem_size(dtype) == 0 || (way != 2 && way != 3) || is_mfma(path)) return 0;
     if (idx >= 0 && idx < kNumValuCfgs) {
-        const int fpw = 4 / elem_size(dtype);  // fields per 32-bit word
         if (bm) *bm = kValuCfgs[idx].bm();
         if (bn) *bn = kValuCfgs[idx].bn();
-        if (bk) *bk = kValuCfgs[idx].bkw * fpw;
+        if (bk) *bk = kValuCfgs[idx].bkw * word_bytes(dtype) / elem_size(dtype);  // fields
     }
     return kNumValuCfgs;
 }

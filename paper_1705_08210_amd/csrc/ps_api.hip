@@ -83,6 +83,7 @@ static hipError_t launch_mg2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
     case PS_F32: return launch_mg2_f32(a, st);
     case PS_F16: return launch_mg2_f16(a, st);
     case PS_B1: return launch_mg2_b1(a, st);
+    case PS_F64: return launch_mg2_f64(a, st);
     default: return launch_mg2_u8(a, st);
     }
 }
@@ -92,6 +93,7 @@ static hipError_t launch_mg3(int32_t dt, const Mg3Launch& a, hipStream_t st) {
     case PS_F32: return launch_mg3_f32(a, st);
     case PS_F16: return launch_mg3_f16(a, st);
     case PS_B1: return launch_mg3_b1(a, st);
+    case PS_F64: return launch_mg3_f64(a, st);
     default: return launch_mg3_u8(a, st);
     }
 }
@@ -260,8 +262,9 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
 
 // The field-split partials of the pair prepass and of the slices run one
 // after the other on the stream and share one region.
-static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t nchunks2,
-                         int32_t nchunks3, int64_t stage, size_t packed_bytes, void* ws,
+static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int n2_bytes,
+                         int32_t nchunks2, int32_t nchunks3, int64_t stage, size_t packed_bytes,
+                         void* ws,
                          double** s_ws, void** n2_ws, int64_t** prefix, float** partial,
                          uint32_t** packed) {
     Carver c(ws);
@@ -271,10 +274,11 @@ static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int32_t
     if (packed) *packed = packed_bytes ? (uint32_t*)c.take(packed_bytes) : nullptr;
     else if (packed_bytes) c.take(packed_bytes);
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
-    if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * 4);
+    if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * (size_t)n2_bytes);
     int64_t* pre = (int64_t*)c.take((size_t)(n_v + 1) * sizeof(int64_t));
     const int64_t need2 = (!n2_given && nchunks2 > 1) ? nchunks2 * (n_v * (n_v - 1) / 2) : 0;
-    const int64_t need3 = nchunks3 > 1 ? nchunks3 * stage : 0;
+    // floats of the slice sums: FP32 chunk partials, or (nchunks3 < 0) FP64 raw sums
+    const int64_t need3 = nchunks3 < 0 ? 2 * stage : nchunks3 > 1 ? nchunks3 * stage : 0;
     if (need2 > 0 || need3 > 0)
         part = (float*)c.take((size_t)(need2 > need3 ? need2 : need3) * sizeof(float));
     if (s_ws) *s_ws = s;
@@ -298,7 +302,7 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
     int64_t* prefix = nullptr;
     float* partial = nullptr;
     uint32_t* planes = nullptr;
-    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, 1, 1, stage,
+    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, 4, 1, 1, stage,
                                    mfma_workspace_bytes(n_f, n_v, levels, fmt), workspace,
                                    &s_ws, &n2_ws, &prefix, &partial, &planes);
     if (ws_bytes < need || !workspace)
@@ -335,19 +339,19 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (j_end > n_v - 1) j_end = n_v - 1;
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
     if (is_bits(opts))
-        return ws3_layout(n_v, s_given, n2_given, 1, 1, stage, bits_bytes(n_f, n_v), nullptr,
+        return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage, bits_bytes(n_f, n_v), nullptr,
                           nullptr, nullptr, nullptr, nullptr, nullptr);
     const int path = choose_path(dtype, opts);
     if (is_mfma(path) && dtype == PS_U8)
-        return ws3_layout(n_v, s_given, n2_given, 1, 1, stage,
+        return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage,
                           mfma_workspace_bytes(n_f, n_v, opts ? opts->levels : 0,
                                                path == PS_PATH_MFMA_FP4 ? 1 : 0),
                           nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     const Split sp2 =
         plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
-    return ws3_layout(n_v, s_given, n2_given, sp2.nchunks,
-                      split_chunks(dtype, n_f, choose_acc(n_f, opts)), stage, 0, nullptr, nullptr,
-                      nullptr, nullptr, nullptr, nullptr);
+    return ws3_layout(n_v, s_given, n2_given, dtype == PS_F64 ? 8 : 4, sp2.nchunks,
+                      dtype == PS_F64 ? -1 : split_chunks(dtype, n_f, choose_acc(n_f, opts)),
+                      stage, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 ps_status ps_quantize_u8(const float* c, int64_t n, uint8_t* q, hipStream_t stream) {
@@ -426,7 +430,8 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     const int32_t nchunks = bits ? 1 : split_chunks(dtype, n_f, choose_acc(n_f, opts));
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
     uint32_t* packed = nullptr;
-    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, sp2.nchunks, nchunks, stage,
+    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, dtype == PS_F64 ? 8 : 4,
+                                   sp2.nchunks, dtype == PS_F64 ? -1 : nchunks, stage,
                                    bits ? bits_bytes(n_f, n_v) : 0, workspace, &s_ws, &n2_ws,
                                    &prefix, &partial, &packed);
     if (ws_bytes < need || !workspace)
@@ -531,8 +536,9 @@ static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, con
     if (n > 0 && !probs) return fail(PS_ERR_ARG, "probs is NULL");
     ps_status st = check_opts(o);
     if (st != PS_OK) return st;
-    if (o && is_mfma(o->path))
+    if (o && (is_mfma(o->path) || o->path == PS_PATH_BITS))
         return fail(PS_ERR_UNSUPPORTED, "batched runs on the VALU path only");
+    if (dt == PS_F64) return fail(PS_ERR_UNSUPPORTED, "batched calls take F32, F16 or U8 data");
     for (int32_t i = 0; i < n; ++i) {
         const ps_problem& p = probs[i];
         st = check_matrix(p.V, dt, p.n_f, p.n_v, p.ld);

@@ -21,13 +21,16 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Element size in bytes of a storage type (0 if unknown).
 inline int elem_size(int32_t dt) {
-    return dt == PS_F32 ? 4 : dt == PS_F16 ? 2 : dt == PS_U8 ? 1 : 0;
+    return dt == PS_F32 ? 4 : dt == PS_F16 ? 2 : dt == PS_U8 ? 1 : dt == PS_F64 ? 8 : 0;
 }
 
 // Internal operand type of the BITS path (never a public ps_dtype): binary
 // data packed 32 fields to a 32-bit word, bit e of word w = field 32 w + e.
-constexpr int32_t PS_B1 = 3;
+constexpr int32_t PS_B1 = 4;
 constexpr int kBitsPerWord = 32;
+// Bytes of the words the VALU tile kernels stage and compute on: 8 for
+// FP64 (one element), 4 otherwise (1, 2 or 4 elements, or 32 packed bits).
+inline int word_bytes(int32_t dt) { return dt == PS_F64 ? 8 : 4; }
 // Packed row length in words: whole 16-byte chunks.
 inline int64_t bits_row_words(int64_t n_f) { return ceil_div(ceil_div(n_f, kBitsPerWord), 4) * 4; }
 
@@ -140,8 +143,8 @@ struct Mg3Launch {
     int64_t ntiles;
     int cfg;
     int32_t nchunks;             // field-chunk split as for Mg2Launch; partial
-    int64_t chunk_tiles;         // holds nchunks * stage-size FP32 values
-    float* partial;
+    int64_t chunk_tiles;         // holds nchunks * stage-size FP32 values (for
+    float* partial;              // PS_F64: stage-size doubles of raw n3', no split)
 };
 
 // Device problem record of a batched launch.
@@ -187,6 +190,8 @@ hipError_t launch_mg3_f32(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_f16(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg2_b1(const Mg2Launch& a, hipStream_t st);
+hipError_t launch_mg2_f64(const Mg2Launch& a, hipStream_t st);
+hipError_t launch_mg3_f64(const Mg3Launch& a, hipStream_t st);
 hipError_t launch_mg3_b1(const Mg3Launch& a, hipStream_t st);
 // V (uint8 0/1, n_v rows of ld bytes, n_f fields) -> P (n_v rows of
 // bits_row_words(n_f) words), pad bits zero.

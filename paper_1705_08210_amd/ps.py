@@ -30,10 +30,11 @@ I32 = ctypes.c_int32
 I64 = ctypes.c_int64
 SZ = ctypes.c_size_t
 
-PS_F32, PS_F16, PS_U8 = 0, 1, 2
+PS_F32, PS_F16, PS_U8, PS_F64 = 0, 1, 2, 3
 ACC = {"auto": 0, "plain": 1, "blocked": 2}
 PATH = {"auto": 0, "valu": 1, "mfma": 2, "mfma_fp4": 3, "bits": 4}
-DTYPES = {torch.float32: PS_F32, torch.float16: PS_F16, torch.uint8: PS_U8}
+DTYPES = {torch.float32: PS_F32, torch.float16: PS_F16, torch.uint8: PS_U8,
+          torch.float64: PS_F64}
 
 
 class Opts(ctypes.Structure):
@@ -115,7 +116,7 @@ def _matrix(V: torch.Tensor):
     if not V.is_cuda:
         raise ValueError("V must be on a GPU (device memory)")
     if V.dtype not in DTYPES:
-        raise TypeError(f"unsupported dtype {V.dtype}; use float32, float16 or uint8")
+        raise TypeError(f"unsupported dtype {V.dtype}; use float32, float16, uint8 or float64")
     if V.shape[1] > 1 and V.stride(1) != 1:
         raise ValueError("the fields of a vector must be contiguous (V.stride(1) == 1)")
     n_v, n_f = V.shape
@@ -134,7 +135,9 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def n2_dtype(V_dtype) -> torch.dtype:
-    return torch.int32 if V_dtype == torch.uint8 else torch.float32
+    if V_dtype == torch.uint8:
+        return torch.int32
+    return torch.float64 if V_dtype == torch.float64 else torch.float32
 
 
 def vector_sums(V: torch.Tensor, out: torch.Tensor | None = None, want_bad: bool = True,
