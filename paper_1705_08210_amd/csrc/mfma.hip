@@ -286,7 +286,29 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t
                         }
                     }
             }
-            if (kt + 1 < nk) store(cur ^ 1);   // tile kt+1 into the other buffer
+            // tile kt+1 into the other buffer (after the last tile the write is
+            // stale and never read; unconditional, so it joins this block)
+            store(cur ^ 1);
+            // schedule (measured 5% faster on int8): the next k-step's fragment
+            // reads between the MFMAs of this one, the staging writes of the
+            // next field tile between the MFMAs of the last k-step
+            if constexpr (FMT == kFmtI8 && WN == 2 && kMK == 128) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+                for (int ks = 0; ks < kMK / 32 - 1; ++ks) {
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    }
+                    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                }
+            }
             __syncthreads();   // kt+1 visible; everyone is done reading kt
             if (kt + 2 < nk) load((kt + 2) * kMK);
         }
