@@ -139,6 +139,7 @@ struct MfmaArgs {
     int64_t j_begin, j_end;
     const int64_t* prefix;
     uint32_t* c3;
+    int64_t item0;        // first work item of this launch
 };
 
 // Wave w owns j rows [(w%2)*128, +128) and i columns [(w/2)*32*WN, +32*WN)
@@ -324,7 +325,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t
 template <int FMT, int WN>
 __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArgs a) {
     __shared__ __attribute__((aligned(16))) int8_t lds[mfma_lds_bytes<FMT, WN>()];
-    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                      blockIdx.x / kXcds;
     if (t >= a.ntiles) return;
     int64_t bi, bj;
     grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
@@ -354,7 +356,8 @@ template <int FMT>
 __global__ __launch_bounds__(mfma_threads<2>(), 1) void ps_mfma3_kernel(MfmaArgs a) {
     constexpr int WN = 2;
     __shared__ __attribute__((aligned(16))) int8_t lds[mfma_lds_bytes<FMT, WN>()];
-    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                      blockIdx.x / kXcds;
     if (t >= a.ntiles) return;
     // slab j: largest jj with prefix[jj] <= t (every slab has >= 1 tile)
     int64_t lo = 0, hi = a.j_end - a.j_begin;
@@ -434,7 +437,8 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_dma_kernel(Mfm
     using AccT = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
     __shared__ __attribute__((aligned(1024))) int8_t As[2 * kStageBytes];   // j rows
     __shared__ __attribute__((aligned(1024))) int8_t Bs[2 * kStageBytes];   // i rows
-    const int64_t t = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                      blockIdx.x / kXcds;
     if (t >= a.ntiles) return;
     int64_t bi, bj;
     grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
@@ -544,15 +548,17 @@ static hipError_t go_mfma2(const MfmaLaunch& m, hipStream_t st) {
     if (e != hipSuccess) return e;
     const int64_t nb = (m.n_v + kMB - 1) / kMB;
     const int64_t T = nb * (nb + 1) / 2;
-    MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T, 0, 0, nullptr, nullptr};
-    const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
-    if constexpr (FMT == kFmtF4 && WN == 2)
-        hipLaunchKernelGGL((ps_mfma2_dma_kernel<FMT, WN>), dim3((unsigned)grid),
-                           dim3(mfma_threads<WN>()), 0, st, a);
-    else
-        hipLaunchKernelGGL((ps_mfma2_kernel<FMT, WN>), dim3((unsigned)grid),
-                           dim3(mfma_threads<WN>()), 0, st, a);
-    return hipGetLastError();
+    MfmaArgs a{m.planes, kp, m.n_v, m.s, m.c2, (int32_t*)m.n2, nb, T, 0, 0, nullptr, nullptr, 0};
+    return launch_items(T, mfma_threads<WN>(), kXcds, [&](unsigned grid, int64_t item0) {
+        MfmaArgs b = a;
+        b.item0 = item0;
+        if constexpr (FMT == kFmtF4 && WN == 2)
+            hipLaunchKernelGGL((ps_mfma2_dma_kernel<FMT, WN>), dim3(grid),
+                               dim3(mfma_threads<WN>()), 0, st, b);
+        else
+            hipLaunchKernelGGL((ps_mfma2_kernel<FMT, WN>), dim3(grid), dim3(mfma_threads<WN>()),
+                               0, st, b);
+    });
 }
 
 template <int FMT>
@@ -565,11 +571,12 @@ static hipError_t go_mfma3(const MfmaLaunch& m, hipStream_t st) {
     const int64_t T = slab_tiles(m.n_v, m.j_begin, m.j_end, kMB, kMB);
     if (T == 0) return hipSuccess;
     MfmaArgs a{m.planes, kp, m.n_v, m.s, nullptr, nullptr, 0, T, m.j_begin, m.j_end, m.prefix,
-               (uint32_t*)m.c3};
-    const int64_t grid = (T + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(ps_mfma3_kernel<FMT>, dim3((unsigned)grid), dim3(mfma_threads<2>()), 0,
-                       st, a);
-    return hipGetLastError();
+               (uint32_t*)m.c3, 0};
+    return launch_items(T, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+        MfmaArgs b = a;
+        b.item0 = item0;
+        hipLaunchKernelGGL(ps_mfma3_kernel<FMT>, dim3(grid), dim3(mfma_threads<2>()), 0, st, b);
+    });
 }
 
 hipError_t launch_mfma3(const MfmaLaunch& m, hipStream_t st) {

@@ -1,5 +1,6 @@
 // mg_common.hip -- per-vector sums, the 3-way tile prefix, and small fill
 // kernels shared by the entry points.
+#include <algorithm>
 #include <type_traits>
 
 #include "mgemm_core.h"
@@ -85,19 +86,21 @@ __device__ __forceinline__ void wave_reduce(double& acc, uint64_t& iacc, int& ba
 template <int DT>
 __global__ __launch_bounds__(256) void ps_sums_kernel(const void* V, int64_t n_f, int64_t n_v,
                                                       int64_t ld, double* s, int32_t* bad) {
-    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    if (i >= n_v) return;  // whole waves leave together; no block barrier below
     constexpr int ESZ = Ops<DT>::kEsz;
-    const char* row = (const char*)V + i * ld * ESZ;
     const bool vec = ((uintptr_t)V % 16 == 0) && ((ld * ESZ) % 16 == 0);
-    double acc = 0.0;
-    uint64_t iacc = 0;
-    int nbad = 0;
-    sum_row<DT>(row, n_f, vec, acc, iacc, nbad);
-    wave_reduce(acc, iacc, nbad);
-    if (threadIdx.x % 64 == 0) {
-        s[i] = DT == PS_U8 ? (double)iacc : acc;
-        if (bad && nbad) atomicAdd(bad, nbad);
+    // one wave per vector, waves striding over the vectors (no block barrier)
+    for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64; i < n_v;
+         i += (int64_t)gridDim.x * 4) {
+        const char* row = (const char*)V + i * ld * ESZ;
+        double acc = 0.0;
+        uint64_t iacc = 0;
+        int nbad = 0;
+        sum_row<DT>(row, n_f, vec, acc, iacc, nbad);
+        wave_reduce(acc, iacc, nbad);
+        if (threadIdx.x % 64 == 0) {
+            s[i] = DT == PS_U8 ? (double)iacc : acc;
+            if (bad && nbad) atomicAdd(bad, nbad);
+        }
     }
 }
 
@@ -109,17 +112,18 @@ __global__ __launch_bounds__(256) void ps_batched_sums_kernel(const DevProblem* 
     const int p = blockIdx.y;
     if (!need_s[p]) return;
     const DevProblem pr = probs[p];
-    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    if (i >= pr.n_v) return;
     constexpr int ESZ = Ops<DT>::kEsz;
-    const char* row = (const char*)pr.V + i * pr.ld * ESZ;
     const bool vec = ((uintptr_t)pr.V % 16 == 0) && ((pr.ld * ESZ) % 16 == 0);
-    double acc = 0.0;
-    uint64_t iacc = 0;
-    int nbad = 0;
-    sum_row<DT>(row, pr.n_f, vec, acc, iacc, nbad);
-    wave_reduce(acc, iacc, nbad);
-    if (threadIdx.x % 64 == 0) ((double*)pr.s)[i] = DT == PS_U8 ? (double)iacc : acc;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64; i < pr.n_v;
+         i += (int64_t)gridDim.x * 4) {
+        const char* row = (const char*)pr.V + i * pr.ld * ESZ;
+        double acc = 0.0;
+        uint64_t iacc = 0;
+        int nbad = 0;
+        sum_row<DT>(row, pr.n_f, vec, acc, iacc, nbad);
+        wave_reduce(acc, iacc, nbad);
+        if (threadIdx.x % 64 == 0) ((double*)pr.s)[i] = DT == PS_U8 ? (double)iacc : acc;
+    }
 }
 
 __global__ void ps_zero_i32_kernel(int32_t* p, int64_t n) {
@@ -143,7 +147,8 @@ hipError_t launch_sums(const void* V, int32_t dt, int64_t n_f, int64_t n_v, int6
         if (e != hipSuccess) return e;
     }
     if (n_v == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n_v + 3) / 4));
+    // four vectors per block; large n_v strides (the dispatch size is 32-bit)
+    const dim3 grid((unsigned)std::min<int64_t>((n_v + 3) / 4, 1 << 20));
     switch (dt) {
     case PS_F32: hipLaunchKernelGGL(ps_sums_kernel<PS_F32>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
     case PS_F16: hipLaunchKernelGGL(ps_sums_kernel<PS_F16>, grid, dim3(256), 0, st, V, n_f, n_v, ld, s, bad); break;
@@ -157,7 +162,7 @@ hipError_t launch_sums(const void* V, int32_t dt, int64_t n_f, int64_t n_v, int6
 hipError_t launch_batched_sums(const DevProblem* probs, const int32_t* need_s, int32_t n,
                                int32_t dt, int64_t max_nv, hipStream_t st) {
     if (n <= 0 || max_nv <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((max_nv + 3) / 4), (unsigned)n);
+    const dim3 grid((unsigned)std::min<int64_t>((max_nv + 3) / 4, 1 << 16), (unsigned)n);
     switch (dt) {
     case PS_F32: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F32>, grid, dim3(256), 0, st, probs, need_s); break;
     case PS_F16: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F16>, grid, dim3(256), 0, st, probs, need_s); break;

@@ -37,14 +37,15 @@ __device__ __forceinline__ void store_pairs_raw(const typename Ops<DT>::Acc (&ac
 }
 
 template <int DT, int TM, int BKW>
-__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launch a, int64_t ntiles) {
+__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launch a, int64_t ntiles,
+                                                                      int64_t item0) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     using Word = typename Ops<DT>::Word;
     __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
     __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
-    // work item = (field chunk, tile), chunk-major
-    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+    // work item = (field chunk, tile), chunk-major; item0: this launch's first
+    const int64_t w = item0 + xcd_remap(blockIdx.x, gridDim.x);
     if (w >= ntiles * a.nchunks) return;
     const int64_t chunk = w / ntiles, t = w % ntiles;
     int64_t bi, bj;
@@ -111,13 +112,13 @@ __device__ __forceinline__ void store_slice(const typename Ops<DT>::Acc (&acc)[T
 }
 
 template <int DT, int TM, int BKW>
-__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launch a) {
+__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launch a, int64_t item0) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     using Word = typename Ops<DT>::Word;
     __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
     __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
-    const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t w = item0 + xcd_remap(blockIdx.x, gridDim.x);
     if (w >= a.ntiles * a.nchunks) return;
     const int64_t chunk = w / a.ntiles, t = w % a.ntiles;
     // slice j: largest jj with prefix[jj] <= t (every slice has >= 1 tile)
@@ -229,13 +230,14 @@ __device__ __forceinline__ int64_t run_remap(int64_t b) {
 }
 
 template <int DT, int TM, int BKW>
-__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchLaunch a) {
+__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchLaunch a,
+                                                                      int64_t item0) {
     using Acc = typename Ops<DT>::Acc;
     constexpr int BM = 16 * TM;
     using Word = typename Ops<DT>::Word;
     __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
     __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
-    const int64_t t = run_remap(blockIdx.x);
+    const int64_t t = item0 + run_remap(blockIdx.x);
     if (t >= a.ntiles) return;
     const int wave = threadIdx.x / 64;
     const BatchTile bt = a.tiles[t];
@@ -261,33 +263,33 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchL
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
-inline int64_t round_up_xcd(int64_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
 
 template <int DT, int TM, int BKW>
 hipError_t go_mg2(const Mg2Launch& a, hipStream_t st) {
     const int64_t T = tri_tiles(a.n_v, 16 * TM);
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL((ps_mg2_kernel<DT, TM, BKW>),
-                       dim3((unsigned)round_up_xcd(T * a.nchunks)), dim3(kThreads), 0, st, a, T);
-    return hipGetLastError();
+    return launch_items(T * a.nchunks, kThreads, kXcds, [&](unsigned grid, int64_t item0) {
+        hipLaunchKernelGGL((ps_mg2_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,
+                           T, item0);
+    });
 }
 
 template <int DT, int TM, int BKW>
 hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW>),
-                       dim3((unsigned)round_up_xcd(a.ntiles * a.nchunks)), dim3(kThreads), 0, st,
-                       a);
-    return hipGetLastError();
+    return launch_items(a.ntiles * a.nchunks, kThreads, kXcds, [&](unsigned grid, int64_t item0) {
+        hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,
+                           item0);
+    });
 }
 
 template <int DT, int TM, int BKW>
 hipError_t go_mgb(const MgBatchLaunch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    const int64_t grid = ceil_div(a.ntiles, kXcds * kRun) * (kXcds * kRun);
-    hipLaunchKernelGGL((ps_mgb_kernel<DT, TM, BKW>), dim3((unsigned)grid), dim3(kThreads), 0,
-                       st, a);
-    return hipGetLastError();
+    return launch_items(a.ntiles, kThreads, kXcds * kRun, [&](unsigned grid, int64_t item0) {
+        hipLaunchKernelGGL((ps_mgb_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,
+                           item0);
+    });
 }
 
 }  // namespace ps

@@ -2,6 +2,8 @@
 // the tuning table that overrides the defaults, the accumulation mode and
 // field-chunk split, and the path choice.  The kernels' work and traffic
 // follow from these choices and from the kernel sources alone.
+#include <stdlib.h>
+
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -100,6 +102,18 @@ int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o) {
         if (it->dt == dt && it->way == 0 && nf >= it->nf_lo && nf < it->nf_hi)
             return it->idx;
     return 2;
+}
+
+int64_t max_grid_blocks(int threads, int64_t multiple) {
+    static const int64_t env_cap = [] {
+        const char* e = getenv("PS_MAX_GRID_BLOCKS");
+        const long long v = e ? atoll(e) : 0;
+        return v > 0 ? (int64_t)v : (int64_t)0;
+    }();
+    int64_t cap = (int64_t)0xffffffffu / threads;
+    if (env_cap > 0 && env_cap < cap) cap = env_cap;
+    cap = cap / multiple * multiple;
+    return cap > 0 ? cap : multiple;
 }
 
 bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4; }

@@ -24,6 +24,30 @@ inline int elem_size(int32_t dt) {
     return dt == PS_F32 ? 4 : dt == PS_F16 ? 2 : dt == PS_U8 ? 1 : dt == PS_F64 ? 8 : 0;
 }
 
+// Blocks of one launch: the dispatch size in work-items is a 32-bit number,
+// so a launch holds at most (2^32 - 1) / threads blocks; the result is also
+// a multiple of `multiple` (the block-to-work remaps need whole rounds of
+// XCDs).  The environment variable PS_MAX_GRID_BLOCKS, read once, lowers the
+// cap (a testing aid: it makes small problems take the multi-launch path).
+int64_t max_grid_blocks(int threads, int64_t multiple);
+
+// Launches `total` work items, one block each, in as few launches as the
+// dispatch size allows; launch(grid, item0) enqueues one of them.  Every grid
+// is a multiple of `multiple`.
+template <class Launch>
+hipError_t launch_items(int64_t total, int threads, int64_t multiple, Launch launch) {
+    const int64_t cap = max_grid_blocks(threads, multiple);
+    for (int64_t item0 = 0; item0 < total; item0 += cap) {
+        const int64_t left = total - item0;
+        const int64_t grid = left < cap ? ceil_div(left, multiple) * multiple : cap;
+        launch((unsigned)grid, item0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+
 // Internal operand type of the BITS path (never a public ps_dtype): binary
 // data packed 32 fields to a 32-bit word, bit e of word w = field 32 w + e.
 constexpr int32_t PS_B1 = 4;
