@@ -43,6 +43,10 @@
  *    unspecified.
  *  - Thread safety: calls may be made from several host threads; calls that
  *    share a workspace buffer must be ordered by the caller.
+ *  - Work lists longer than one dispatch allows (2^32 work-items) are split
+ *    over several launches on the same stream.  The environment variable
+ *    PS_MAX_GRID_BLOCKS (read once per process, a testing aid) lowers the
+ *    blocks per launch so that small problems take that path too.
  */
 #ifndef PS_H
 #define PS_H
