@@ -221,7 +221,7 @@ def _batch_outputs(Vs, want_n2=False):
 
 
 def ps2_batched(Vs, outs=None, acc="auto", tile=0, want_n2=False, stream=None):
-    """Many independent 2-way problems in one persistent launch.  Returns the
+    """Many independent 2-way problems in one launch.  Returns the
     list of (c2, n2, s) tuples (s is None: sums computed inside)."""
     if outs is None:
         outs = _batch_outputs(Vs, want_n2)

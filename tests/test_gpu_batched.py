@@ -1,4 +1,4 @@
-"""Batched 2-way: many uneven problems in one persistent launch (and as a
+"""Batched 2-way: many uneven problems in one launch (and as a
 captured plan) against one launch per problem and against the oracle."""
 
 import numpy as np
