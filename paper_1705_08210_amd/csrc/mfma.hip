@@ -29,6 +29,7 @@
 
 namespace ps {
 
+typedef unsigned v4u_t __attribute__((ext_vector_type(4)));
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef int v8i_t __attribute__((ext_vector_type(8)));
 typedef int v16i_t __attribute__((ext_vector_type(16)));
@@ -60,8 +61,12 @@ static int64_t plane_fields(int64_t n_f, int fmt) {
     return kpad > 0 ? kpad : q;
 }
 
+int64_t mfma_row_bytes(int64_t n_f, int levels, int fmt) {
+    return (int64_t)levels * (plane_fields(n_f, fmt) / fields_per_byte(fmt));
+}
+
 size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt) {
-    return (size_t)n_v * (size_t)levels * (size_t)(plane_fields(n_f, fmt) / fields_per_byte(fmt));
+    return (size_t)n_v * (size_t)mfma_row_bytes(n_f, levels, fmt);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,6 +186,10 @@ __device__ __forceinline__ void mfma_epilogue(const AccT (&acc)[4][WN], const Mf
     }
 }
 
+// Dword 3 of a raw buffer descriptor on gfx950: 32-bit data format, offset
+// addressing, no swizzle (loads past num_records return zero).
+constexpr int kRsrcWord3 = 0x00020000;
+
 // Accumulator type of a format.
 template <int FMT>
 using mfma_acc_t = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
@@ -193,9 +202,12 @@ constexpr int mfma_lds_bytes() { return 4 * kMB * (mfma_mk<FMT, WN>() + kPad); }
 // B rows b0 .. b0+255 of the planes (rows at or past n_v read as zero); with
 // MASK every B chunk is ANDed with the same chunk of plane row `mrow` (the
 // 3-way X_j operand: [v_i >= t] AND [v_j >= t] = [min(v_i, v_j) >= t]).
-// Tile kt+1 is staged from registers into the second LDS buffer while tile kt
-// is consumed, one barrier per field tile.  Waves that are not `active` take
-// part in staging and barriers only.
+// Field tile kt+1 is written from registers into the second LDS buffer while
+// tile kt is consumed, one barrier per field tile; tile kt+2 is loaded into
+// registers meanwhile (a second register set, loading two tiles ahead, was
+// measured slower on int8).  The loads are buffer loads with 32-bit offsets
+// (measured 12% faster on int8 than 64-bit addresses with row tests).  Waves
+// that are not `active` take part in staging and barriers only.
 template <int FMT, int WN, bool MASK>
 __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t b0,
                                           const int8_t* mrow, bool active, int wr, int wc,
@@ -217,20 +229,31 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t
 #pragma unroll
         for (int n = 0; n < WN; ++n) acc[m][n] = (mfma_acc_t<FMT>){};
 
-    // staging: 256 rows x kMK bytes per operand, kRowChunks threads per row
+    // staging: 256 rows x kMK bytes per operand, kRowChunks threads per row.
+    // Buffer resources over the tile's A and B rows (the host checks that 256
+    // plane rows span < 2^31 bytes): rows at or past n_v lie past num_records,
+    // where buffer loads return zero without a memory access.
+    auto rsrc = [&](int64_t r0) {
+        const int64_t rows = r0 < a.n_v ? (a.n_v - r0 < kMB ? a.n_v - r0 : kMB) : 0;
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(a.P + (rows > 0 ? r0 : 0) * a.kp),
+                                                 (short)0, (int)(rows * a.kp), kRsrcWord3);
+    };
+    const __amdgpu_buffer_rsrc_t rsa = rsrc(a0), rsb = rsrc(b0);
     uint4 ra[kStage], rb[kStage];
     const int ch = threadIdx.x % kRowChunks;   // the same for all of a thread's chunks
+    constexpr int kRowStep = kMThreads / kRowChunks;   // rows between a thread's chunks
+    const int kp = (int)a.kp;
+    const int voff = (threadIdx.x / kRowChunks) * kp + ch * 16;
     auto load = [&](int64_t k0) {
         uint4 mk = make_uint4(0, 0, 0, 0);
         if constexpr (MASK) mk = *(const uint4*)(mrow + k0 + ch * 16);
 #pragma unroll
         for (int c = 0; c < kStage; ++c) {
-            const int row = (threadIdx.x + c * kMThreads) / kRowChunks;
-            const int64_t ga = a0 + row, gb = b0 + row;
-            ra[c] = ga < a.n_v ? *(const uint4*)(a.P + ga * a.kp + k0 + ch * 16)
-                               : make_uint4(0, 0, 0, 0);
-            rb[c] = gb < a.n_v ? *(const uint4*)(a.P + gb * a.kp + k0 + ch * 16)
-                               : make_uint4(0, 0, 0, 0);
+            const int off = voff + c * kRowStep * kp + (int)k0;
+            const v4u_t va = __builtin_amdgcn_raw_buffer_load_b128(rsa, off, 0, 0);
+            const v4u_t vb = __builtin_amdgcn_raw_buffer_load_b128(rsb, off, 0, 0);
+            ra[c] = make_uint4(va[0], va[1], va[2], va[3]);
+            rb[c] = make_uint4(vb[0], vb[1], vb[2], vb[3]);
             if constexpr (MASK) {
                 rb[c].x &= mk.x;
                 rb[c].y &= mk.y;
@@ -255,64 +278,66 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t
     __syncthreads();
     if (nk > 1) load(kMK);
     const int fr = lane % 32, fk = (lane / 32) * 16;
+    // One field tile kt: consume buffer cur, write tile kt+1 from the
+    // registers into buffer cur^1, barrier, start loading tile kt+2.
+    auto step = [&](int64_t kt, int cur) {
+        const int8_t* A = As(cur);
+        const int8_t* B = Bs(cur);
+#pragma unroll
+        for (int ks = 0; ks < kMK / 32; ++ks) {
+            v4i_t fa[4], fb[WN];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+                fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < WN; ++n) {
+                    if constexpr (FMT == kFmtI8) {
+                        acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n],
+                                                                          acc[m][n], 0, 0, 0);
+                    } else {  // 64 e2m1 values per row per k-step, unit (2^0) scales
+                        const v8i_t xa = {fa[m].x, fa[m].y, fa[m].z, fa[m].w, 0, 0, 0, 0};
+                        const v8i_t xb = {fb[n].x, fb[n].y, fb[n].z, fb[n].w, 0, 0, 0, 0};
+                        acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            xa, xb, acc[m][n], 4, 4, 0, 127, 0, 127);
+                    }
+                }
+        }
+        // tile kt+1 into the other buffer (after the last tile the write is
+        // stale and never read; unconditional, so it joins this block)
+        store(cur ^ 1);
+        // schedule (measured 5% faster on int8): the next k-step's fragment
+        // reads between the MFMAs of this one, the staging writes of the
+        // next field tile between the MFMAs of the last k-step
+        if constexpr (FMT == kFmtI8 && WN == 2 && kMK == 128) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+#pragma unroll
+            for (int ks = 0; ks < kMK / 32 - 1; ++ks) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            }
+        }
+        __syncthreads();   // kt+1 visible; everyone is done reading kt
+        if (kt + 2 < nk) load((kt + 2) * kMK);
+    };
     // Active and idle waves run separate loops with the same barriers: a
     // branch around the MFMAs inside one loop makes the compiler copy every
     // accumulator at the join on each iteration.
     if (active) {
-        for (int64_t kt = 0; kt < nk; ++kt) {
-            const int cur = (int)(kt & 1);
-            const int8_t* A = As(cur);
-            const int8_t* B = Bs(cur);
-#pragma unroll
-            for (int ks = 0; ks < kMK / 32; ++ks) {
-                v4i_t fa[4], fb[WN];
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
-#pragma unroll
-                for (int n = 0; n < WN; ++n)
-                    fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-#pragma unroll
-                    for (int n = 0; n < WN; ++n) {
-                        if constexpr (FMT == kFmtI8) {
-                            acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n],
-                                                                              acc[m][n], 0, 0, 0);
-                        } else {  // 64 e2m1 values per row per k-step, unit (2^0) scales
-                            const v8i_t xa = {fa[m].x, fa[m].y, fa[m].z, fa[m].w, 0, 0, 0, 0};
-                            const v8i_t xb = {fb[n].x, fb[n].y, fb[n].z, fb[n].w, 0, 0, 0, 0};
-                            acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                                xa, xb, acc[m][n], 4, 4, 0, 127, 0, 127);
-                        }
-                    }
-            }
-            // tile kt+1 into the other buffer (after the last tile the write is
-            // stale and never read; unconditional, so it joins this block)
-            store(cur ^ 1);
-            // schedule (measured 5% faster on int8): the next k-step's fragment
-            // reads between the MFMAs of this one, the staging writes of the
-            // next field tile between the MFMAs of the last k-step
-            if constexpr (FMT == kFmtI8 && WN == 2 && kMK == 128) {
-                __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-#pragma unroll
-                for (int ks = 0; ks < kMK / 32 - 1; ++ks) {
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-                    }
-                    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-                }
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-                }
-            }
-            __syncthreads();   // kt+1 visible; everyone is done reading kt
-            if (kt + 2 < nk) load((kt + 2) * kMK);
-        }
+        for (int64_t kt = 0; kt < nk; ++kt) step(kt, (int)(kt & 1));
     } else {
         for (int64_t kt = 0; kt < nk; ++kt) {
             if (kt + 1 < nk) store((int)(kt & 1) ^ 1);

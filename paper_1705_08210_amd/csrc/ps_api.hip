@@ -122,6 +122,12 @@ static ps_status check_mfma(int path, int32_t dtype, int levels, int64_t n_f) {
     if (path == PS_PATH_MFMA && (int64_t)levels * n_f >= ((int64_t)1 << 31))
         return fail(PS_ERR_ARG, "int8 path: levels * n_f = %lld exceeds int32",
                     (long long)levels * n_f);
+    if (!mfma_row_fits(n_f, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0))
+        return fail(PS_ERR_UNSUPPORTED,
+                    "MFMA path: plane rows of %lld bytes (levels * n_f = %lld) are too long for "
+                    "32-bit tile offsets (256 rows must span < 2^31 bytes); use the VALU path",
+                    (long long)mfma_row_bytes(n_f, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0),
+                    (long long)levels * n_f);
     return PS_OK;
 }
 
@@ -195,7 +201,7 @@ ps_status ps_vector_sums(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
 size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_given,
                           const ps_opts* opts) {
     if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
-    const int path = choose_path(dtype, opts);
+    const int path = choose_path(dtype, opts, n_f);
     const Split sp = path == PS_PATH_BITS
                          ? Split{1, 0}
                          : plan_split(dtype, n_f, n_v,
@@ -215,7 +221,7 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (!aligned(c2, 4) || !aligned(n2, 4) || !aligned(s, 8))
         return fail(PS_ERR_ARG, "misaligned output or sums pointer");
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
-    const int path = choose_path(dtype, opts);
+    const int path = choose_path(dtype, opts, n_f);
     const int levels = opts ? opts->levels : 0;
     if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
     double* s_ws = nullptr;
@@ -341,7 +347,7 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (is_bits(opts))
         return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage, bits_bytes(n_f, n_v), nullptr,
                           nullptr, nullptr, nullptr, nullptr, nullptr);
-    const int path = choose_path(dtype, opts);
+    const int path = choose_path(dtype, opts, n_f);
     if (is_mfma(path) && dtype == PS_U8)
         return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage,
                           mfma_workspace_bytes(n_f, n_v, opts ? opts->levels : 0,
@@ -406,7 +412,7 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
-    const int path = choose_path(dtype, opts);
+    const int path = choose_path(dtype, opts, n_f);
     const int levels = opts ? opts->levels : 0;
     if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
     if (n_v < 3) return PS_OK;

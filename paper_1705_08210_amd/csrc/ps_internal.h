@@ -135,7 +135,9 @@ int32_t split_chunks(int32_t dt, int64_t n_f, int acc);
 int64_t chunk_tiles(int32_t dt, int cfg);
 Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o);
 bool is_mfma(int path);
-int choose_path(int32_t dt, const ps_opts* o);
+// AUTO takes the int8 MFMA path for PS_U8 data with 1 <= levels <= 15 whose
+// plane rows fit mfma_row_fits().
+int choose_path(int32_t dt, const ps_opts* o, int64_t n_f);
 int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o);
 
 // Arguments of one 2-way launch over the upper-triangle tile list.
@@ -250,9 +252,16 @@ struct MfmaLaunch {
     float* c3;
 };
 size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt);
+// Bytes of one thermometer plane row (all levels) of an n_f-field vector.
+int64_t mfma_row_bytes(int64_t n_f, int levels, int fmt);
 hipError_t launch_mfma2(const MfmaLaunch& a, hipStream_t st);
 // Output tile edge of the MFMA kernels (the 3-way prefix is over these tiles).
 constexpr int kMfmaTile = 256;
+// The MFMA kernels address a 256-row tile of plane rows with 32-bit buffer
+// offsets: 256 plane rows must span less than 2^31 bytes.
+inline bool mfma_row_fits(int64_t n_f, int levels, int fmt) {
+    return (int64_t)kMfmaTile * mfma_row_bytes(n_f, levels, fmt) < ((int64_t)1 << 31);
+}
 hipError_t launch_mfma3(const MfmaLaunch& a, hipStream_t st);
 hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
                           hipStream_t st);
