@@ -93,11 +93,17 @@ typedef enum {
 
 /* Compute path for the pair numerators. */
 typedef enum {
-    PS_PATH_AUTO = 0,    /* U8 with 1 <= levels <= 15: MFMA; otherwise VALU */
+    PS_PATH_AUTO = 0,    /* U8 with 1 <= levels <= 15 and plane rows within the
+                            MFMA limit below: MFMA; otherwise VALU */
     PS_PATH_VALU = 1,    /* register-blocked min/add on the vector ALUs */
     PS_PATH_MFMA = 2,    /* U8 only: min(a,b) = sum_{t=1..levels} [a>=t][b>=t],
                             an exact int8 matrix-core contraction with int32
-                            accumulation; needs levels >= max(V) */
+                            accumulation; needs levels >= max(V).  Both MFMA
+                            paths address 256 plane rows (levels x n_f rounded
+                            up to 128 fields, one byte per field for int8, half
+                            a byte for FP4) with 32-bit offsets: 256 rows must
+                            span < 2^31 bytes (int8: levels * n_f below about
+                            8.4e6), else PS_ERR_UNSUPPORTED */
     PS_PATH_MFMA_FP4 = 3, /* U8 only: the same 0/1 planes as FP4 (e2m1) operands
                             of the scaled matrix-core instruction, FP32
                             accumulation (exact: sums are integers < 2^24,
