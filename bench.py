@@ -326,9 +326,8 @@ def main(argv=None):
                                      args.pmc_command))
         return 0
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(sharding across GPUs is described in DESIGN.md, not implemented)",
-              file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         return 2
 
     import numpy as np

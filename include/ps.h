@@ -65,7 +65,7 @@ typedef enum {
     PS_ERR_DTYPE = 2,        /* unknown or unsupported storage type */
     PS_ERR_WORKSPACE = 3,    /* workspace too small (see *_workspace_size) */
     PS_ERR_HIP = 4,          /* a HIP runtime call failed */
-    PS_ERR_UNSUPPORTED = 5   /* valid request this build does not implement */
+    PS_ERR_UNSUPPORTED = 5   /* valid request the library does not implement */
 } ps_status;
 
 /* Storage type of V. */

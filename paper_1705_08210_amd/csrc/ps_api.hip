@@ -249,7 +249,7 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
                      1, 0, 0, nullptr, nullptr};
         e = launch_mfma2(m, stream);
         if (e == hipErrorNotSupported)
-            return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this build");
+            return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this library");
         return e == hipSuccess ? PS_OK : hip_fail(e, "mfma launch");
     }
     if (bits) {   // pack, then the min-product on words (zero pad words add nothing)
