@@ -117,7 +117,12 @@ def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3, 0), reps=3, quick=False, log=p
                     if way == 2:
                         f = (lambda i=idx: ps.ps2(V, s=s, c2=c2, path="valu", tile=i + 1))
                     else:
-                        f = (lambda i=idx: ps.ps3(V, s=s, n2=n2, c3=c3, tile=i + 1))
+                        # as the library runs a tuned choice (opts.tile = 0): the
+                        # 128-wide configurations over whole slab tiles, with
+                        # 64-wide tiles at the slab edges
+                        ps.tune_clear()
+                        ps.tune_register(dt, 3, "valu", (0, 1 << 40), (0, 1 << 40), idx)
+                        f = (lambda: ps.ps3(V, s=s, n2=n2, c3=c3))
                     times.append(_time(f, reps))
                 best = int(np.argmin(times))
                 rec = {"dtype": dname, "way": way, "nf": list(NF_BUCKETS[fb]),
@@ -127,6 +132,9 @@ def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3, 0), reps=3, quick=False, log=p
                 out.append(rec)
                 del V
                 torch.cuda.empty_cache()
+    ps.tune_clear()      # the library now follows the new choices
+    for e in out:
+        ps.tune_register(DTYPES[e["dtype"]], e["way"], "valu", e["nf"], e["nv"], e["tile"])
     return {"device": torch.cuda.get_device_name(0), "time": time.time(), "entries": out}
 
 
@@ -154,8 +162,18 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=CACHE)
     ap.add_argument("--dtypes", default="f32,f16,u8")
+    ap.add_argument("--ways", default="2,3,0",
+                    help="ways to tune; the entries of other ways are kept from --out")
     a = ap.parse_args(argv)
-    cache = tune(tuple(a.dtypes.split(",")), reps=a.reps, quick=a.quick)
+    ways = tuple(int(w) for w in a.ways.split(","))
+    dtypes = tuple(a.dtypes.split(","))
+    cache = tune(dtypes, ways=ways, reps=a.reps, quick=a.quick)
+    if os.path.exists(a.out):    # keep the entries this run did not re-tune
+        with open(a.out) as f:
+            old = json.load(f)
+        kept = [e for e in old.get("entries", [])
+                if not (e["way"] in ways and e["dtype"] in dtypes)]
+        cache["entries"] = kept + cache["entries"]
     save(cache, a.out)
     print(f"wrote {a.out} ({len(cache['entries'])} entries)")
 

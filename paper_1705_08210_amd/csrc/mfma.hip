@@ -613,9 +613,9 @@ static hipError_t go_mfma3(const MfmaLaunch& m, hipStream_t st) {
     int64_t kp = 0;
     hipError_t e = expand_planes<FMT>(m, kp, st);
     if (e != hipSuccess) return e;
-    e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kMB, m.prefix, st);
+    e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kMB, kSlabAll, kMB, m.prefix, st);
     if (e != hipSuccess) return e;
-    const int64_t T = slab_tiles(m.n_v, m.j_begin, m.j_end, kMB, kMB);
+    const int64_t T = slab_tiles(m.n_v, m.j_begin, m.j_end, kMB, kSlabAll, kMB);
     if (T == 0) return hipSuccess;
     MfmaArgs a{m.planes, kp, m.n_v, m.s, nullptr, nullptr, 0, T, m.j_begin, m.j_end, m.prefix,
                (uint32_t*)m.c3, 0};

@@ -82,9 +82,7 @@ hipError_t launch_mg2_b1(const Mg2Launch& a, hipStream_t st) {
 }
 
 hipError_t launch_mg3_b1(const Mg3Launch& a, hipStream_t st) {
-    hipError_t e = dispatch(a.cfg, [&](auto tm, auto bkw) {
-        return go_mg3<PS_B1, decltype(tm)::value, decltype(bkw)::value>(a, st);
-    });
+    hipError_t e = go_mg3_all<PS_B1>(a, [](int cfg, auto go) { return dispatch(cfg, go); }, st);
     return e == hipSuccess ? go_c3_finish<PS_B1>(a, st) : e;
 }
 

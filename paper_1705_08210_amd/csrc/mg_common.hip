@@ -178,7 +178,8 @@ hipError_t launch_batched_sums(const DevProblem* probs, const int32_t* need_s, i
 // One workgroup of 1024 threads.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void ps_prefix3_kernel(int64_t n_v, int64_t jb, int64_t je,
-                                                          int bm, int64_t* prefix) {
+                                                          int bm, int mode, int ob,
+                                                          int64_t* prefix) {
     __shared__ int64_t part[1024];
     const int64_t nj = je - jb;
     const int64_t per = (nj + 1023) / 1024;
@@ -186,8 +187,7 @@ __global__ __launch_bounds__(1024) void ps_prefix3_kernel(int64_t n_v, int64_t j
     const int64_t hi = lo + per < nj ? lo + per : nj;
     int64_t sum = 0;
     for (int64_t t = lo; t < hi; ++t) {
-        const int64_t j = jb + t;
-        sum += ((j + bm - 1) / bm) * ((n_v - 1 - j + bm - 1) / bm);
+        sum += slab_tile_count(n_v, jb + t, bm, mode, ob);
     }
     part[threadIdx.x] = sum;
     __syncthreads();
@@ -202,9 +202,8 @@ __global__ __launch_bounds__(1024) void ps_prefix3_kernel(int64_t n_v, int64_t j
     __syncthreads();
     int64_t run = part[threadIdx.x];
     for (int64_t t = lo; t < hi; ++t) {
-        const int64_t j = jb + t;
         prefix[t] = run;
-        run += ((j + bm - 1) / bm) * ((n_v - 1 - j + bm - 1) / bm);
+        run += slab_tile_count(n_v, jb + t, bm, mode, ob);
     }
     if (hi == nj && lo < hi) prefix[nj] = run;
     if (nj == 0 && threadIdx.x == 0) prefix[0] = 0;
@@ -282,14 +281,19 @@ hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(ps_prefix3_kernel, dim3(1), dim3(1024), 0, st, n_v, jb, je, bm, prefix);
+hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob,
+                          int64_t* prefix, hipStream_t st) {
+    hipLaunchKernelGGL(ps_prefix3_kernel, dim3(1), dim3(1024), 0, st, n_v, jb, je, bm, mode, ob,
+                       prefix);
     return hipGetLastError();
 }
 
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
-    return launch_prefix3(a.n_v, a.j_begin, a.j_end, kValuCfgs[a.cfg].bm(), a.prefix, st);
+    const int bm = kValuCfgs[a.cfg].bm();
+    hipError_t e = launch_prefix3(a.n_v, a.j_begin, a.j_end, bm, a.mode, bm, a.prefix, st);
+    if (e != hipSuccess || a.mode != kSlabFull) return e;
+    return launch_prefix3(a.n_v, a.j_begin, a.j_end, kValuCfgs[a.edge_cfg].bm(), kSlabEdge, bm,
+                          a.edge_prefix, st);
 }
 
 }  // namespace ps

@@ -26,9 +26,7 @@ hipError_t launch_mg2_f32(const Mg2Launch& a, hipStream_t st) {
 }
 
 hipError_t launch_mg3_f32(const Mg3Launch& a, hipStream_t st) {
-    hipError_t e = dispatch(a.cfg, [&](auto tm, auto bkw) {
-        return go_mg3<PS_F32, decltype(tm)::value, decltype(bkw)::value>(a, st);
-    });
+    hipError_t e = go_mg3_all<PS_F32>(a, [](int cfg, auto go) { return dispatch(cfg, go); }, st);
     return e == hipSuccess ? go_c3_finish<PS_F32>(a, st) : e;
 }
 

@@ -26,9 +26,7 @@ hipError_t launch_mg2_u8(const Mg2Launch& a, hipStream_t st) {
 }
 
 hipError_t launch_mg3_u8(const Mg3Launch& a, hipStream_t st) {
-    hipError_t e = dispatch(a.cfg, [&](auto tm, auto bkw) {
-        return go_mg3<PS_U8, decltype(tm)::value, decltype(bkw)::value>(a, st);
-    });
+    hipError_t e = go_mg3_all<PS_U8>(a, [](int cfg, auto go) { return dispatch(cfg, go); }, st);
     return e == hipSuccess ? go_c3_finish<PS_U8>(a, st) : e;
 }
 

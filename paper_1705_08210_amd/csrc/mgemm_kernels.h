@@ -121,17 +121,16 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
     const int64_t w = item0 + xcd_remap(blockIdx.x, gridDim.x);
     if (w >= a.ntiles * a.nchunks) return;
     const int64_t chunk = w / a.ntiles, t = w % a.ntiles;
-    // slice j: largest jj with prefix[jj] <= t (every slice has >= 1 tile)
+    // slice j: largest jj with prefix[jj] <= t (the slice holding tile t;
+    // slices without tiles in this tile set repeat their prefix and are passed)
     int64_t lo = 0, hi = a.j_end - a.j_begin;
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) / 2;
         if (a.prefix[mid] <= t) lo = mid; else hi = mid;
     }
     const int64_t j = a.j_begin + lo;
-    const int64_t local = t - a.prefix[lo];
-    const int64_t nk = (a.n_v - 1 - j + BM - 1) / BM;
-    const int64_t bi = local / nk, bk = local % nk;
-    const int64_t row0 = bi * BM, col0 = j + 1 + bk * BM;
+    int64_t row0, col0;
+    slab_tile_origin(a.n_v, j, t - a.prefix[lo], BM, a.mode, a.ob, row0, col0);
     const int wave = threadIdx.x / 64;
     const int64_t r_lo = row0 + (wave & 1) * 8 * TM;
     const int64_t c_lo = col0 + (wave >> 1) * 8 * TM;
@@ -281,6 +280,21 @@ hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
         hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,
                            item0);
     });
+}
+
+// The slice launches of a: one over its tile set and, for kSlabFull, the
+// kSlabEdge launch that completes it.  dispatch(cfg, go) runs go with the
+// compiled tile configuration cfg.
+template <int DT, class Dispatch>
+hipError_t go_mg3_all(const Mg3Launch& a, Dispatch dispatch, hipStream_t st) {
+    auto one = [&](const Mg3Launch& p) {
+        return dispatch(p.cfg, [&](auto tm, auto bkw) {
+            return go_mg3<DT, decltype(tm)::value, decltype(bkw)::value>(p, st);
+        });
+    };
+    hipError_t e = one(a);
+    if (e == hipSuccess && a.mode == kSlabFull) e = one(mg3_edge_launch(a));
+    return e;
 }
 
 template <int DT, int TM, int BKW>

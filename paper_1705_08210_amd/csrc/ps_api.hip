@@ -27,9 +27,9 @@ static ps_status hip_fail(hipError_t e, const char* what) {
     return fail(PS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-int64_t slab_tiles(int64_t n_v, int64_t jb, int64_t je, int bm, int bn) {
+int64_t slab_tiles(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob) {
     int64_t t = 0;
-    for (int64_t j = jb; j < je; ++j) t += ceil_div(j, bm) * ceil_div(n_v - 1 - j, bn);
+    for (int64_t j = jb; j < je; ++j) t += slab_tile_count(n_v, j, bm, mode, ob);
     return t;
 }
 
@@ -281,7 +281,8 @@ static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int n2_
     else if (packed_bytes) c.take(packed_bytes);
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
     if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * (size_t)n2_bytes);
-    int64_t* pre = (int64_t*)c.take((size_t)(n_v + 1) * sizeof(int64_t));
+    // two slab prefixes of n_v + 1 entries: the launch's tiles, then its edge tiles
+    int64_t* pre = (int64_t*)c.take((size_t)2 * (n_v + 1) * sizeof(int64_t));
     const int64_t need2 = (!n2_given && nchunks2 > 1) ? nchunks2 * (n_v * (n_v - 1) / 2) : 0;
     // floats of the slice sums: FP32 chunk partials, or (nchunks3 < 0) FP64 raw sums
     const int64_t need3 = nchunks3 < 0 ? 2 * stage : nchunks3 > 1 ? nchunks3 * stage : 0;
@@ -332,7 +333,8 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
     }
     e = launch_mfma3(m, stream);
     if (e != hipSuccess) return hip_fail(e, "3-way mfma launch");
-    Mg3Launch f{V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, prefix, 0, 0, 1, 0, nullptr};
+    Mg3Launch f{V,        n_f,     n_v, ld, s,  n2,      j_begin, j_end, c3, prefix, 0, 0, 1,
+                0,        nullptr, kSlabAll, 0, -1, nullptr, 0,       0};
     e = launch_c3_finish_int(f, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way finish launch");
 }
@@ -468,9 +470,14 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     }
     const int cfg = choose_cfg(kdt, 3, bits ? PS_PATH_BITS : PS_PATH_VALU, n_f, n_v, opts);
     const int bm = kValuCfgs[cfg].bm();
+    const int ecfg = edge_cfg3(cfg, opts);   // >= 0: whole tiles, then the edges in ecfg tiles
+    const int mode = ecfg >= 0 ? kSlabFull : kSlabAll;
     Mg3Launch a{KV, kn_f, n_v, kld, s, n2, j_begin, j_end, c3, prefix,
-                slab_tiles(n_v, j_begin, j_end, bm, bm), cfg, nchunks,
-                bits ? 0 : chunk_tiles(dtype, cfg), partial};
+                slab_tiles(n_v, j_begin, j_end, bm, mode, bm), cfg, nchunks,
+                bits ? 0 : chunk_tiles(dtype, cfg), partial, mode, bm, ecfg, prefix + (n_v + 1),
+                ecfg >= 0 ? slab_tiles(n_v, j_begin, j_end, kValuCfgs[ecfg].bm(), kSlabEdge, bm)
+                          : 0,
+                ecfg >= 0 && !bits ? chunk_tiles(dtype, ecfg) : 0};
     e = launch_mg3_prefix(a, stream);
     if (e == hipSuccess) e = launch_mg3(kdt, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");

@@ -65,6 +65,49 @@ __host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
     return (n - 1) * (j * (j - 1) / 2) - ((j - 1) * j * (2 * j - 1)) / 6;
 }
 
+// Tile sets of a 3-way slab j (the rectangle i in [0, j), k in (j, n_v)):
+//   kSlabAll   every bm x bm tile of the rectangle (edge tiles partly outside);
+//   kSlabFull  only the ob x ob tiles wholly inside it (bm == ob);
+//   kSlabEdge  the rest, in bm x bm tiles: rows [I1, j) against every k, and
+//              rows [0, I1) against k in [K1, n_v), where I1 = ob floor(j / ob)
+//              and K1 = j + 1 + ob floor((n_v - 1 - j) / ob).
+// kSlabFull with ob tiles plus kSlabEdge with smaller bm tiles cover the
+// rectangle exactly once, with edge waste at the bm granularity only.
+enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2 };
+
+__host__ __device__ inline int64_t slab_tile_count(int64_t n_v, int64_t j, int bm, int mode,
+                                                   int ob) {
+    const int64_t wk = n_v - 1 - j;
+    if (mode == kSlabAll) return ((j + bm - 1) / bm) * ((wk + bm - 1) / bm);
+    if (mode == kSlabFull) return (j / ob) * (wk / ob);
+    const int64_t i1 = j / ob * ob, rk = wk % ob;
+    return ((j - i1 + bm - 1) / bm) * ((wk + bm - 1) / bm) + (i1 / bm) * ((rk + bm - 1) / bm);
+}
+
+// Origin (first i, first k) of tile `local` of slab j in the order the tile
+// counts above enumerate them (row-major within each part).
+__host__ __device__ inline void slab_tile_origin(int64_t n_v, int64_t j, int64_t local, int bm,
+                                                 int mode, int ob, int64_t& row0,
+                                                 int64_t& col0) {
+    const int64_t wk = n_v - 1 - j;
+    if (mode != kSlabEdge) {
+        const int64_t nk = mode == kSlabAll ? (wk + bm - 1) / bm : wk / bm;
+        row0 = local / nk * bm;
+        col0 = j + 1 + local % nk * bm;
+        return;
+    }
+    const int64_t i1 = j / ob * ob, k1 = j + 1 + wk / ob * ob;
+    const int64_t nk = (wk + bm - 1) / bm, part1 = ((j - i1 + bm - 1) / bm) * nk;
+    if (local < part1) {
+        row0 = i1 + local / nk * bm;
+        col0 = j + 1 + local % nk * bm;
+    } else {
+        const int64_t l = local - part1, nk2 = (n_v - k1 + bm - 1) / bm;
+        row0 = l / nk2 * bm;
+        col0 = k1 + l % nk2 * bm;
+    }
+}
+
 // Upper-triangle block (bi <= bj) number t of an nb x nb block triangle in
 // grouped order: block columns are taken G at a time and, inside a group,
 // row by row, so the tiles that run side by side on one XCD share their row
@@ -131,6 +174,9 @@ constexpr int64_t kMinChunkTiles = 4;
 int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
                const ps_opts* o);
 int choose_acc(int64_t n_f, const ps_opts* o);
+// 3-way slices: the configuration of the edge tiles that complete a launch
+// over whole tiles of cfg (kSlabFull), or -1 for one launch over every tile.
+int edge_cfg3(int cfg, const ps_opts* o);
 int32_t split_chunks(int32_t dt, int64_t n_f, int acc);
 int64_t chunk_tiles(int32_t dt, int cfg);
 Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o);
@@ -171,7 +217,29 @@ struct Mg3Launch {
     int32_t nchunks;             // field-chunk split as for Mg2Launch; partial
     int64_t chunk_tiles;         // holds nchunks * stage-size FP32 values (for
     float* partial;              // PS_F64: stage-size doubles of raw n3', no split)
+    int32_t mode;                // tile set of this launch (kSlabAll / kSlabFull / kSlabEdge)
+    int32_t ob;                  // kSlabEdge: edge of the whole tiles around which it runs
+    // kSlabFull: a second launch covers the slab edges with configuration
+    // edge_cfg (kSlabEdge around the cfg tiles); its slab prefix is edge_prefix
+    int32_t edge_cfg;
+    int64_t* edge_prefix;        // workspace: j_end - j_begin + 1 int64
+    int64_t edge_ntiles, edge_chunk_tiles;
 };
+
+// The kSlabEdge launch that completes a kSlabFull launch a.
+inline Mg3Launch mg3_edge_launch(const Mg3Launch& a) {
+    Mg3Launch e = a;
+    e.mode = kSlabEdge;
+    e.ob = kValuCfgs[a.cfg].bm();
+    e.cfg = a.edge_cfg;
+    e.prefix = a.edge_prefix;
+    e.ntiles = a.edge_ntiles;
+    e.chunk_tiles = a.edge_chunk_tiles;
+    e.edge_cfg = -1;
+    e.edge_prefix = nullptr;
+    e.edge_ntiles = e.edge_chunk_tiles = 0;
+    return e;
+}
 
 // Device problem record of a batched launch.
 struct DevProblem {
@@ -204,7 +272,8 @@ inline int64_t tri_tiles(int64_t n_v, int bm) {
 }
 
 // Tiles of the 3-way slices j in [jb, je).
-int64_t slab_tiles(int64_t n_v, int64_t jb, int64_t je, int bm, int bn);
+// Tiles of slabs [jb, je) in a tile set (slab_tile_count).
+int64_t slab_tiles(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob);
 
 // Launchers (one per storage type; defined in the per-type units).
 hipError_t launch_sums(const void* V, int32_t dt, int64_t n_f, int64_t n_v,
@@ -263,8 +332,9 @@ inline bool mfma_row_fits(int64_t n_f, int levels, int fmt) {
     return (int64_t)kMfmaTile * mfma_row_bytes(n_f, levels, fmt) < ((int64_t)1 << 31);
 }
 hipError_t launch_mfma3(const MfmaLaunch& a, hipStream_t st);
-hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
-                          hipStream_t st);
+// prefix[t] = tiles of slabs jb .. jb+t-1 in a tile set, t = 0 .. je - jb.
+hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob,
+                          int64_t* prefix, hipStream_t st);
 // Output reduction (reduce.hip).
 hipError_t launch_quantize_u8(const float* c, int64_t n, uint8_t* q, hipStream_t st);
 int64_t select_tiles(int64_t n);

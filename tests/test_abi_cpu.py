@@ -121,14 +121,13 @@ def test_workspace_sizes():
     g = lib.ps3_workspace_size
     n = 100
     pairs = n * (n - 1) // 2
-    expect = (math.ceil(n * 8 / 256) * 256 + math.ceil(pairs * 4 / 256) * 256
-              + math.ceil((n + 1) * 8 / 256) * 256)
+    prefixes = math.ceil(2 * (n + 1) * 8 / 256) * 256    # whole-tile and edge-tile slab prefixes
+    expect = math.ceil(n * 8 / 256) * 256 + math.ceil(pairs * 4 / 256) * 256 + prefixes
     assert g(0, 10, n, 0, 0, 1, n - 1, None) == expect
-    assert g(0, 10, n, 1, 1, 1, n - 1, None) == math.ceil((n + 1) * 8 / 256) * 256
+    assert g(0, 10, n, 1, 1, 1, n - 1, None) == prefixes
     # blocked accumulation beyond 4096 fields: FP32 partials of each field chunk
     stage = math.comb(n, 3)
-    assert g(0, 9000, n, 1, 1, 1, n - 1, None) == (math.ceil((n + 1) * 8 / 256) * 256
-                                                  + math.ceil(3 * stage * 4 / 256) * 256)
+    assert g(0, 9000, n, 1, 1, 1, n - 1, None) == prefixes + math.ceil(3 * stage * 4 / 256) * 256
     blocked = opts(acc=2)
     assert f(0, 9000, 1000, 1, blocked) == math.ceil(3 * (1000 * 999 // 2) * 4 / 256) * 256
     assert f(0, 9000, 1000, 1, opts(acc=1)) == 0   # plain: one chunk, no partials

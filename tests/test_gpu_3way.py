@@ -5,7 +5,8 @@ import pytest
 
 import oracle
 import workloads
-from psx import (announce, check_exact_f32, check_rel, host, jslab, need_gpu, to_dev)
+from psx import (announce, check_exact_f32, check_rel, host, jslab, need_gpu, sample_triples,
+                 to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -190,3 +191,68 @@ def test_mfma_3way_full_size_sampled(path):
     c3 = host(ps.ps3(to_dev(V), path=path, levels=3))
     i, j, k = sample_triples(n_v, 4096, seed=52)
     check_exact_f32(c3[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), "c3 sampled")
+
+
+# ------------------------------------------- whole tiles + edge tiles ----
+
+def _edge_case_input(storage, n_v, n_f, seed):
+    if storage == "bits":
+        return workloads.binary(n_v, n_f, seed=seed, dtype=np.uint8), dict(path="bits", levels=1)
+    if storage == "u8":
+        return workloads.levels(n_v, n_f, seed=seed), dict(path="valu")
+    V = workloads.sparse_uniform(n_v, n_f, seed=seed)
+    return (workloads.to_f16(V) if storage == "f16" else V), {}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u8", "bits"])
+@pytest.mark.parametrize("n_v", [256, 389])
+def test_edge_tiles_agree_with_single_configurations(storage, n_v):
+    """From n_v = 256 the library runs 128-wide tiles over the whole tiles of
+    each slab rectangle and 64-wide tiles over its ragged edges (two
+    launches).  Each slice sum is the same field-ordered sum in any tiling,
+    so with the same pair numerators and sums the result equals a launch of
+    either configuration over every tile bit for bit; a NaN-filled output
+    shows that every triple is written."""
+    import torch
+    from paper_1705_08210_amd import ps
+    V, kw = _edge_case_input(storage, n_v, 700, seed=n_v + 5)
+    Vd = to_dev(V)
+    announce(f"3-way edge tiles {storage} n_v={n_v}")
+    s, _ = ps.vector_sums(Vd)
+    _, n2 = ps.ps2(Vd, s=s, want_c2=False, want_n2=True, **kw)
+    c3 = torch.full((ps.stage_size(n_v, 1, n_v - 1),), float("nan"), device=Vd.device)
+    ps.ps3(Vd, s=s, n2=n2, c3=c3, **kw)
+    both = host(c3)
+    assert not np.isnan(both).any()
+    for tile in (2, 3):      # 64-wide, 128-wide tiles over every tile of the slab
+        one = host(ps.ps3(Vd, s=s, n2=n2, tile=tile, **kw))
+        assert np.array_equal(both.view(np.uint32), one.view(np.uint32)), tile
+    i, j, k = sample_triples(n_v, 2048, seed=n_v)
+    ref = oracle.c3_triples(V, i, j, k)
+    got = both[jslab(n_v, i, j, k)]
+    if storage in ("u8", "bits"):
+        check_exact_f32(got, ref, "c3")
+    else:
+        check_rel(got, ref, FP32_TOL, "c3")
+
+
+def test_edge_tiles_with_field_chunks_and_stages():
+    """Blocked accumulation over two field chunks and staged slabs with the
+    two-launch tiling: the chunks and the stages combine exactly as in a
+    single-configuration launch."""
+    from paper_1705_08210_amd import ps
+    n_v = 300
+    V = workloads.gwas_like(n_v, 5000, seed=91)
+    Vd = to_dev(V)
+    announce("3-way edge tiles, blocked chunks and stages")
+    s, _ = ps.vector_sums(Vd)
+    _, n2 = ps.ps2(Vd, s=s, acc="blocked", want_c2=False, want_n2=True)
+    full = host(ps.ps3(Vd, s=s, n2=n2, acc="blocked"))
+    one = host(ps.ps3(Vd, s=s, n2=n2, acc="blocked", tile=3))
+    assert np.array_equal(full.view(np.uint32), one.view(np.uint32))
+    cuts = [1, 2, 130, 131, 257, n_v - 1]
+    parts = [host(ps.ps3(Vd, s=s, n2=n2, acc="blocked", j_begin=a, j_end=b))
+             for a, b in zip(cuts, cuts[1:])]
+    assert np.array_equal(np.concatenate(parts).view(np.uint32), full.view(np.uint32))
+    i, j, k = sample_triples(n_v, 1024, seed=92)
+    check_rel(full[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), FP32_TOL, "c3")
