@@ -4,10 +4,14 @@ of Section 6.5).
 The triples are computed one stage (a range of middle indices j) at a time
 into a device buffer, reduced on the device (one byte per metric, or a
 thresholded (index, value) list), copied to pinned host memory on a second
-stream and handed to a caller-supplied sink -- while the next stage is
-already computing.  Two device buffers alternate; a buffer is reused only
-after its copy has completed.  The per-vector sums and pair numerators are
-computed once and stay resident.
+stream and handed to a caller-supplied sink -- while the next two stages are
+already queued, so the sink's host work overlaps GPU work.  Consecutive
+stages alternate between two compute streams, so one stage's last
+workgroups run beside the next stage's first ones instead of leaving the
+GPU partly idle at every stage boundary.  Three buffer sets rotate; a device
+buffer is reused only after its copy has completed, a host buffer only after
+the sink has returned.  The per-vector sums and pair numerators are computed
+once and stay resident.
 
     from paper_1705_08210_amd import campaign
     campaign.run3(V, n_stages=8, sink=lambda st: ..., reduce="u8")
@@ -81,44 +85,54 @@ def run3(V: torch.Tensor, n_stages: int, sink, reduce: str = "u8", threshold: fl
     if not stages:
         return 0
     dev = V.device
-    compute = torch.cuda.current_stream(dev)
-    copy = torch.cuda.Stream(dev)          # default priority
+    main = torch.cuda.current_stream(dev)
+    computes = [torch.cuda.Stream(dev) for _ in range(2)]   # default priority
+    copy = torch.cuda.Stream(dev)
     s, _ = ps.vector_sums(V, want_bad=False)
     _, n2 = ps.ps2(V, s=s, want_c2=False, want_n2=True, path=path, levels=levels, acc=acc,
                    tile=tile)
+    ready = torch.cuda.Event()
+    ready.record(main)
+    for cs in computes:
+        cs.wait_event(ready)
     biggest = max(ps.stage_size(n_v, a, b) for a, b in stages)
     cap_ = biggest if cap is None else int(cap)
-    c3 = [torch.empty(biggest, dtype=torch.float32, device=dev) for _ in range(2)]
+    nbuf = min(3, len(stages))      # stage k uses buffer set k % nbuf
+    c3 = [torch.empty(biggest, dtype=torch.float32, device=dev) for _ in range(nbuf)]
     if reduce == "u8":
-        dout = [torch.empty(biggest, dtype=torch.uint8, device=dev) for _ in range(2)]
-        hout = [torch.empty(biggest, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        dout = [torch.empty(biggest, dtype=torch.uint8, device=dev) for _ in range(nbuf)]
+        hout = [torch.empty(biggest, dtype=torch.uint8, pin_memory=True) for _ in range(nbuf)]
     elif reduce == "none":
         dout = c3
-        hout = [torch.empty(biggest, dtype=torch.float32, pin_memory=True) for _ in range(2)]
+        hout = [torch.empty(biggest, dtype=torch.float32, pin_memory=True) for _ in range(nbuf)]
     else:
-        hidx = [torch.empty(max(cap_, 1), dtype=torch.int64, pin_memory=True) for _ in range(2)]
+        hidx = [torch.empty(max(cap_, 1), dtype=torch.int64, pin_memory=True)
+                for _ in range(nbuf)]
         hval = [torch.empty(max(cap_, 1), dtype=torch.float32, pin_memory=True)
-                for _ in range(2)]
-        hcnt = [torch.empty(1, dtype=torch.int64, pin_memory=True) for _ in range(2)]
-        dsel = [None, None]
-    copied = [None, None]     # event: the buffer's copy to the host has finished
+                for _ in range(nbuf)]
+        hcnt = [torch.empty(1, dtype=torch.int64, pin_memory=True) for _ in range(nbuf)]
+        dsel = [None] * nbuf
+    copied = [None] * nbuf    # event: the buffer set's copy to the host has finished
 
     def launch(k):
-        """Compute, reduce and start the copy of stage k on buffer k % 2."""
-        b = k % 2
+        """Compute, reduce and start the copy of stage k on buffer set k % nbuf
+        (its previous stage has been delivered: the host buffer is free)."""
+        b = k % nbuf
         a, e = stages[k]
         m = ps.stage_size(n_v, a, e)
-        if copied[b] is not None:                 # the buffer's previous copy is done
-            compute.wait_event(copied[b])
-        out = c3[b][:m]
-        ps.ps3(V, s=s, n2=n2, j_begin=a, j_end=e, c3=out, acc=acc, tile=tile, path=path,
-               levels=levels)
-        if reduce == "u8":
-            ps.quantize_u8(out, out=dout[b][:m])
-        elif reduce == "threshold":
-            dsel[b] = ps.threshold(out, threshold, base=ps.stage_size(n_v, 1, a), cap=cap_)
-        done = torch.cuda.Event()
-        done.record(compute)
+        compute = computes[k % 2]
+        with torch.cuda.stream(compute):
+            if copied[b] is not None:             # the buffer's previous copy is done
+                compute.wait_event(copied[b])
+            out = c3[b][:m]
+            ps.ps3(V, s=s, n2=n2, j_begin=a, j_end=e, c3=out, acc=acc, tile=tile, path=path,
+                   levels=levels)
+            if reduce == "u8":
+                ps.quantize_u8(out, out=dout[b][:m])
+            elif reduce == "threshold":
+                dsel[b] = ps.threshold(out, threshold, base=ps.stage_size(n_v, 1, a), cap=cap_)
+            done = torch.cuda.Event()
+            done.record(compute)
         copy.wait_event(done)
         with torch.cuda.stream(copy):
             if reduce == "threshold":
@@ -133,7 +147,7 @@ def run3(V: torch.Tensor, n_stages: int, sink, reduce: str = "u8", threshold: fl
         copied[b] = ev
 
     def deliver(k):
-        b = k % 2
+        b = k % nbuf
         a, e = stages[k]
         m = ps.stage_size(n_v, a, e)
         copied[b].synchronize()
@@ -148,12 +162,15 @@ def run3(V: torch.Tensor, n_stages: int, sink, reduce: str = "u8", threshold: fl
             st.idx, st.val, st.dropped = hidx[b][:kept], hval[b][:kept], cnt - kept
         sink(st)
 
-    launch(0)
-    for k in range(1, len(stages)):
-        launch(k)          # stage k computes while stage k-1 is copied and delivered
-        deliver(k - 1)
-    deliver(len(stages) - 1)
-    copy.synchronize()
+    ahead = nbuf - 1            # stages queued while the oldest one is delivered
+    for k in range(ahead):
+        launch(k)
+    for k in range(len(stages)):
+        if k + ahead < len(stages):
+            launch(k + ahead)   # its set was used by stage k - 1, delivered already
+        deliver(k)
+    copy.synchronize()          # every stage's copy, hence every stage, has finished
+    main.wait_stream(copy)
     return len(stages)
 
 
