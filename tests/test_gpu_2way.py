@@ -253,6 +253,22 @@ def test_mfma_auto_path_and_unaligned_rows():
     check_exact_f32(host(c2), oracle.c2_all(V), "c2")
 
 
+def test_mfma_plane_rows_beyond_32bit_tile_offsets():
+    """levels * n_f too large for 32-bit offsets over 256 plane rows: an
+    explicit MFMA path is refused (PS_ERR_UNSUPPORTED) and AUTO takes the
+    VALU path, still exact."""
+    from paper_1705_08210_amd import ps
+    n_f = 2_900_000                       # 3 levels: 8.7e6 plane bytes per row
+    V = workloads.levels(3, n_f, seed=43)
+    announce(f"2-way mfma limit n_f={n_f}")
+    Vd = to_dev(V)
+    with pytest.raises(ps.PSError) as e:
+        ps.ps2(Vd, path="mfma", levels=3)
+    assert e.value.status == 5
+    c2, _ = ps.ps2(Vd, levels=3)
+    check_exact_f32(host(c2), oracle.c2_all(V), "c2")
+
+
 # ------------------------------------------ blocked (field-chunk) split ----
 
 @pytest.mark.parametrize("tile", [1, 2, 3])
