@@ -145,14 +145,17 @@ struct MfmaArgs {
     const int64_t* prefix;
     uint32_t* c3;
     int64_t item0;        // first work item of this launch
+    int32_t mode, ob;     // 3-way tile set (slab_tile_count) and its outer tile edge
 };
 
 // Wave w owns j rows [(w%2)*128, +128) and i columns [(w/2)*32*WN, +32*WN)
 // of the 256 x 256 tile: 4 x WN blocks of 32 x 32.  WN = 2: 8 waves, 128
 // accumulator registers, 2 waves per SIMD; WN = 4: 4 waves, 256 accumulator
 // registers (AGPRs), one wave per SIMD, a third less LDS traffic per MAC.
-template <int WN>
-__host__ __device__ constexpr int mfma_threads() { return 64 * 2 * (kMB / (32 * WN)); }
+// The 128 x 128 tile (TB = 128, 3-way slab edges) halves the wave rows: 4
+// waves of 2 x 2 blocks, two workgroups per CU.
+template <int WN, int TB = kMB>
+__host__ __device__ constexpr int mfma_threads() { return 64 * 2 * (TB / (32 * WN)); }
 
 // Epilogue of one wave's 4 x WN blocks of 32 x 32 (Section 2.1): n2 exact,
 // c2 = 2 n2 / (s_i + s_j) in FP64, rounded once to FP32, d = 0 gives 0.
@@ -195,11 +198,11 @@ template <int FMT>
 using mfma_acc_t = typename std::conditional<FMT == kFmtF4, v16f_t, v16i_t>::type;
 
 // LDS of the register-staged tile: two buffers for each of the two operands.
-template <int FMT, int WN>
-constexpr int mfma_lds_bytes() { return 4 * kMB * (mfma_mk<FMT, WN>() + kPad); }
+template <int FMT, int WN, int TB = kMB>
+constexpr int mfma_lds_bytes() { return 4 * TB * (mfma_mk<FMT, WN>() + kPad); }
 
-// Main loop of one register-staged 256 x 256 tile: A rows a0 .. a0+255 and
-// B rows b0 .. b0+255 of the planes (rows at or past n_v read as zero); with
+// Main loop of one register-staged TB x TB tile: A rows a0 .. a0+TB-1 and
+// B rows b0 .. b0+TB-1 of the planes (rows at or past n_v read as zero); with
 // MASK every B chunk is ANDed with the same chunk of plane row `mrow` (the
 // 3-way X_j operand: [v_i >= t] AND [v_j >= t] = [min(v_i, v_j) >= t]).
 // Field tile kt+1 is written from registers into the second LDS buffer while
@@ -208,33 +211,34 @@ constexpr int mfma_lds_bytes() { return 4 * kMB * (mfma_mk<FMT, WN>() + kPad); }
 // measured slower on int8).  The loads are buffer loads with 32-bit offsets
 // (measured 12% faster on int8 than 64-bit addresses with row tests).  Waves
 // that are not `active` take part in staging and barriers only.
-template <int FMT, int WN, bool MASK>
+template <int FMT, int WN, bool MASK, int TB = kMB>
 __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t b0,
                                           const int8_t* mrow, bool active, int wr, int wc,
-                                          mfma_acc_t<FMT> (&acc)[4][WN], int8_t* lds) {
-    constexpr int kMThreads = mfma_threads<WN>();
+                                          mfma_acc_t<FMT> (&acc)[TB / 64][WN], int8_t* lds) {
+    constexpr int WM = TB / 64;                    // 32-row blocks per wave
+    constexpr int kMThreads = mfma_threads<WN, TB>();
     constexpr int kMK = mfma_mk<FMT, WN>();
     constexpr int kPitch = kMK + kPad;
     constexpr int kRowChunks = kMK / 16;           // 16-byte chunks per tile row
-    constexpr int kStage = kMB * kRowChunks / kMThreads;   // 16-byte chunks per thread per operand
-    static_assert(kMB * kRowChunks % kMThreads == 0, "staging must divide evenly");
+    constexpr int kStage = TB * kRowChunks / kMThreads;   // 16-byte chunks per thread per operand
+    static_assert(TB * kRowChunks % kMThreads == 0, "staging must divide evenly");
     static_assert(kMThreads % kRowChunks == 0, "a thread's chunks share one column");
-    // two buffers per operand: [A0 | B0 | A1 | B1], each kMB * kPitch bytes
-    auto As = [&](int buf) { return lds + (2 * buf) * (kMB * kPitch); };
-    auto Bs = [&](int buf) { return lds + (2 * buf + 1) * (kMB * kPitch); };
+    // two buffers per operand: [A0 | B0 | A1 | B1], each TB * kPitch bytes
+    auto As = [&](int buf) { return lds + (2 * buf) * (TB * kPitch); };
+    auto Bs = [&](int buf) { return lds + (2 * buf + 1) * (TB * kPitch); };
     const int lane = threadIdx.x % 64;
 
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < WM; ++m)
 #pragma unroll
         for (int n = 0; n < WN; ++n) acc[m][n] = (mfma_acc_t<FMT>){};
 
-    // staging: 256 rows x kMK bytes per operand, kRowChunks threads per row.
+    // staging: TB rows x kMK bytes per operand, kRowChunks threads per row.
     // Buffer resources over the tile's A and B rows (the host checks that 256
     // plane rows span < 2^31 bytes): rows at or past n_v lie past num_records,
     // where buffer loads return zero without a memory access.
     auto rsrc = [&](int64_t r0) {
-        const int64_t rows = r0 < a.n_v ? (a.n_v - r0 < kMB ? a.n_v - r0 : kMB) : 0;
+        const int64_t rows = r0 < a.n_v ? (a.n_v - r0 < TB ? a.n_v - r0 : TB) : 0;
         return __builtin_amdgcn_make_buffer_rsrc((void*)(a.P + (rows > 0 ? r0 : 0) * a.kp),
                                                  (short)0, (int)(rows * a.kp), kRsrcWord3);
     };
@@ -285,15 +289,15 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t
         const int8_t* B = Bs(cur);
 #pragma unroll
         for (int ks = 0; ks < kMK / 32; ++ks) {
-            v4i_t fa[4], fb[WN];
+            v4i_t fa[WM], fb[WN];
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < WM; ++m)
                 fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
 #pragma unroll
             for (int n = 0; n < WN; ++n)
                 fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < WM; ++m)
 #pragma unroll
                 for (int n = 0; n < WN; ++n) {
                     if constexpr (FMT == kFmtI8) {
@@ -314,20 +318,22 @@ __device__ __forceinline__ void mfma_tile(const MfmaArgs& a, int64_t a0, int64_t
         // reads between the MFMAs of this one, the staging writes of the
         // next field tile between the MFMAs of the last k-step
         if constexpr (FMT == kFmtI8 && WN == 2 && kMK == 128) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+            constexpr int R = WM + WN, M = WM * WN, W = 2 * kStage;   // per k-step / tile
+            static_assert(M >= R && W % M == 0, "schedule pattern");
+            __builtin_amdgcn_sched_group_barrier(0x100, R, 0);
 #pragma unroll
             for (int ks = 0; ks < kMK / 32 - 1; ++ks) {
 #pragma unroll
-                for (int i = 0; i < 6; ++i) {
+                for (int i = 0; i < R; ++i) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
                 }
-                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                if constexpr (M > R) __builtin_amdgcn_sched_group_barrier(0x008, M - R, 0);
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < M; ++i) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, W / M, 0);
             }
         }
         __syncthreads();   // kt+1 visible; everyone is done reading kt
@@ -376,35 +382,38 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_kernel(MfmaArg
 // P_j while staging, so the lane index of the MFMA output runs along i and 32
 // lanes store 32 consecutive entries of the j-slab layout.  The exact integer
 // n3' is stored as int32 bits; the integer 3-way finish applies Eq. 1.
+// Two launches cover each slab rectangle: TB = 256 over its whole 256 x 256
+// tiles, TB = 128 over the rest (two workgroups per CU, so one workgroup's
+// waves that lie outside the rectangle leave their SIMD to the other's).
 // ---------------------------------------------------------------------------
-template <int FMT>
-__global__ __launch_bounds__(mfma_threads<2>(), 1) void ps_mfma3_kernel(MfmaArgs a) {
-    constexpr int WN = 2;
-    __shared__ __attribute__((aligned(16))) int8_t lds[mfma_lds_bytes<FMT, WN>()];
+template <int FMT, int TB>
+__global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_kernel(MfmaArgs a) {
+    constexpr int WN = 2, WM = TB / 64;
+    __shared__ __attribute__((aligned(16))) int8_t lds[mfma_lds_bytes<FMT, WN, TB>()];
     const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
                       blockIdx.x / kXcds;
     if (t >= a.ntiles) return;
-    // slab j: largest jj with prefix[jj] <= t (every slab has >= 1 tile)
+    // slab j: largest jj with prefix[jj] <= t (the slab holding tile t; slabs
+    // without tiles in this tile set repeat their prefix and are passed)
     int64_t lo = 0, hi = a.j_end - a.j_begin;
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) / 2;
         if (a.prefix[mid] <= t) lo = mid; else hi = mid;
     }
     const int64_t j = a.j_begin + lo;
-    const int64_t local = t - a.prefix[lo];
-    const int64_t nbk = (a.n_v - 1 - j + kMB - 1) / kMB;
-    const int64_t i0 = (local / nbk) * kMB, k0 = j + 1 + (local % nbk) * kMB;
+    int64_t i0, k0;
+    slab_tile_origin(a.n_v, j, t - a.prefix[lo], TB, a.mode, a.ob, i0, k0);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int wr = (wave % 2) * 128;        // k offset of the wave's block (A rows)
+    const int wr = (wave % 2) * (TB / 2);   // k offset of the wave's block (A rows)
     const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
     const bool active = (k0 + wr < a.n_v) && (i0 + wc < j);
-    mfma_acc_t<FMT> acc[4][WN];
-    mfma_tile<FMT, WN, true>(a, k0, i0, a.P + j * a.kp, active, wr, wc, acc, lds);
+    mfma_acc_t<FMT> acc[WM][WN];
+    mfma_tile<FMT, WN, true, TB>(a, k0, i0, a.P + j * a.kp, active, wr, wc, acc, lds);
     if (!active) return;
     const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin);
     const int64_t ib = i0 + wc + (lane % 32);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < WM; ++m) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t k = k0 + wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
@@ -613,16 +622,32 @@ static hipError_t go_mfma3(const MfmaLaunch& m, hipStream_t st) {
     int64_t kp = 0;
     hipError_t e = expand_planes<FMT>(m, kp, st);
     if (e != hipSuccess) return e;
-    e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kMB, kSlabAll, kMB, m.prefix, st);
+    // whole 256-wide tiles of each slab rectangle, then 128-wide edge tiles
+    constexpr int kEdge = kMB / 2;
+    e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kMB, kSlabFull, kMB, m.prefix, st);
+    if (e == hipSuccess)
+        e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kEdge, kSlabEdge, kMB, m.edge_prefix, st);
     if (e != hipSuccess) return e;
-    const int64_t T = slab_tiles(m.n_v, m.j_begin, m.j_end, kMB, kSlabAll, kMB);
-    if (T == 0) return hipSuccess;
-    MfmaArgs a{m.planes, kp, m.n_v, m.s, nullptr, nullptr, 0, T, m.j_begin, m.j_end, m.prefix,
-               (uint32_t*)m.c3, 0};
-    return launch_items(T, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+    const int64_t T1 = slab_tiles(m.n_v, m.j_begin, m.j_end, kMB, kSlabFull, kMB);
+    const int64_t T2 = slab_tiles(m.n_v, m.j_begin, m.j_end, kEdge, kSlabEdge, kMB);
+    MfmaArgs a{m.planes, kp, m.n_v, m.s, nullptr, nullptr, 0, T1, m.j_begin, m.j_end, m.prefix,
+               (uint32_t*)m.c3, 0, kSlabFull, kMB};
+    if (T1 > 0)
+        e = launch_items(T1, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+            MfmaArgs b = a;
+            b.item0 = item0;
+            hipLaunchKernelGGL((ps_mfma3_kernel<FMT, kMB>), dim3(grid), dim3(mfma_threads<2>()),
+                               0, st, b);
+        });
+    if (e != hipSuccess || T2 == 0) return e;
+    a.ntiles = T2;
+    a.prefix = m.edge_prefix;
+    a.mode = kSlabEdge;
+    return launch_items(T2, mfma_threads<2, kEdge>(), kXcds, [&](unsigned grid, int64_t item0) {
         MfmaArgs b = a;
         b.item0 = item0;
-        hipLaunchKernelGGL(ps_mfma3_kernel<FMT>, dim3(grid), dim3(mfma_threads<2>()), 0, st, b);
+        hipLaunchKernelGGL((ps_mfma3_kernel<FMT, kEdge>), dim3(grid),
+                           dim3(mfma_threads<2, kEdge>()), 0, st, b);
     });
 }
 

@@ -321,8 +321,8 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
         if (e != hipSuccess) return hip_fail(e, "sums launch");
         s = s_ws;
     }
-    MfmaLaunch m{V, n_f, n_v, ld, levels, s, nullptr, nullptr, (int8_t*)planes, fmt, 0,
-                 1, j_begin, j_end, prefix, c3};
+    MfmaLaunch m{V,       n_f,     n_v,   ld, levels, s,      nullptr, nullptr, (int8_t*)planes,
+                 fmt,     0,       1,     j_begin, j_end, prefix, c3, prefix + (n_v + 1)};
     if (!n2) {   // pair numerators; this launch also writes the planes
         MfmaLaunch m2 = m;
         m2.n2 = n2_ws;

@@ -319,6 +319,7 @@ struct MfmaLaunch {
     int64_t j_begin, j_end;
     int64_t* prefix;             // workspace: j_end - j_begin + 1 int64
     float* c3;
+    int64_t* edge_prefix;        // 3-way: the edge tiles' slab prefix, as prefix
 };
 size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt);
 // Bytes of one thermometer plane row (all levels) of an n_f-field vector.

@@ -256,3 +256,29 @@ def test_edge_tiles_with_field_chunks_and_stages():
     assert np.array_equal(np.concatenate(parts).view(np.uint32), full.view(np.uint32))
     i, j, k = sample_triples(n_v, 1024, seed=92)
     check_rel(full[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), FP32_TOL, "c3")
+
+
+@pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
+@pytest.mark.parametrize("n_v", [300, 600])
+def test_mfma_whole_and_edge_tiles(path, n_v):
+    """The matrix-core slices run 256-wide tiles over the whole tiles of each
+    slab rectangle (from n_v = 513 there are some) and 128-wide tiles over
+    the rest: every triple is written once (NaN-filled output) and equals the
+    VALU result bit for bit; stages concatenate to the full run."""
+    import torch
+    from paper_1705_08210_amd import ps
+    V = workloads.levels(n_v, 333, seed=n_v + 7)
+    Vd = to_dev(V)
+    announce(f"3-way {path} whole + edge tiles n_v={n_v}")
+    c3 = torch.full((ps.stage_size(n_v, 1, n_v - 1),), float("nan"), device=Vd.device)
+    ps.ps3(Vd, c3=c3, path=path, levels=3)
+    got = host(c3)
+    assert not np.isnan(got).any()
+    ref = host(ps.ps3(Vd, path="valu"))
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    cuts = [1, 200, 257, n_v - 1]
+    parts = [host(ps.ps3(Vd, j_begin=a, j_end=b, path=path, levels=3))
+             for a, b in zip(cuts, cuts[1:])]
+    assert np.array_equal(np.concatenate(parts).view(np.uint32), got.view(np.uint32))
+    i, j, k = sample_triples(n_v, 2048, seed=n_v + 8)
+    check_exact_f32(got[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), "c3")
