@@ -158,13 +158,26 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
 // slice j; the triples of the slice are contiguous in the j-slab layout, with
 // i fastest.  n3 = ((n2(i,j) + n2(i,k)) + n2(j,k)) - n3', d3 = (s_i + s_j) + s_k,
 // c3 = (3 n3) / (2 d3) in FP64, rounded once to FP32.
+// Outputs per workgroup of the finish: 256 threads x 8.  Work items are
+// (slab, range of kFinishRange consecutive outputs), found through a slab
+// prefix of the range counts, so every workgroup has the same work whatever
+// the slab sizes.
+constexpr int kFinishRange = 2048;
+
 template <int DT>
-__global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
+__global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a, int64_t nitems,
+                                                           int64_t item0) {
     using N2T = typename std::conditional<
         DT == PS_U8 || DT == PS_B1, int32_t,
         typename std::conditional<DT == PS_F64, double, float>::type>::type;
-    const int64_t j = a.j_begin + blockIdx.x;
-    if (j >= a.j_end) return;
+    const int64_t b = item0 + blockIdx.x;
+    if (b >= nitems) return;
+    int64_t lo = 0, hi = a.j_end - a.j_begin;   // slab holding range b (see ps_mg3_kernel)
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (a.prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    const int64_t j = a.j_begin + lo;
     const N2T* N2 = (const N2T*)a.n2;
     const int64_t n_v = a.n_v;
     const int64_t base = slab_offset(n_v, j) - slab_offset(n_v, a.j_begin);
@@ -173,8 +186,22 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
     const int64_t nj = j * (j - 1) / 2;
     uint32_t* io = (uint32_t*)a.c3;
     const int64_t stage = slab_offset(n_v, a.j_end) - slab_offset(n_v, a.j_begin);
-    for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
-        const int64_t k = j + 1 + t / j, i = t % j;
+    const int64_t t0 = (b - a.prefix[lo]) * kFinishRange;
+    const bool small = cnt <= 0xffffffffLL;   // 32-bit division suffices
+#pragma unroll 4
+    for (int e = 0; e < kFinishRange / 256; ++e) {
+        const int64_t t = t0 + e * 256 + threadIdx.x;
+        if (t >= cnt) break;
+        int64_t kk, i;   // t = (k - j - 1) j + i
+        if (small) {
+            const uint32_t q = (uint32_t)t / (uint32_t)j;
+            kk = q;
+            i = (int64_t)((uint32_t)t - q * (uint32_t)j);
+        } else {
+            kk = t / j;
+            i = t - kk * j;
+        }
+        const int64_t k = j + 1 + kk;
         const uint32_t raw = (a.nchunks > 1 || DT == PS_F64) ? 0u : io[base + t];
         const double nij = (double)N2[nj + i];
         const double nik = (double)N2[k * (k - 1) / 2 + i];
@@ -202,12 +229,20 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a) {
     }
 }
 
+// The finish after the slice launches of a: its slab prefix (over output
+// ranges) reuses a.prefix, which the slice launches before it on the stream
+// have finished reading.
 template <int DT>
 hipError_t go_c3_finish(const Mg3Launch& a, hipStream_t st) {
     if (a.j_end <= a.j_begin) return hipSuccess;
-    hipLaunchKernelGGL(ps_c3_finish_kernel<DT>, dim3((unsigned)(a.j_end - a.j_begin)),
-                       dim3(256), 0, st, a);
-    return hipGetLastError();
+    hipError_t e = launch_prefix3(a.n_v, a.j_begin, a.j_end, kFinishRange, kSlabRange, 0,
+                                  a.prefix, st);
+    if (e != hipSuccess) return e;
+    const int64_t n = slab_tiles(a.n_v, a.j_begin, a.j_end, kFinishRange, kSlabRange, 0);
+    if (n == 0) return hipSuccess;
+    return launch_items(n, 256, 1, [&](unsigned grid, int64_t item0) {
+        hipLaunchKernelGGL(ps_c3_finish_kernel<DT>, dim3(grid), dim3(256), 0, st, a, n, item0);
+    });
 }
 
 // ---------------------------------------------------------------------------

@@ -73,11 +73,14 @@ __host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
 //              and K1 = j + 1 + ob floor((n_v - 1 - j) / ob).
 // kSlabFull with ob tiles plus kSlabEdge with smaller bm tiles cover the
 // rectangle exactly once, with edge waste at the bm granularity only.
-enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2 };
+// kSlabRange counts ranges of bm consecutive outputs of the slab instead
+// (the elementwise 3-way finish).
+enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2, kSlabRange = 3 };
 
 __host__ __device__ inline int64_t slab_tile_count(int64_t n_v, int64_t j, int bm, int mode,
                                                    int ob) {
     const int64_t wk = n_v - 1 - j;
+    if (mode == kSlabRange) return (j * wk + bm - 1) / bm;
     if (mode == kSlabAll) return ((j + bm - 1) / bm) * ((wk + bm - 1) / bm);
     if (mode == kSlabFull) return (j / ob) * (wk / ob);
     const int64_t i1 = j / ob * ob, rk = wk % ob;
