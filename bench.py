@@ -188,8 +188,9 @@ def traffic_file(kernel, key):
 
 
 def recorded_traffic(kernel, key):
-    """HBM bytes per launch from a committed counter summary, or None when
-    there is none or the kernel's sources changed since it was taken."""
+    """HBM bytes per call (all dispatches of the kernel in one library call)
+    from a committed counter summary, or None when there is none, it predates
+    this format, or the kernel's sources changed since it was taken."""
     path = traffic_file(kernel, key)
     if not os.path.exists(path):
         return None
@@ -199,9 +200,10 @@ def recorded_traffic(kernel, key):
             if ":" in line:
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("sources_sha256") != source_digest(kernel):
+    if fields.get("sources_sha256") != source_digest(kernel) or \
+            "traffic_bytes_per_call" not in fields:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(fields["traffic_bytes_per_call"])
 
 
 def roofline(bound, ops_per_cmp, cmp, kernel_ms, peak, traffic=None):
@@ -240,9 +242,15 @@ def pmc_summary(fetch_dir, write_dir, kernel, key, commands):
     wf, wv, wk = calib(write)
 
     def mean(cnt):
-        v = [x for k, x in cnt.items()
-             if k[1].startswith(f"void ps::{kernel}<") or k[1].startswith(f"ps::{kernel}(")]
-        return sum(v) / len(v), len(v)
+        # per call: the mean over the dispatches of each instance of the
+        # kernel (the 3-way slices launch two tile sizes per call), summed
+        inst = {}
+        for k, x in cnt.items():
+            if k[1].startswith(f"void ps::{kernel}<") or k[1].startswith(f"ps::{kernel}("):
+                inst.setdefault(k[1], []).append(x)
+        return (sum(sum(v) / len(v) for v in inst.values()),
+                f"{len(inst)} kernel instance(s), mean of {min(len(v) for v in inst.values())}"
+                " dispatches each")
 
     fm, fn = mean(fetch)
     wm, wn = mean(write)
@@ -254,16 +262,16 @@ def pmc_summary(fetch_dir, write_dir, kernel, key, commands):
         f"-> factor {ff:.4f}",
         f"calibration write: copy dispatch {wk[0]} writes 1 GiB, WRITE_SIZE {wv:.1f} KiB "
         f"-> factor {wf:.4f}",
-        f"FETCH_SIZE per dispatch: {fm:.1f} KiB (mean of {fn}) -> {fm * 1024 * ff / 1e9:.3f} GB",
-        f"WRITE_SIZE per dispatch: {wm:.1f} KiB (mean of {wn}) -> {wm * 1024 * wf / 1e9:.3f} GB",
-        f"traffic_bytes_per_launch: {int(round(traffic))}",
+        f"FETCH_SIZE per call: {fm:.1f} KiB ({fn}) -> {fm * 1024 * ff / 1e9:.3f} GB",
+        f"WRITE_SIZE per call: {wm:.1f} KiB ({wn}) -> {wm * 1024 * wf / 1e9:.3f} GB",
+        f"traffic_bytes_per_call: {int(round(traffic))}",
         f"sources_sha256: {source_digest(kernel)}",
     ]
     return "\n".join(lines) + "\n"
 
 
 def counter_summary(d, kernel, commands):
-    """Means per dispatch of the counters of one rocprofv3 --pmc run and what
+    """Per-call sums of the counters of one rocprofv3 --pmc run and what
     they give.  GRBM_GUI_ACTIVE counts GPU cycles on each of the 8 XCDs, so
     cycles = GRBM_GUI_ACTIVE / 8 and the clock = cycles / dispatch duration.
     MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles); VALU issue
@@ -271,7 +279,7 @@ def counter_summary(d, kernel, commands):
     (FP32 min/add issue up to 2, packed FP16 and v_sad_u8 up to 1)."""
     import csv
     import glob
-    per, dur = {}, {}
+    per, dur, name = {}, {}, {}
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         with open(f) as fh:
             for r in csv.DictReader(fh):
@@ -281,15 +289,24 @@ def counter_summary(d, kernel, commands):
                 key = (r["Dispatch_Id"], r["Counter_Name"])
                 per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
                 dur[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    sums = {}
+                name[r["Dispatch_Id"]] = n
+    # per call: means over the dispatches of each kernel instance, summed over
+    # the instances (the 3-way slices launch two tile sizes per call)
+    inst = {}
     for (disp, c), v in per.items():
-        sums.setdefault(c, []).append(v)
-    m = {c: sum(v) / len(v) for c, v in sums.items()}
+        inst.setdefault((name[disp], c), []).append(v)
+    m = {}
+    for (n, c), v in inst.items():
+        m[c] = m.get(c, 0.0) + sum(v) / len(v)
+    idur = {}
+    for disp, ns_ in dur.items():
+        idur.setdefault(name[disp], []).append(ns_)
     lines = [f"kernel: {kernel}"] + [f"command: {c}" for c in commands]
-    lines += [f"{c} per dispatch: {m[c]:.6g}" for c in sorted(m)]
+    lines += [f"{c} per call: {m[c]:.6g}" for c in sorted(m)]
     if dur:
-        ns = sum(dur.values()) / len(dur)
-        lines.append(f"dispatch duration: {ns / 1e6:.3f} ms (mean of {len(dur)})")
+        ns = sum(sum(v) / len(v) for v in idur.values())
+        lines.append(f"duration per call: {ns / 1e6:.3f} ms ({len(idur)} kernel instance(s), "
+                     f"mean of {min(len(v) for v in idur.values())} dispatches each)")
     if "GRBM_GUI_ACTIVE" in m:
         cyc = m["GRBM_GUI_ACTIVE"] / 8.0
         if dur:
