@@ -31,6 +31,8 @@ CASES = textwrap.dedent("""
     out["c2_split"] = ps.ps2(Vf, acc="blocked", tile=2)[0]
     Vg = dev(workloads.sparse_uniform(300, 900, seed=82))
     out["c3"] = ps.ps3(Vg, tile=2)
+    Vh = dev(workloads.sparse_uniform(1100, 200, seed=86))   # whole + edge tile launches
+    out["c3_edges"] = ps.ps3(Vh, j_begin=400, j_end=430)
     Vl = dev(workloads.levels(1300, 500, seed=83))
     out["mfma"] = ps.ps2(Vl, path="mfma", levels=3)[0]
     out["fp4"] = ps.ps2(Vl, path="mfma_fp4", levels=3)[0]
