@@ -158,7 +158,8 @@ size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
  *           into the workspace
  *   c2      device float, n_v(n_v-1)/2, colex layout; may be NULL if n2 given
  *   n2      device, optional raw numerators n2(i,j) in colex layout: float
- *           for PS_F32/PS_F16, int32 for PS_U8 (every path); may be NULL
+ *           for PS_F32/PS_F16, double for PS_F64, int32 for PS_U8 (every
+ *           path); may be NULL
  *   workspace / ws_bytes   device scratch, at least ps2_workspace_size()
  *   opts    may be NULL (all defaults)
  * Each c2 is formed in FP64 from the numerator and FP64 sums, then rounded
@@ -183,11 +184,13 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
  * range; calling with consecutive ranges and concatenating the outputs gives
  * the full j-slab layout.
  *   s      device FP64 sums, or NULL (computed into the workspace)
- *   n2     device pair numerators in colex layout (float for F32/F16, int32
- *          for U8, as written by ps2_compute for the same V), or NULL to
- *          compute them into the workspace
- *   opts   path VALU (default) or BITS (binary U8 data, X_j = V AND v_j);
- *          the MFMA paths give PS_ERR_UNSUPPORTED
+ *   n2     device pair numerators in colex layout (float for F32/F16, double
+ *          for F64, int32 for U8, as written by ps2_compute for the same V),
+ *          or NULL to compute them into the workspace
+ *   opts   path VALU, BITS (binary U8 data, X_j = V AND v_j), or for U8
+ *          data the MFMA paths (the thermometer planes with the B operand
+ *          ANDed with the planes of v_j: [a>=t][b>=t][c>=t] =
+ *          [min(a,b,c)>=t], exact); AUTO picks as for ps2_compute
  *   c3     device float; receives the triples of [j_begin, j_end) packed in
  *          j-slab order starting at offset 0 (i.e. at global index
  *          off(j_begin))
