@@ -180,7 +180,8 @@ def ps3(V: torch.Tensor, s: torch.Tensor | None = None, n2: torch.Tensor | None 
         c3: torch.Tensor | None = None, stream=None, path="auto",
         levels=0) -> torch.Tensor:
     """3-way metric of the triples i<j<k with j in [j_begin, j_end), j-slab
-    packed from offset 0.  path "bits" (with levels=1) for binary uint8 data."""
+    packed from offset 0.  path "bits" (with levels=1) for binary uint8 data;
+    "mfma" / "mfma_fp4" (with levels >= max(V)) for uint8 levels."""
     dt, n_f, n_v, ld = _matrix(V)
     if j_end is None:
         j_end = max(n_v - 1, j_begin)
