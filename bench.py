@@ -60,6 +60,8 @@ def parse(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-3way", action="store_true",
+                    help="default workload: skip the 3-way measurement of the same line")
     ap.add_argument("--per-problem", action="store_true",
                     help="batched workload: one launch per problem instead of the plan")
     ap.add_argument("--campaign", type=int, default=0, metavar="STAGES",
@@ -101,7 +103,20 @@ class Timer:
         return sum(v) / len(v) if v else float("nan")
 
 
-def cpu_baseline_pairs(V, n_f, seconds, seed=123):
+def _oracle_rate(run, seconds, m0=256, cap=1 << 24):
+    """Grow the sample until one run takes 0.2 s, then size it to `seconds`.
+    run(m) -> (seconds taken, tuples done)."""
+    m = m0
+    t, m = run(m)
+    while t < 0.2 and m < cap:
+        t, m = run(m * 4)
+    return run(max(m0, int(m * seconds / max(t, 1e-9))))
+
+
+def cpu_baseline(V, n_f, seconds, way, seed=123):
+    """The oracle timed on the host: c2 (way 2) or c3 (way 3) of random
+    tuples of the full input, once on all threads and once on one thread
+    (each about `seconds`)."""
     import numpy as np
 
     import oracle
@@ -110,50 +125,32 @@ def cpu_baseline_pairs(V, n_f, seconds, seed=123):
     s = oracle.sums(V)
 
     def run(m):
-        a = g.integers(0, n_v, size=m)
-        b = (a + 1 + g.integers(0, n_v - 1, size=m)) % n_v
-        t0 = time.perf_counter()
-        oracle.c2_pairs(V, a, b, s=s)
-        return time.perf_counter() - t0
-
-    m = 256
-    t = run(m)
-    while t < 0.2 and m < (1 << 24):
-        m *= 4
-        t = run(m)
-    m = max(256, int(m * seconds / max(t, 1e-9)))
-    t = run(m)
-    return {"value": m * n_f / t, "unit": "comparisons/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{m} random pairs of the full input, {n_f} fields each "
-                      f"(oracle c2 of listed pairs, {t:.1f} s)"}
-
-
-def cpu_baseline_triples(V, n_f, seconds, seed=123):
-    import numpy as np
-
-    import oracle
-    g = np.random.default_rng(seed)
-    n_v = V.shape[0]
-    s = oracle.sums(V)
-
-    def run(m):
+        if way == 2:
+            a = g.integers(0, n_v, size=m)
+            b = (a + 1 + g.integers(0, n_v - 1, size=m)) % n_v
+            t0 = time.perf_counter()
+            oracle.c2_pairs(V, a, b, s=s)
+            return time.perf_counter() - t0, m
         t = np.sort(g.integers(0, n_v, size=(3 * m, 3)), axis=1)
         t = t[(t[:, 0] < t[:, 1]) & (t[:, 1] < t[:, 2])][:m]
         t0 = time.perf_counter()
         oracle.c3_triples(V, t[:, 0], t[:, 1], t[:, 2], s=s)
         return time.perf_counter() - t0, len(t)
 
-    m = 256
-    t, m = run(m)
-    while t < 0.2 and m < (1 << 22):
-        t, m = run(m * 4)
-    t, m = run(max(256, int(m * seconds / max(t, 1e-9))))
-    # each listed triple evaluates its three pair terms directly as well
-    return {"value": m * n_f / t, "unit": "comparisons/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{m} random triples of the full input, {n_f} fields each "
-                      f"(oracle c3 of listed triples, pair terms included, {t:.1f} s)"}
+    threads = oracle.num_threads()
+    t, m = _oracle_rate(run, seconds)
+    oracle.set_threads(1)
+    try:
+        t1, m1 = _oracle_rate(run, seconds)
+    finally:
+        oracle.set_threads(threads)
+    what = "pairs" if way == 2 else "triples"
+    extra = "" if way == 2 else ", pair terms included"
+    return {"value": m * n_f / t, "unit": "comparisons/s", "cores": threads, "kind": "oracle",
+            "value_1thread": m1 * n_f / t1,
+            "sample": f"{m} random {what} of the full input on {threads} threads ({t:.1f} s) "
+                      f"and {m1} on 1 thread ({t1:.1f} s), {n_f} fields each (oracle c{way} of "
+                      f"listed {what}{extra})"}
 
 
 # Source files that decide what each kernel does and how it is launched; their
@@ -323,50 +320,72 @@ def counter_summary(d, kernel, commands):
     return "\n".join(lines) + "\n"
 
 
-def traffic_key(args):
+def traffic_key(args, wl):
     """Workload and operand type of a run: names its traffic file."""
-    wl = args.workload
     if wl in ("levels_8192x32768", "binary_8192x32768", "levels_4096x1024"):
         return wl + {"mfma_fp4": "_fp4", "bits": "_bits"}.get(args.path, "_u8")
     return wl + {"f16": "_f16", "f64": "_f64"}.get(args.storage, "_f32")
 
 
-def main(argv=None):
-    args = parse(argv)
-    if args.counter_summary:
-        sys.stdout.write(counter_summary(args.counter_summary[0], args.counter_summary[1],
-                                         args.pmc_command))
-        return 0
-    if args.pmc_summary:
-        fetch_dir, write_dir, kernel = args.pmc_summary
-        sys.stdout.write(pmc_summary(fetch_dir, write_dir, kernel, traffic_key(args),
-                                     args.pmc_command))
-        return 0
-    if args.gpus != 1:
-        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
-              "(sharding across GPUs is not implemented)", file=sys.stderr)
-        return 2
+def _parity_pairs(Vh, c2_dev, n_v, m, seed, dev_to_host):
+    """Sampled pairs of a 2-way output against the oracle."""
+    import numpy as np
 
+    import oracle
+    g = np.random.default_rng(seed)
+    I = g.integers(0, n_v, m)
+    J = (I + 1 + g.integers(0, n_v - 1, m)) % n_v
+    I, J = np.minimum(I, J), np.maximum(I, J)
+    got = dev_to_host(c2_dev)[J * (J - 1) // 2 + I]
+    return got, oracle.c2_pairs(Vh, I, J)
+
+
+def _parity_triples(Vh, c3_dev, n_v, m, seed, dev_to_host):
+    import numpy as np
+
+    import oracle
+    g = np.random.default_rng(seed)
+    t = np.sort(g.integers(0, n_v, size=(3 * m, 3)), axis=1)
+    t = t[(t[:, 0] < t[:, 1]) & (t[:, 1] < t[:, 2])][:m]
+    i, j, k = t[:, 0], t[:, 1], t[:, 2]
+    off = (n_v - 1) * (j * (j - 1) // 2) - ((j - 1) * j * (2 * j - 1)) // 6
+    got = dev_to_host(c3_dev)[off + (k - j - 1) * j + i]
+    return got, oracle.c3_triples(Vh, i, j, k)
+
+
+def _errors(got, ref):
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64)
+    nz = ref > 0
+    rel = np.abs(got[nz] - ref[nz]) / ref[nz]
+    return {"tuples": int(len(ref)), "max_rel_err": float(rel.max()) if rel.size else 0.0,
+            "max_abs_err": float(np.abs(got - ref).max()) if len(ref) else 0.0,
+            "zero_mismatches": int(np.count_nonzero(got[~nz] != 0))}
+
+
+def measure(args, wl, K, W, with_cpu=True):
+    """Times K steps of one workload after W warm-ups; returns the bench
+    line's fields (metric, value, roofline, parity sample, oracle rates)."""
     import numpy as np
     import torch
 
     import workloads
     from paper_1705_08210_amd import ps
 
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        return 1
     dev = torch.device("cuda:0")
-    wl = args.workload
-    K, W = args.steps, args.warmup
     timer = Timer(torch)
     extra = {}
+    f16_source = None          # FP16 storage: the FP32 input it was rounded from
+
+    def to_host(t):
+        torch.cuda.synchronize()
+        return t.cpu().numpy()
 
     if wl in ("gwas_20000x16384", "uniform_1024x256", "levels_8192x32768",
               "binary_8192x32768"):
         V = workloads.WORKLOADS[wl](0)
         if args.storage == "f16" and V.dtype == np.float32:
-            V = workloads.to_f16(V)
+            f16_source, V = V, workloads.to_f16(V)
         elif args.storage == "f64" and V.dtype == np.float32:
             V = V.astype(np.float64)
         n_v, n_f = V.shape
@@ -409,12 +428,19 @@ def main(argv=None):
             dtype, bound, ops_per_cmp, peak = "f32", "alu", 2.0, FP32_LANE_OPS_TOPS
             kernel = "ps_mg2_kernel"
         config = {"workload": wl, "way": 2, "n_f": n_f, "n_v": n_v}
-        cpu = (lambda: cpu_baseline_pairs(V, n_f, args.cpu_seconds))
-        parity_fn = ("pairs", V)
+        cpu = (lambda: cpu_baseline(V, n_f, args.cpu_seconds, 2))
+
+        def parity():
+            got, ref = _parity_pairs(V, c2, n_v, 2048, 7, to_host)
+            out = _errors(got, ref)
+            if f16_source is not None:   # the user-visible error: against the FP32 input
+                got, ref = _parity_pairs(f16_source, c2, n_v, 2048, 7, to_host)
+                out["vs_fp32_source"] = _errors(got, ref)
+            return out
     elif wl in ("sparse_4096x1024", "levels_4096x1024"):
         V = workloads.WORKLOADS[wl](0)
         if args.storage == "f16" and V.dtype == np.float32:
-            V = workloads.to_f16(V)
+            f16_source, V = V, workloads.to_f16(V)
         elif args.storage == "f64" and V.dtype == np.float32:
             V = V.astype(np.float64)
         n_v, n_f = V.shape
@@ -434,6 +460,14 @@ def main(argv=None):
             if rec:
                 timer.add(a, timer.mark())
 
+        def parity():
+            got, ref = _parity_triples(V, c3, n_v, 2048, 7, to_host)
+            out = _errors(got, ref)
+            if f16_source is not None:
+                got, ref = _parity_triples(f16_source, c3, n_v, 2048, 7, to_host)
+                out["vs_fp32_source"] = _errors(got, ref)
+            return out
+
         if args.campaign > 0:   # staged: every stage's bytes end in host memory
             from paper_1705_08210_amd import campaign
             host_out = np.empty(math.comb(n_v, 3), dtype=np.uint8)
@@ -450,6 +484,7 @@ def main(argv=None):
             extra["campaign"] = {"stages": args.campaign, "output": "u8 to host",
                                  "timed": "whole campaign (sums, pair numerators, stages, "
                                           "quantize, device-to-host copies, host sink)"}
+            parity = None
 
         cmp = n_f * math.comb(n_v, 3)
         use_mfma = V.dtype == np.uint8 and (args.path in ("mfma", "mfma_fp4") or
@@ -471,8 +506,7 @@ def main(argv=None):
                                                                     (2.0, FP32_LANE_OPS_TOPS))
             kernel = "ps_mg3_kernel"
         config = {"workload": wl, "way": 3, "n_f": n_f, "n_v": n_v}
-        cpu = (lambda: cpu_baseline_triples(V, n_f, args.cpu_seconds))
-        parity_fn = ("triples", V) if args.campaign == 0 else None
+        cpu = (lambda: cpu_baseline(V, n_f, args.cpu_seconds, 3))
     elif wl == "batched_64_uneven":
         Vs_np = workloads.batched_64_uneven(0)
         Vs = [torch.from_numpy(x).to(dev) for x in Vs_np]
@@ -498,11 +532,17 @@ def main(argv=None):
         config = {"workload": wl, "way": 2, "problems": len(Vs),
                   "mode": "per-problem launches" if args.per_problem else "one graph"}
         big = max(range(len(Vs_np)), key=lambda t: Vs_np[t].size)
-        cpu = (lambda: cpu_baseline_pairs(Vs_np[big], Vs_np[big].shape[1], args.cpu_seconds))
-        parity_fn = None
+        cpu = (lambda: cpu_baseline(Vs_np[big], Vs_np[big].shape[1], args.cpu_seconds, 2))
+
+        def parity():   # 64 pairs of every problem
+            got, ref = [], []
+            for p, (Vh, (c, _, _)) in enumerate(zip(Vs_np, outs)):
+                g_, r_ = _parity_pairs(Vh, c, Vh.shape[0], 64, 100 + p, to_host)
+                got.append(g_)
+                ref.append(r_)
+            return _errors(np.concatenate(got), np.concatenate(ref))
     else:
-        print(f"unknown workload {wl}", file=sys.stderr)
-        return 2
+        raise ValueError(f"unknown workload {wl}")
 
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
@@ -520,49 +560,77 @@ def main(argv=None):
         step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = wall / K * 1e3
     kernel_ms = timer.mean_ms()
+    if args.campaign > 0:
+        from paper_1705_08210_amd import campaign
+        campaign.release()
 
-    # quick sampled parity against the oracle (not timed)
-    if parity_fn is not None:
-        import oracle
-        kind, Vh = parity_fn
-        g = np.random.default_rng(7)
-        if kind == "pairs":
-            I = g.integers(0, n_v, 2048)
-            J = (I + 1 + g.integers(0, n_v - 1, 2048)) % n_v
-            I, J = np.minimum(I, J), np.maximum(I, J)
-            got = c2.cpu().numpy()[J * (J - 1) // 2 + I]
-            ref = oracle.c2_pairs(Vh, I, J)
-        else:
-            t = np.sort(g.integers(0, n_v, size=(6000, 3)), axis=1)
-            t = t[(t[:, 0] < t[:, 1]) & (t[:, 1] < t[:, 2])][:2048]
-            i, j, k = t[:, 0], t[:, 1], t[:, 2]
-            off = (n_v - 1) * (j * (j - 1) // 2) - ((j - 1) * j * (2 * j - 1)) // 6
-            got = c3.cpu().numpy()[off - 0 + (k - j - 1) * j + i]
-            ref = oracle.c3_triples(Vh, i, j, k)
-        nz = ref > 0
-        rel = np.abs(got[nz] - ref[nz]) / ref[nz]
-        extra["parity_sample"] = {"tuples": int(len(ref)),
-                                  "max_rel_err": float(rel.max()) if rel.size else 0.0,
-                                  "max_abs_err": float(np.abs(got - ref).max())}
-
-    value = cmp * K / wall
+    if parity is not None:   # sampled parity against the oracle (not timed)
+        extra["parity_sample"] = parity()
     line = {
-        "metric": "elementwise comparisons/sec, 2-way & 3-way PS, 1 MI355X; % of VALU/MFMA peak",
-        "value": value, "unit": "comparisons/s", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": dtype, "data": "synthetic (seeded numpy PCG64)",
-        "config": config,
+        "value": cmp * K / wall, "unit": "comparisons/s", "ms_per_step": wall / K * 1e3,
+        "dtype": dtype, "config": config,
         "roofline": dict(roofline(bound, ops_per_cmp, cmp, kernel_ms, peak,
-                                  recorded_traffic(kernel, traffic_key(args))),
+                                  recorded_traffic(kernel, traffic_key(args, wl))),
                          kernel=kernel, kernel_ms=round(kernel_ms, 4)),
     }
-    if not args.no_cpu_baseline:
+    if with_cpu:
         line["cpu_baseline"] = cpu()
     line.update(extra)
+    if wl == "batched_64_uneven" and not args.per_problem:
+        plan.close()
+    return line
+
+
+def main(argv=None):
+    args = parse(argv)
+    if args.counter_summary:
+        sys.stdout.write(counter_summary(args.counter_summary[0], args.counter_summary[1],
+                                         args.pmc_command))
+        return 0
+    if args.pmc_summary:
+        fetch_dir, write_dir, kernel = args.pmc_summary
+        sys.stdout.write(pmc_summary(fetch_dir, write_dir, kernel,
+                                     traffic_key(args, args.workload), args.pmc_command))
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1705_08210_amd import ps
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    if args.workload not in WORKLOADS:
+        print(f"unknown workload {args.workload}", file=sys.stderr)
+        return 2
+    K, W = args.steps, args.warmup
+    head = measure(args, args.workload, K, W, with_cpu=not args.no_cpu_baseline)
+    line = {
+        "metric": "elementwise comparisons/sec, 2-way & 3-way PS, 1 MI355X; % of VALU/MFMA peak",
+        "value": head.pop("value"), "unit": head.pop("unit"), "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": head.pop("ms_per_step"), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": head.pop("dtype"),
+        "data": "synthetic (seeded numpy PCG64)", "config": head.pop("config"),
+    }
+    line.update(head)
+    if args.workload == "gwas_20000x16384" and not args.no_3way and args.storage == "auto" \
+            and args.campaign == 0:
+        # the metric's 3-way half: the 3-way FP32 workload, same steps
+        tw = measure(args, "sparse_4096x1024", K, W, with_cpu=not args.no_cpu_baseline)
+        tw["steps"], tw["warmup"] = K, W
+        line["three_way"] = tw
+    line["gpu_clock_ghz"] = round(ps.clock_probe(), 3)
     print(json.dumps(line), flush=True)
     return 0
+
+
+WORKLOADS = ("gwas_20000x16384", "uniform_1024x256", "levels_8192x32768", "binary_8192x32768",
+             "sparse_4096x1024", "levels_4096x1024", "batched_64_uneven")
 
 
 if __name__ == "__main__":

@@ -79,16 +79,18 @@ typedef enum {
                      the batched calls. */
 } ps_dtype;
 
-/* FP32 accumulation of the numerator sums (floating storage only). */
+/* FP32 accumulation of the numerator sums (floating storage only).  A NULL
+ * opts means PS_ACC_AUTO; a zero-filled ps_opts means PS_ACC_PLAIN. */
 typedef enum {
-    PS_ACC_AUTO = 0,     /* BLOCKED when n_f > 4096, else PLAIN */
-    PS_ACC_PLAIN = 1,    /* one running FP32 sum per output over all fields */
-    PS_ACC_BLOCKED = 2   /* ps2_compute / ps3_compute: the fields are split
-                            into chunks of 4096, each chunk is summed in FP32
-                            and the chunk sums are added in FP64 in a fixed
-                            order (deterministic; needs workspace for the
-                            chunk partials; batched calls split the same way
-                            per problem). */
+    PS_ACC_PLAIN = 0,    /* one running FP32 sum per output over all fields */
+    PS_ACC_BLOCKED = 1,  /* the fields are split into chunks of 4096, each
+                            chunk is summed in FP32 and the chunk sums are
+                            added in FP64 in a fixed order (deterministic;
+                            needs workspace for the chunk partials; batched
+                            calls split the same way per problem) */
+    PS_ACC_AUTO = 2      /* BLOCKED when n_f > 4096, else PLAIN; a 2-way
+                            triangle too small to fill the chip is also split
+                            over field chunks so that enough workgroups run */
 } ps_acc;
 
 /* Compute path for the pair numerators. */
@@ -96,8 +98,8 @@ typedef enum {
     PS_PATH_AUTO = 0,    /* U8 with 1 <= levels <= 15 and plane rows within the
                             MFMA limit below: MFMA; otherwise VALU */
     PS_PATH_VALU = 1,    /* register-blocked min/add on the vector ALUs */
-    PS_PATH_MFMA = 2,    /* U8 only: min(a,b) = sum_{t=1..levels} [a>=t][b>=t],
-                            an exact int8 matrix-core contraction with int32
+    PS_PATH_MFMA = 2,    /* alias PS_PATH_MFMA_THERMO.  U8 only:
+                            min(a,b) = sum_{t=1..levels} [a>=t][b>=t], an exact int8 matrix-core contraction with int32
                             accumulation; needs levels >= max(V).  Both MFMA
                             paths address 256 plane rows (levels x n_f rounded
                             up to 128 fields, one byte per field for int8, half
@@ -116,6 +118,7 @@ typedef enum {
                             1 are outside this path's domain (results
                             unspecified). */
 } ps_path;
+#define PS_PATH_MFMA_THERMO PS_PATH_MFMA
 
 typedef struct {
     int32_t acc;      /* ps_acc */
@@ -223,24 +226,23 @@ size_t ps2_batched_workspace_size(const ps_problem* probs, int32_t n,
  * of (problem, tile, field chunk) work items ordered longest first (the
  * load-balancing idea of Section 4.1 applied to the tiles of one GPU); the
  * hardware hands items to free slots in list order, a greedy longest-first
- * schedule.  A finish pass forms every problem's c2 (and n2).  Uploads the problem table and
- * tile list into the workspace from host memory on `stream` and, as the one
- * exception to the no-synchronisation rule, waits for `stream` once so that
- * the upload has completed before returning; then launches.  Use the plan
- * calls below to upload once and replay without any host wait.  All problems
- * share `dtype`.
+ * schedule.  A finish pass forms every problem's c2 (and n2).  The problem
+ * table and the list's groups travel to the workspace as kernel arguments
+ * and a kernel expands the list there, so the call returns without waiting
+ * for anything and the host arrays may be freed at once.  All problems share
+ * `dtype` (F32, F16 or U8; VALU path only, else PS_ERR_UNSUPPORTED).
  */
 ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype,
                               void* workspace, size_t ws_bytes,
                               const ps_opts* opts, hipStream_t stream);
 
-/* A captured batch: the upload is done once at creation and the launches
- * (sums, tile sums, finish) are captured in a HIP graph. */
+/* A captured batch: the whole launch sequence of ps2_compute_batched (table
+ * writes, work-list expansion, sums, tile sums, finish) in a HIP graph. */
 typedef struct ps_plan ps_plan;
 
-/* Builds the tile list, uploads it (synchronously, once) and captures the
- * launch sequence into a graph.  The workspace must stay valid and
- * untouched by others until ps_plan_destroy. */
+/* Captures the sequence into a graph (on a private stream; nothing is
+ * launched at creation, `stream` is not used).  The workspace must stay
+ * valid and untouched by others until ps_plan_destroy. */
 ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs,
                                  int32_t n, int32_t dtype, const ps_opts* opts,
                                  void* workspace, size_t ws_bytes,
@@ -296,6 +298,19 @@ size_t ps_threshold_workspace_size(int64_t n);
 ps_status ps_threshold(const float* c, int64_t n, float threshold, int64_t base,
                        int64_t* idx, float* val, int64_t cap, int64_t* count,
                        void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Measurement aid (not part of the metric): the shader clock under a full
+ * vector-ALU load.  Launches 2048 workgroups of 256 lanes, each running
+ * `iters` rounds of FP32 min + add on 8 independent chains; the first lane of
+ * each workgroup writes three uint64 values to the workspace: shader-clock
+ * cycles elapsed, 100 MHz real-time ticks elapsed, and a zero.  The mean
+ * clock in GHz is sum(cycles) / sum(ticks) / 10.  workspace: device, at
+ * least ps_clock_probe_workspace_size() bytes, 8-byte aligned.
+ */
+size_t ps_clock_probe_workspace_size(void);
+ps_status ps_clock_probe(int64_t iters, void* workspace, size_t ws_bytes,
+                         hipStream_t stream);
 
 #ifdef __cplusplus
 }

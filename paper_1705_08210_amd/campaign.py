@@ -22,12 +22,31 @@ the calls on two streams.
 
 from __future__ import annotations
 
+import atexit
 import dataclasses
 import math
 
 import torch
 
 from . import ps
+
+
+def release() -> None:
+    """Free the pinned host blocks that campaigns leave in torch's host-memory
+    cache (their staging buffers), with the HIP runtime fully up.  Registered
+    to run at interpreter exit, so no page-locked block is left for the
+    runtime's own teardown (exit-time destructors run after tools that
+    intercept HIP calls, such as a profiler, may have shut down); call it
+    earlier to return the memory sooner."""
+    if not torch.cuda.is_initialized():
+        return
+    torch.cuda.synchronize()
+    empty = getattr(torch._C, "_host_emptyCache", None)
+    if empty is not None:
+        empty()
+
+
+atexit.register(release)
 
 
 def stage_bounds(n_v: int, n_stages: int) -> list[tuple[int, int]]:
@@ -170,7 +189,17 @@ def run3(V: torch.Tensor, n_stages: int, sink, reduce: str = "u8", threshold: fl
             launch(k + ahead)   # its set was used by stage k - 1, delivered already
         deliver(k)
     copy.synchronize()          # every stage's copy, hence every stage, has finished
+    for cs in computes:
+        cs.synchronize()
     main.wait_stream(copy)
+    # nothing of this call outlives it: events, device and pinned buffers go
+    # back to torch's caches now (release() frees the pinned ones)
+    copied.clear()
+    del c3
+    if reduce == "threshold":
+        del hidx, hval, hcnt, dsel
+    else:
+        del dout, hout
     return len(stages)
 
 

@@ -26,7 +26,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libps.so")
 
 SOURCES = ["ps_api.hip", "policy.hip", "mg_common.hip", "mg_f32.hip", "mg_f16.hip", "mg_u8.hip",
-           "mg_b1.hip", "mg_f64.hip", "mfma.hip", "reduce.hip"]
+           "mg_b1.hip", "mg_f64.hip", "mfma.hip", "reduce.hip", "probe.hip"]
 HEADERS = ["ps_internal.h", "mgemm_core.h", "mgemm_kernels.h"]
 
 ARCH = os.environ.get("PS_OFFLOAD_ARCH", "gfx950")

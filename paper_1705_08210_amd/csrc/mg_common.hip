@@ -1,5 +1,7 @@
 // mg_common.hip -- per-vector sums, the 3-way tile prefix, and small fill
 // kernels shared by the entry points.
+#include <string.h>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -105,13 +107,11 @@ __global__ __launch_bounds__(256) void ps_sums_kernel(const void* V, int64_t n_f
 }
 
 // Sums for the problems of a batch that did not bring their own: blockIdx.y
-// is the problem, need_s[p] != 0 marks the ones to compute into p.s.
+// is the problem, need_s != 0 marks the ones to compute into p.s.
 template <int DT>
-__global__ __launch_bounds__(256) void ps_batched_sums_kernel(const DevProblem* probs,
-                                                              const int32_t* need_s) {
-    const int p = blockIdx.y;
-    if (!need_s[p]) return;
-    const DevProblem pr = probs[p];
+__global__ __launch_bounds__(256) void ps_batched_sums_kernel(const DevProblem* probs) {
+    const DevProblem pr = probs[blockIdx.y];
+    if (!pr.need_s) return;
     constexpr int ESZ = Ops<DT>::kEsz;
     const bool vec = ((uintptr_t)pr.V % 16 == 0) && ((pr.ld * ESZ) % 16 == 0);
     for (int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64; i < pr.n_v;
@@ -159,16 +159,78 @@ hipError_t launch_sums(const void* V, int32_t dt, int64_t n_f, int64_t n_v, int6
     return hipGetLastError();
 }
 
-hipError_t launch_batched_sums(const DevProblem* probs, const int32_t* need_s, int32_t n,
-                               int32_t dt, int64_t max_nv, hipStream_t st) {
+hipError_t launch_batched_sums(const DevProblem* probs, int32_t n, int32_t dt, int64_t max_nv,
+                               hipStream_t st) {
     if (n <= 0 || max_nv <= 0) return hipSuccess;
     const dim3 grid((unsigned)std::min<int64_t>((max_nv + 3) / 4, 1 << 16), (unsigned)n);
     switch (dt) {
-    case PS_F32: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F32>, grid, dim3(256), 0, st, probs, need_s); break;
-    case PS_F16: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F16>, grid, dim3(256), 0, st, probs, need_s); break;
-    case PS_U8:  hipLaunchKernelGGL(ps_batched_sums_kernel<PS_U8>, grid, dim3(256), 0, st, probs, need_s); break;
+    case PS_F32: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F32>, grid, dim3(256), 0, st, probs); break;
+    case PS_F16: hipLaunchKernelGGL(ps_batched_sums_kernel<PS_F16>, grid, dim3(256), 0, st, probs); break;
+    case PS_U8:  hipLaunchKernelGGL(ps_batched_sums_kernel<PS_U8>, grid, dim3(256), 0, st, probs); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Host tables to the device without a host wait: the bytes travel as kernel
+// arguments (copied by the runtime at launch, or into the graph node at
+// capture), and one workgroup writes them out.  kPutWords * 4 bytes per
+// launch keeps the argument block well inside the kernel-argument limit.
+// ---------------------------------------------------------------------------
+constexpr int kPutWords = 448;
+struct PutArgs {
+    uint32_t* dst;
+    int32_t nwords;
+    int32_t pad;
+    uint32_t w[kPutWords];
+};
+
+__global__ __launch_bounds__(256) void ps_put_kernel(PutArgs a) {
+    for (int t = threadIdx.x; t < a.nwords; t += 256) a.dst[t] = a.w[t];
+}
+
+hipError_t launch_put(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes % 4) return hipErrorInvalidValue;
+    const uint32_t* w = (const uint32_t*)src;
+    const size_t nw = bytes / 4;
+    for (size_t w0 = 0; w0 < nw; w0 += kPutWords) {
+        PutArgs a;
+        a.dst = (uint32_t*)dst + w0;
+        a.nwords = (int32_t)std::min<size_t>(kPutWords, nw - w0);
+        a.pad = 0;
+        memcpy(a.w, w + w0, (size_t)a.nwords * 4);
+        hipLaunchKernelGGL(ps_put_kernel, dim3(1), dim3(256), 0, st, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Work list of a batch: position t lies in the last group whose start is
+// <= t; inside the group, the tiles of the problem's upper triangle in
+// column-major order, (0,0), (0,1), (1,1), (0,2), ...
+__global__ __launch_bounds__(256) void ps_batch_expand_kernel(const BatchGroup* g, int32_t ng,
+                                                              BatchTile* tiles, int64_t ntiles) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = ng;
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) / 2;
+            if (g[mid].start <= t) lo = mid; else hi = mid;
+        }
+        int64_t bi, bj;
+        tri_decode(t - g[lo].start, bi, bj);
+        tiles[t] = BatchTile{g[lo].prob, (int32_t)bi, (int32_t)bj, g[lo].chunk};
+    }
+}
+
+hipError_t launch_batch_expand(const BatchGroup* groups, int32_t ngroups, BatchTile* tiles,
+                               int64_t ntiles, hipStream_t st) {
+    if (ntiles <= 0 || ngroups <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((ntiles + 255) / 256, 4096);
+    hipLaunchKernelGGL(ps_batch_expand_kernel, dim3((unsigned)blocks), dim3(256), 0, st, groups,
+                       ngroups, tiles, ntiles);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ int64_t slab_tiles(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob
 // ---------------------------------------------------------------------------
 static ps_status check_opts(const ps_opts* o) {
     if (!o) return PS_OK;
-    if (o->acc < PS_ACC_AUTO || o->acc > PS_ACC_BLOCKED)
+    if (o->acc < PS_ACC_PLAIN || o->acc > PS_ACC_AUTO)
         return fail(PS_ERR_ARG, "opts.acc = %d is not a ps_acc value", o->acc);
     if (o->path < PS_PATH_AUTO || o->path > PS_PATH_BITS)
         return fail(PS_ERR_ARG, "opts.path = %d is not a ps_path value", o->path);
@@ -128,6 +128,24 @@ static ps_status check_mfma(int path, int32_t dtype, int levels, int64_t n_f) {
                     "32-bit tile offsets (256 rows must span < 2^31 bytes); use the VALU path",
                     (long long)mfma_row_bytes(n_f, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0),
                     (long long)levels * n_f);
+    return PS_OK;
+}
+
+// The uint8 VALU kernels sum |a - b| four bytes at a time into uint32 and
+// store pair numerators as int32; both hold only while 255 n_f < 2^31.  The
+// BITS path stores population counts (at most n_f) as int32.
+static ps_status check_int_range(int path, int32_t dtype, int64_t n_f) {
+    if (dtype != PS_U8 || is_mfma(path)) return PS_OK;
+    if (path == PS_PATH_BITS) {
+        if (n_f >= ((int64_t)1 << 31))
+            return fail(PS_ERR_UNSUPPORTED, "BITS path: n_f = %lld exceeds the int32 counts",
+                        (long long)n_f);
+        return PS_OK;
+    }
+    if (255 * n_f >= ((int64_t)1 << 31))
+        return fail(PS_ERR_UNSUPPORTED,
+                    "uint8 VALU path: 255 * n_f = %lld exceeds the 32-bit integer sums "
+                    "(n_f must be below 8421505)", (long long)(255 * n_f));
     return PS_OK;
 }
 
@@ -224,6 +242,7 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     const int path = choose_path(dtype, opts, n_f);
     const int levels = opts ? opts->levels : 0;
     if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
+    if ((st = check_int_range(path, dtype, n_f)) != PS_OK) return st;
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
     float* partial = nullptr;
@@ -417,6 +436,7 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     const int path = choose_path(dtype, opts, n_f);
     const int levels = opts ? opts->levels : 0;
     if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
+    if ((st = check_int_range(path, dtype, n_f)) != PS_OK) return st;
     if (n_v < 3) return PS_OK;
     if (j_begin < 1 || j_end > n_v - 1 || j_begin > j_end)
         return fail(PS_ERR_ARG, "need 1 <= j_begin <= j_end <= n_v-1, got [%lld, %lld)",
@@ -492,7 +512,7 @@ namespace ps {
 // ---------------------------------------------------------------------------
 struct BatchLayout {
     DevProblem* probs = nullptr;
-    int32_t* need_s = nullptr;
+    BatchGroup* groups = nullptr;
     BatchTile* tiles = nullptr;
     double* s = nullptr;
     float* partial = nullptr;    // all split problems' chunk partials, back to back
@@ -531,17 +551,34 @@ static int64_t batch_partial_len(const ps_problem* p, int32_t n, int32_t dt, con
     return t;
 }
 
+// Field-chunk groups of a batch: one per (problem with pairs, chunk).
+static int64_t batch_groups(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o) {
+    int64_t t = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (p[i].n_v >= 2) t += batch_chunks(p[i], dt, o);
+    return t;
+}
+
 static BatchLayout batch_layout(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o,
                                 int bm, void* ws) {
     Carver c(ws);
     BatchLayout L;
     L.probs = (DevProblem*)c.take(sizeof(DevProblem) * (size_t)(n > 0 ? n : 1));
-    L.need_s = (int32_t*)c.take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    L.groups = (BatchGroup*)c.take(sizeof(BatchGroup) * (size_t)batch_groups(p, n, dt, o));
     L.tiles = (BatchTile*)c.take(sizeof(BatchTile) * (size_t)batch_items(p, n, dt, o, bm));
     L.s = (double*)c.take(sizeof(double) * (size_t)batch_sums_len(p, n));
     L.partial = (float*)c.take(sizeof(float) * (size_t)batch_partial_len(p, n, dt, o));
     L.bytes = c.used;
     return L;
+}
+
+// Prefix the recorded message with the number of the problem it concerns
+// (copied first: the message buffer is also the destination).
+static ps_status prefix_error(ps_status st, int32_t i) {
+    char msg[sizeof g_err];
+    memcpy(msg, g_err, sizeof msg);
+    msg[sizeof msg - 1] = 0;
+    return fail(st, "problem %d: %s", i, msg);
 }
 
 static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, const ps_opts* o) {
@@ -555,75 +592,88 @@ static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, con
     for (int32_t i = 0; i < n; ++i) {
         const ps_problem& p = probs[i];
         st = check_matrix(p.V, dt, p.n_f, p.n_v, p.ld);
-        if (st != PS_OK) return fail(st, "problem %d: %s", i, ps_last_error());
+        if (st != PS_OK) return prefix_error(st, i);
         if (p.n_v >= 2 && !p.c2 && !p.n2)
             return fail(PS_ERR_ARG, "problem %d: both c2 and n2 are NULL", i);
         if (!aligned(p.c2, 4) || !aligned(p.n2, 4) || !aligned(p.s, 8))
             return fail(PS_ERR_ARG, "problem %d: misaligned pointer", i);
         if (p.n_v > ((int64_t)1 << 31) / 2) return fail(PS_ERR_ARG, "problem %d too large", i);
+        st = check_int_range(PS_PATH_VALU, dt, p.n_f);
+        if (st != PS_OK) return prefix_error(st, i);
     }
     return PS_OK;
 }
 
 // Host-side tables of a batch: device problem records (with workspace sums
-// and chunk partials where needed) and the work list, longest items first.
-static void batch_tables(const ps_problem* probs, int32_t n, int32_t dt, const ps_opts* o,
-                         int bm, const BatchLayout& L, std::vector<DevProblem>& dp,
-                         std::vector<int32_t>& need, std::vector<BatchTile>& tiles,
-                         int64_t& max_nv, int64_t& max_pairs) {
-    dp.resize(n);
-    need.resize(n);
+// and chunk partials where needed) and the groups of the work list, longest
+// first.  An item's cost is the number of fields its chunk covers; the groups
+// are stably sorted by it, so equal costs keep problem and chunk order, and
+// each group lists its problem's tiles in column-major order.
+struct BatchTables {
+    std::vector<DevProblem> dp;
+    std::vector<BatchGroup> groups;
+    int64_t ntiles = 0, max_nv = 0, max_pairs = 0;
+};
+
+static BatchTables batch_tables(const ps_problem* probs, int32_t n, int32_t dt, const ps_opts* o,
+                                int bm, const BatchLayout& L) {
+    BatchTables T;
+    T.dp.resize(n);
     int64_t soff = 0, poff = 0;
-    max_nv = 0;
-    max_pairs = 0;
     for (int32_t i = 0; i < n; ++i) {
         const ps_problem& p = probs[i];
         const int32_t nch = p.n_v >= 2 ? batch_chunks(p, dt, o) : 1;
-        dp[i] = DevProblem{p.V, p.n_f, p.n_v, p.ld, p.s, p.c2, p.n2, nullptr, nch, 0};
-        need[i] = p.s ? 0 : 1;
+        T.dp[i] = DevProblem{p.V, p.n_f, p.n_v, p.ld, p.s, p.c2, p.n2, nullptr, nch, p.s ? 0 : 1};
         if (!p.s) {
-            dp[i].s = L.s + soff;
+            T.dp[i].s = L.s + soff;
             soff += p.n_v;
         }
         if (p.n_v >= 2) {
-            dp[i].partial = L.partial + poff;
+            T.dp[i].partial = L.partial + poff;
             poff += (int64_t)nch * pairs_of(p.n_v);
-            max_pairs = std::max(max_pairs, pairs_of(p.n_v));
+            T.max_pairs = std::max(T.max_pairs, pairs_of(p.n_v));
         }
-        max_nv = std::max(max_nv, p.n_v);
+        T.max_nv = std::max(T.max_nv, p.n_v);
     }
-    // an item's cost is the number of fields its chunk covers
-    struct Item { int64_t cost; BatchTile t; };
-    std::vector<Item> items;
+    struct G { int64_t cost, tiles; BatchGroup g; };
+    std::vector<G> gs;
     for (int32_t pi = 0; pi < n; ++pi) {
         if (probs[pi].n_v < 2) continue;
-        const int64_t nb = ceil_div(probs[pi].n_v, bm);
-        const int32_t nch = dp[pi].nchunks;
+        const int32_t nch = T.dp[pi].nchunks;
         for (int32_t c = 0; c < nch; ++c) {
             const int64_t f0 = nch > 1 ? c * kChunkFields : 0;
             const int64_t f1 = nch > 1 ? std::min(probs[pi].n_f, f0 + kChunkFields) : probs[pi].n_f;
-            for (int64_t bj = 0; bj < nb; ++bj)
-                for (int64_t bi = 0; bi <= bj; ++bi)
-                    items.push_back(Item{f1 - f0, BatchTile{pi, (int32_t)bi, (int32_t)bj, c}});
+            gs.push_back(G{f1 - f0, tri_tiles(probs[pi].n_v, bm), BatchGroup{pi, c, 0}});
         }
     }
-    std::stable_sort(items.begin(), items.end(),
-                     [](const Item& a, const Item& b) { return a.cost > b.cost; });
-    tiles.resize(items.size());
-    for (size_t k = 0; k < items.size(); ++k) tiles[k] = items[k].t;
+    std::stable_sort(gs.begin(), gs.end(), [](const G& a, const G& b) { return a.cost > b.cost; });
+    T.groups.resize(gs.size());
+    for (size_t k = 0; k < gs.size(); ++k) {
+        T.groups[k] = gs[k].g;
+        T.groups[k].start = T.ntiles;
+        T.ntiles += gs[k].tiles;
+    }
+    return T;
 }
 
-static ps_status batch_enqueue(const BatchLayout& L, int32_t n, int32_t dt, int64_t ntiles,
-                               int64_t max_nv, int64_t max_pairs, int cfg, hipStream_t st) {
-    hipError_t e = launch_batched_sums(L.probs, L.need_s, n, dt, max_nv, st);
+// The whole batched sequence on one stream: table upload (through kernel
+// arguments), work-list expansion, sums, tile sums, finish.  Nothing waits on
+// the host, so the same sequence serves eager calls and graph capture.
+static ps_status batch_enqueue(const BatchLayout& L, const BatchTables& T, int32_t n, int32_t dt,
+                               int cfg, hipStream_t st) {
+    hipError_t e = launch_put(L.probs, T.dp.data(), sizeof(DevProblem) * (size_t)n, st);
+    if (e == hipSuccess && !T.groups.empty())
+        e = launch_put(L.groups, T.groups.data(), sizeof(BatchGroup) * T.groups.size(), st);
+    if (e == hipSuccess)
+        e = launch_batch_expand(L.groups, (int32_t)T.groups.size(), L.tiles, T.ntiles, st);
+    if (e == hipSuccess) e = launch_batched_sums(L.probs, n, dt, T.max_nv, st);
     if (e == hipSuccess) {
-        MgBatchLaunch a{L.probs, L.tiles, ntiles, cfg, chunk_tiles(dt, cfg)};
+        MgBatchLaunch a{L.probs, L.tiles, T.ntiles, cfg, chunk_tiles(dt, cfg)};
         e = launch_mgb(dt, a, st);
     }
-    if (e == hipSuccess) e = launch_finish2_batched(dt, L.probs, n, max_pairs, st);
+    if (e == hipSuccess) e = launch_finish2_batched(dt, L.probs, n, T.max_pairs, st);
     return e == hipSuccess ? PS_OK : hip_fail(e, "batched launch");
 }
-
 
 }  // namespace ps
 
@@ -648,34 +698,52 @@ ps_status ps2_compute_batched(const ps_problem* probs, int32_t n, int32_t dtype,
     if (ws_bytes < L.bytes || !ws)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.bytes);
     if (!aligned(ws, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
-    std::vector<DevProblem> dp;
-    std::vector<int32_t> need;
-    std::vector<BatchTile> tiles;
-    int64_t max_nv, max_pairs;
-    batch_tables(probs, n, dtype, opts, bm, L, dp, need, tiles, max_nv, max_pairs);
-    hipError_t e = hipMemcpyAsync(L.probs, dp.data(), sizeof(DevProblem) * n,
-                                  hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(L.need_s, need.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
-                           stream);
-    if (e == hipSuccess && !tiles.empty())
-        e = hipMemcpyAsync(L.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
-                           hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "batched table upload");
-    // the host tables die at return: wait until the copies have consumed them
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "batched table upload");
-    return batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv, max_pairs, cfg, stream);
+    const BatchTables T = batch_tables(probs, n, dtype, opts, bm, L);
+    return batch_enqueue(L, T, n, dtype, cfg, stream);
 }
+
+}  // extern "C"
 
 struct ps_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
+// Captures enqueue(cs) on a private stream into a graph and instantiates it.
+template <class Enqueue>
+static ps_status capture_plan(ps_plan** plan, Enqueue enqueue) {
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "plan capture stream");
+    ps_plan* p = new ps_plan();
+    ps_status st;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue(cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+        if (st == PS_OK && e2 != hipSuccess) st = hip_fail(e2, "plan capture");
+    } else {
+        st = hip_fail(e, "plan capture begin");
+    }
+    if (st == PS_OK) {
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = hip_fail(e, "plan instantiate");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != PS_OK) {
+        ps_plan_destroy(p);
+        return st;
+    }
+    *plan = p;
+    return PS_OK;
+}
+
+extern "C" {
+
 ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs, int32_t n,
                                  int32_t dtype, const ps_opts* opts, void* ws, size_t ws_bytes,
                                  hipStream_t stream) {
+    (void)stream;   // creation launches nothing: the tables travel inside the graph
     if (!plan) return fail(PS_ERR_ARG, "plan is NULL");
     *plan = nullptr;
     ps_status st = check_batch(probs, n, dtype, opts);
@@ -686,47 +754,10 @@ ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs, int32_
     if (ws_bytes < L.bytes || !ws)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.bytes);
     if (!aligned(ws, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
-    std::vector<DevProblem> dp;
-    std::vector<int32_t> need;
-    std::vector<BatchTile> tiles;
-    int64_t max_nv = 0, max_pairs = 0;
-    batch_tables(probs, n, dtype, opts, bm, L, dp, need, tiles, max_nv, max_pairs);
-    hipError_t e = hipSuccess;
-    if (n > 0) {
-        e = hipStreamSynchronize(stream);
-        if (e == hipSuccess)
-            e = hipMemcpy(L.probs, dp.data(), sizeof(DevProblem) * n, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(L.need_s, need.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
-        if (e == hipSuccess && !tiles.empty())
-            e = hipMemcpy(L.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
-                          hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "plan table upload");
-    }
-    hipStream_t cs = nullptr;
-    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_fail(e, "plan capture stream");
-    ps_plan* p = new ps_plan();
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        st = n > 0 ? batch_enqueue(L, n, dtype, (int64_t)tiles.size(), max_nv, max_pairs, cfg, cs)
-                   : PS_OK;
-        hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
-        if (st == PS_OK && e2 != hipSuccess) st = hip_fail(e2, "plan capture");
-    } else {
-        st = hip_fail(e, "plan capture begin");
-    }
-    if (st == PS_OK) {
-        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) st = hip_fail(e, "plan instantiate");
-    }
-    hipStreamDestroy(cs);
-    if (st != PS_OK) {
-        ps_plan_destroy(p);
-        return st;
-    }
-    *plan = p;
-    return PS_OK;
+    const BatchTables T = batch_tables(probs, n, dtype, opts, bm, L);
+    return capture_plan(plan, [&](hipStream_t cs) {
+        return n > 0 ? batch_enqueue(L, T, n, dtype, cfg, cs) : PS_OK;
+    });
 }
 
 ps_status ps_plan_execute(ps_plan* plan, hipStream_t stream) {
@@ -737,8 +768,8 @@ ps_status ps_plan_execute(ps_plan* plan, hipStream_t stream) {
 
 void ps_plan_destroy(ps_plan* plan) {
     if (!plan) return;
-    if (plan->exec) hipGraphExecDestroy(plan->exec);
-    if (plan->graph) hipGraphDestroy(plan->graph);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
     delete plan;
 }
 

@@ -252,12 +252,20 @@ struct DevProblem {
     float* c2;
     void* n2;
     float* partial;              // raw tile sums: nchunks * pairs 32-bit values
-    int32_t nchunks, pad;        // field chunks (1: no split)
+    int32_t nchunks;             // field chunks (1: no split)
+    int32_t need_s;              // 1: the sums are computed into s (the caller gave none)
 };
 
 // One work item of a batched launch: a tile of a problem and a field chunk.
 struct BatchTile {
     int32_t prob, bi, bj, chunk;
+};
+
+// A run of the batched work list: every upper-triangle tile (column-major)
+// of one field chunk of one problem, starting at list position `start`.
+struct BatchGroup {
+    int32_t prob, chunk;
+    int64_t start;
 };
 
 struct MgBatchLaunch {
@@ -303,8 +311,14 @@ hipError_t launch_mgb_f32(const MgBatchLaunch& a, hipStream_t st);
 hipError_t launch_mgb_f16(const MgBatchLaunch& a, hipStream_t st);
 hipError_t launch_mgb_u8(const MgBatchLaunch& a, hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
-hipError_t launch_batched_sums(const DevProblem* probs, const int32_t* need_s, int32_t n,
-                               int32_t dt, int64_t max_nv, hipStream_t st);
+hipError_t launch_batched_sums(const DevProblem* probs, int32_t n, int32_t dt, int64_t max_nv,
+                               hipStream_t st);
+// Host bytes -> device memory through kernel arguments (no host wait, no
+// staging buffer; capturable): `bytes` (a multiple of 4) from src to dst.
+hipError_t launch_put(void* dst, const void* src, size_t bytes, hipStream_t st);
+// The batched work list from its groups: tiles[t] for t < ntiles.
+hipError_t launch_batch_expand(const BatchGroup* groups, int32_t ngroups, BatchTile* tiles,
+                               int64_t ntiles, hipStream_t st);
 
 // Thermometer int8 MFMA path (PS_U8).
 struct MfmaLaunch {

@@ -9,6 +9,7 @@ fails.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import re
@@ -31,7 +32,7 @@ I64 = ctypes.c_int64
 SZ = ctypes.c_size_t
 
 PS_F32, PS_F16, PS_U8, PS_F64 = 0, 1, 2, 3
-ACC = {"auto": 0, "plain": 1, "blocked": 2}
+ACC = {"plain": 0, "blocked": 1, "auto": 2}
 PATH = {"auto": 0, "valu": 1, "mfma": 2, "mfma_fp4": 3, "bits": 4}
 DTYPES = {torch.float32: PS_F32, torch.float16: PS_F16, torch.uint8: PS_U8,
           torch.float64: PS_F64}
@@ -79,6 +80,8 @@ _sig("ps_tune_clear", None, [])
 _sig("ps_quantize_u8", ctypes.c_int, [P, I64, P, P])
 _sig("ps_threshold_workspace_size", SZ, [I64])
 _sig("ps_threshold", ctypes.c_int, [P, I64, ctypes.c_float, I64, P, P, I64, P, P, SZ, P])
+_sig("ps_clock_probe_workspace_size", SZ, [])
+_sig("ps_clock_probe", ctypes.c_int, [I64, P, SZ, P])
 
 
 def header_functions() -> list[str]:
@@ -103,6 +106,14 @@ def _check(st: int) -> None:
 def _stream(stream) -> int:
     s = torch.cuda.current_stream() if stream is None else stream
     return s.cuda_stream
+
+
+def _on(stream):
+    """Allocation context of a call: with an explicit stream, the binding's
+    allocations (workspace, outputs) are made on that stream, so the caching
+    allocator never hands their blocks to other work while the library's
+    kernels on `stream` may still use them."""
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
 
 
 def _opts(acc="auto", path="auto", levels=0, tile=0) -> Opts:
@@ -145,10 +156,11 @@ def vector_sums(V: torch.Tensor, out: torch.Tensor | None = None, want_bad: bool
     """s_i = sum_q V[i, q] (FP64) and, if want_bad, the count of negative,
     NaN or infinite entries (as a 1-element int32 tensor)."""
     dt, n_f, n_v, ld = _matrix(V)
-    s = out if out is not None else torch.empty(n_v, dtype=torch.float64, device=V.device)
-    bad = torch.empty(1, dtype=torch.int32, device=V.device) if want_bad else None
-    _check(lib.ps_vector_sums(V.data_ptr(), dt, n_f, n_v, ld, s.data_ptr(), _ptr(bad),
-                              _stream(stream)))
+    with _on(stream):
+        s = out if out is not None else torch.empty(n_v, dtype=torch.float64, device=V.device)
+        bad = torch.empty(1, dtype=torch.int32, device=V.device) if want_bad else None
+        _check(lib.ps_vector_sums(V.data_ptr(), dt, n_f, n_v, ld, s.data_ptr(), _ptr(bad),
+                                  _stream(stream)))
     return s, bad
 
 
@@ -159,15 +171,16 @@ def ps2(V: torch.Tensor, s: torch.Tensor | None = None, want_c2: bool = True,
     may be None when not requested."""
     dt, n_f, n_v, ld = _matrix(V)
     m = n_v * (n_v - 1) // 2
-    if want_c2 and c2 is None:
-        c2 = torch.empty(m, dtype=torch.float32, device=V.device)
-    if want_n2 and n2 is None:
-        n2 = torch.empty(m, dtype=n2_dtype(V.dtype), device=V.device)
-    o = _opts(acc, path, levels, tile)
-    ws_n = lib.ps2_workspace_size(dt, n_f, n_v, int(s is not None), ctypes.byref(o))
-    ws = _workspace(ws_n, V.device)
-    _check(lib.ps2_compute(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(c2), _ptr(n2),
-                           ws.data_ptr(), ws.numel(), ctypes.byref(o), _stream(stream)))
+    with _on(stream):
+        if want_c2 and c2 is None:
+            c2 = torch.empty(m, dtype=torch.float32, device=V.device)
+        if want_n2 and n2 is None:
+            n2 = torch.empty(m, dtype=n2_dtype(V.dtype), device=V.device)
+        o = _opts(acc, path, levels, tile)
+        ws_n = lib.ps2_workspace_size(dt, n_f, n_v, int(s is not None), ctypes.byref(o))
+        ws = _workspace(ws_n, V.device)
+        _check(lib.ps2_compute(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(c2), _ptr(n2),
+                               ws.data_ptr(), ws.numel(), ctypes.byref(o), _stream(stream)))
     return c2, n2
 
 
@@ -186,15 +199,16 @@ def ps3(V: torch.Tensor, s: torch.Tensor | None = None, n2: torch.Tensor | None 
     if j_end is None:
         j_end = max(n_v - 1, j_begin)
     m = stage_size(n_v, j_begin, j_end)
-    if c3 is None:
-        c3 = torch.empty(m, dtype=torch.float32, device=V.device)
-    o = _opts(acc, path, levels, tile)
-    ws_n = lib.ps3_workspace_size(dt, n_f, n_v, int(s is not None), int(n2 is not None),
-                                  j_begin, j_end, ctypes.byref(o))
-    ws = _workspace(ws_n, V.device)
-    _check(lib.ps3_compute(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(n2), j_begin, j_end,
-                           c3.data_ptr() if m > 0 else None, ws.data_ptr(), ws.numel(),
-                           ctypes.byref(o), _stream(stream)))
+    with _on(stream):
+        if c3 is None:
+            c3 = torch.empty(m, dtype=torch.float32, device=V.device)
+        o = _opts(acc, path, levels, tile)
+        ws_n = lib.ps3_workspace_size(dt, n_f, n_v, int(s is not None), int(n2 is not None),
+                                      j_begin, j_end, ctypes.byref(o))
+        ws = _workspace(ws_n, V.device)
+        _check(lib.ps3_compute(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(n2), j_begin,
+                               j_end, c3.data_ptr() if m > 0 else None, ws.data_ptr(),
+                               ws.numel(), ctypes.byref(o), _stream(stream)))
     return c3
 
 
@@ -224,30 +238,34 @@ def _batch_outputs(Vs, want_n2=False):
 def ps2_batched(Vs, outs=None, acc="auto", tile=0, want_n2=False, stream=None):
     """Many independent 2-way problems in one launch.  Returns the
     list of (c2, n2, s) tuples (s is None: sums computed inside)."""
-    if outs is None:
-        outs = _batch_outputs(Vs, want_n2)
-    arr, dt = _problems(Vs, outs)
-    o = _opts(acc, "valu", 0, tile)
-    ws_n = lib.ps2_batched_workspace_size(arr, len(Vs), dt, ctypes.byref(o))
-    dev = Vs[0].device if Vs else torch.device("cuda")
-    ws = _workspace(ws_n, dev)
-    _check(lib.ps2_compute_batched(arr, len(Vs), dt, ws.data_ptr(), ws.numel(),
-                                   ctypes.byref(o), _stream(stream)))
+    with _on(stream):
+        if outs is None:
+            outs = _batch_outputs(Vs, want_n2)
+        arr, dt = _problems(Vs, outs)
+        o = _opts(acc, "valu", 0, tile)
+        ws_n = lib.ps2_batched_workspace_size(arr, len(Vs), dt, ctypes.byref(o))
+        dev = Vs[0].device if Vs else torch.device("cuda")
+        ws = _workspace(ws_n, dev)
+        _check(lib.ps2_compute_batched(arr, len(Vs), dt, ws.data_ptr(), ws.numel(),
+                                       ctypes.byref(o), _stream(stream)))
     return outs
 
 
 class BatchedPlan:
-    """A batch uploaded once and captured into a HIP graph; run() replays it."""
+    """A batch captured into a HIP graph (table writes included); run()
+    replays it."""
 
     def __init__(self, Vs, outs=None, acc="auto", tile=0, want_n2=False, stream=None):
         self.Vs = list(Vs)
-        self.outs = outs if outs is not None else _batch_outputs(self.Vs, want_n2)
-        arr, dt = _problems(self.Vs, self.outs)
-        self._arr = arr
-        o = _opts(acc, "valu", 0, tile)
-        ws_n = lib.ps2_batched_workspace_size(arr, len(self.Vs), dt, ctypes.byref(o))
-        dev = self.Vs[0].device if self.Vs else torch.device("cuda")
-        self.ws = _workspace(ws_n, dev)
+        with _on(stream):
+            self.outs = outs if outs is not None else _batch_outputs(self.Vs, want_n2)
+            arr, dt = _problems(self.Vs, self.outs)
+            self._arr = arr
+            o = _opts(acc, "valu", 0, tile)
+            ws_n = lib.ps2_batched_workspace_size(arr, len(self.Vs), dt, ctypes.byref(o))
+            dev = self.Vs[0].device if self.Vs else torch.device("cuda")
+            self.ws = _workspace(ws_n, dev)
+            self._home = torch.cuda.current_stream(dev)
         h = P()
         _check(lib.ps_plan_create_batched(ctypes.byref(h), arr, len(self.Vs), dt,
                                           ctypes.byref(o), self.ws.data_ptr(),
@@ -255,7 +273,10 @@ class BatchedPlan:
         self._h = h
 
     def run(self, stream=None):
-        _check(lib.ps_plan_execute(self._h, _stream(stream)))
+        s = torch.cuda.current_stream() if stream is None else stream
+        if s != self._home:   # keep the workspace from reuse while this replay runs
+            self.ws.record_stream(s)
+        _check(lib.ps_plan_execute(self._h, s.cuda_stream))
         return self.outs
 
     def close(self):
@@ -297,10 +318,11 @@ def quantize_u8(c: torch.Tensor, out: torch.Tensor | None = None, stream=None) -
     if c.dtype != torch.float32 or not c.is_cuda or not c.is_contiguous():
         raise ValueError("c must be a contiguous float32 GPU tensor")
     n = c.numel()
-    if out is None:
-        out = torch.empty(n, dtype=torch.uint8, device=c.device)
-    _check(lib.ps_quantize_u8(c.data_ptr() if n else None, n, out.data_ptr() if n else None,
-                              _stream(stream)))
+    with _on(stream):
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=c.device)
+        _check(lib.ps_quantize_u8(c.data_ptr() if n else None, n,
+                                  out.data_ptr() if n else None, _stream(stream)))
     return out
 
 
@@ -312,14 +334,26 @@ def threshold(c: torch.Tensor, thr: float, base: int = 0, cap: int | None = None
         raise ValueError("c must be a contiguous float32 GPU tensor")
     n = c.numel()
     cap = n if cap is None else int(cap)
-    idx = torch.empty(max(cap, 1), dtype=torch.int64, device=c.device)
-    val = torch.empty(max(cap, 1), dtype=torch.float32, device=c.device)
-    count = torch.empty(1, dtype=torch.int64, device=c.device)
-    ws = _workspace(lib.ps_threshold_workspace_size(n), c.device)
-    _check(lib.ps_threshold(c.data_ptr() if n else None, n, float(thr), int(base),
-                            idx.data_ptr(), val.data_ptr(), cap, count.data_ptr(),
-                            ws.data_ptr(), ws.numel(), _stream(stream)))
+    with _on(stream):
+        idx = torch.empty(max(cap, 1), dtype=torch.int64, device=c.device)
+        val = torch.empty(max(cap, 1), dtype=torch.float32, device=c.device)
+        count = torch.empty(1, dtype=torch.int64, device=c.device)
+        ws = _workspace(lib.ps_threshold_workspace_size(n), c.device)
+        _check(lib.ps_threshold(c.data_ptr() if n else None, n, float(thr), int(base),
+                                idx.data_ptr(), val.data_ptr(), cap, count.data_ptr(),
+                                ws.data_ptr(), ws.numel(), _stream(stream)))
     return idx, val, count
+
+
+def clock_probe(iters: int = 200000, stream=None) -> float:
+    """Mean shader clock in GHz under a full vector-ALU load (a measurement
+    aid; synchronises)."""
+    with _on(stream):
+        ws = _workspace(lib.ps_clock_probe_workspace_size(), torch.device("cuda"))
+        _check(lib.ps_clock_probe(int(iters), ws.data_ptr(), ws.numel(), _stream(stream)))
+        torch.cuda.synchronize()
+        v = ws.view(torch.int64).reshape(-1, 3).cpu()
+    return float(v[:, 0].sum()) / float(v[:, 1].sum()) / 10.0
 
 
 # The C ABI's names (include/ps.h) for the same calls.

@@ -23,6 +23,42 @@ def test_exports_every_declared_function():
     assert not missing, missing
 
 
+def _header_enums():
+    """name -> value of every enumerator and #define alias in include/ps.h."""
+    import re
+    txt = re.sub(r"/\*.*?\*/", "", open(ps.HEADER).read(), flags=re.S)
+    vals = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"\b(PS_[A-Z0-9_]+)\s*=\s*(\d+)", txt)}
+    for m in re.finditer(r"#define\s+(PS_[A-Z0-9_]+)\s+(PS_[A-Z0-9_]+)", txt):
+        vals[m.group(1)] = vals[m.group(2)]
+    return vals
+
+
+def test_enum_values_match_the_boundary():
+    """The numbering of the status, storage, accumulation and path enums,
+    as the header declares them and as the binding passes them."""
+    v = _header_enums()
+    assert [v[n] for n in ("PS_OK", "PS_ERR_ARG", "PS_ERR_DTYPE", "PS_ERR_WORKSPACE",
+                           "PS_ERR_HIP", "PS_ERR_UNSUPPORTED")] == [0, 1, 2, 3, 4, 5]
+    assert [v[n] for n in ("PS_F32", "PS_F16", "PS_U8", "PS_F64")] == [0, 1, 2, 3]
+    assert [v[n] for n in ("PS_ACC_PLAIN", "PS_ACC_BLOCKED", "PS_ACC_AUTO")] == [0, 1, 2]
+    assert [v[n] for n in ("PS_PATH_AUTO", "PS_PATH_VALU", "PS_PATH_MFMA",
+                           "PS_PATH_MFMA_FP4", "PS_PATH_BITS")] == [0, 1, 2, 3, 4]
+    assert v["PS_PATH_MFMA_THERMO"] == v["PS_PATH_MFMA"]
+    assert ps.ACC == {"plain": 0, "blocked": 1, "auto": 2}
+    assert ps.PATH == {"auto": 0, "valu": 1, "mfma": 2, "mfma_fp4": 3, "bits": 4}
+    assert (ps.PS_F32, ps.PS_F16, ps.PS_U8, ps.PS_F64) == (0, 1, 2, 3)
+
+
+def test_zero_filled_opts_mean_plain_accumulation():
+    """A zero-filled ps_opts asks for PLAIN accumulation (no field-chunk
+    partials); NULL opts mean AUTO (partials beyond 4096 fields)."""
+    f = lib.ps2_workspace_size
+    zero = ctypes.byref(ps.Opts(0, 0, 0, 0))
+    assert f(0, 9000, 20000, 1, zero) == 0
+    assert f(0, 9000, 20000, 1, None) > 0
+
+
 def test_version_and_status_strings():
     assert lib.ps_version() == 10000
     for st, name in enumerate(["PS_OK", "PS_ERR_ARG", "PS_ERR_DTYPE", "PS_ERR_WORKSPACE",
@@ -30,7 +66,7 @@ def test_version_and_status_strings():
         assert lib.ps_status_string(st).decode() == name
 
 
-def opts(acc=0, path=0, levels=0, tile=0):
+def opts(acc=2, path=0, levels=0, tile=0):
     return ctypes.byref(ps.Opts(acc, path, levels, tile))
 
 
@@ -69,6 +105,28 @@ def call2(V=FAKE, dt=0, n_f=10, n_v=5, ld=10, s=None, c2=FAKE, n2=None, ws=FAKE,
 def test_ps2_argument_errors(kw, status):
     assert call2(**kw) == status
     assert lib.ps_last_error().decode() != ""
+
+
+BIG_NF = 8_421_505          # 255 * n_f >= 2^31: the uint8 VALU sums would overflow
+
+
+@pytest.mark.parametrize("o", [None, opts(path=1), opts(path=1, levels=3)])
+def test_u8_valu_rejects_fields_beyond_its_integer_range(o):
+    assert call2(dt=2, n_f=BIG_NF, ld=BIG_NF, o=o) == UNSUP
+    assert "uint8 VALU" in lib.ps_last_error().decode()
+    assert call3(dt=2, n_f=BIG_NF, ld=BIG_NF, o=o) == UNSUP
+    # one field fewer is inside the range (it fails later, at the fake workspace)
+    assert call2(dt=2, n_f=BIG_NF - 1, ld=BIG_NF, ws_bytes=16, o=o) == WS
+
+
+def test_u8_valu_range_in_a_batch():
+    arr = (ps.Problem * 2)()
+    arr[0] = ps.Problem(FAKE, 10, 5, 10, None, FAKE, None)
+    arr[1] = ps.Problem(FAKE, BIG_NF, 5, BIG_NF, None, FAKE, None)
+    assert lib.ps2_compute_batched(arr, 2, 2, FAKE, 1 << 20, None, None) == UNSUP
+    assert "problem 1" in lib.ps_last_error().decode()
+    # floating data has no such bound
+    assert lib.ps2_compute_batched(arr, 2, 0, FAKE, 16, None, None) == WS
 
 
 def test_ps2_no_pairs_is_noop():
@@ -128,9 +186,9 @@ def test_workspace_sizes():
     # blocked accumulation beyond 4096 fields: FP32 partials of each field chunk
     stage = math.comb(n, 3)
     assert g(0, 9000, n, 1, 1, 1, n - 1, None) == prefixes + math.ceil(3 * stage * 4 / 256) * 256
-    blocked = opts(acc=2)
+    blocked = opts(acc=1)
     assert f(0, 9000, 1000, 1, blocked) == math.ceil(3 * (1000 * 999 // 2) * 4 / 256) * 256
-    assert f(0, 9000, 1000, 1, opts(acc=1)) == 0   # plain: one chunk, no partials
+    assert f(0, 9000, 1000, 1, opts(acc=0)) == 0   # plain: one chunk, no partials
     # auto on a small triangle splits further so that enough workgroups run
     assert f(0, 9000, 1000, 1, None) > f(0, 9000, 1000, 1, blocked)
     assert f(2, 9000, 1000, 1, None) == 0          # integer data: no split

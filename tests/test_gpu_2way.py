@@ -284,7 +284,7 @@ def test_blocked_split_over_field_chunks(tile):
     again, _ = run2(V, acc="blocked", tile=tile)
     assert np.array_equal(c2.view(np.uint32), again.view(np.uint32))
     plain, _ = run2(V, acc="plain", tile=tile)
-    _, er_plain = check_rel(plain, ref, 1e-4, "c2 plain")
+    _, er_plain = check_rel(plain, ref, FP32_TOL, "c2 plain")
     print(f"dense 9001 fields: blocked max rel {er:.2e}, plain max rel {er_plain:.2e}")
 
 
