@@ -205,6 +205,31 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
                       void* workspace, size_t ws_bytes, const ps_opts* opts,
                       hipStream_t stream);
 
+/*
+ * ps3_compute without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Arguments, outputs and results are those of
+ * ps3_compute; the call allocates nothing: its scratch is a static device
+ * array of PS_NOALLOC_SCRATCH_BYTES bytes that each GPU the library runs on
+ * holds from the library's first use there until the process ends.  The
+ * array of the calling thread's current device is used, so `stream` must
+ * belong to that device.
+ *   Scratch need: the value of ps3_workspace_size() for the same arguments.
+ *   With s and n2 given and n_f <= 4096 it is a few tens of KB; computing
+ *   the pair numerators inside takes C(n_v, 2) values plus field-chunk
+ *   partials.  A call that needs more than PS_NOALLOC_SCRATCH_BYTES returns
+ *   PS_ERR_WORKSPACE before anything is launched.
+ *   Every call on one GPU shares that GPU's array, which keeps the last
+ *   call's contents: calls that overlap on one GPU (on different streams,
+ *   or from several host threads without ordering) race and give wrong
+ *   results.  Order them on one stream.
+ */
+#define PS_NOALLOC_SCRATCH_BYTES (32u << 20)
+ps_status ps3_compute_noalloc(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
+                              int64_t ld, const double* s, const void* n2,
+                              int64_t j_begin, int64_t j_end, float* c3,
+                              const ps_opts* opts, hipStream_t stream);
+
 /* Number of c3 values of the stage [j_begin, j_end): off(j_end)-off(j_begin). */
 int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end);
 

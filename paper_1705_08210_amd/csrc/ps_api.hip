@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "ps_internal.h"
@@ -425,10 +426,48 @@ int64_t ps3_stage_size(int64_t n_v, int64_t j_begin, int64_t j_end) {
     return slab_offset(n_v, j_end) - slab_offset(n_v, j_begin);
 }
 
-ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
-                      const double* s, const void* n2, int64_t j_begin, int64_t j_end,
-                      float* c3, void* workspace, size_t ws_bytes, const ps_opts* opts,
-                      hipStream_t stream) {
+}  // extern "C"
+
+namespace ps {
+
+// Static scratch of ps3_compute_noalloc.  Each GPU holds its own copy of this
+// array (allocated when the library's code is loaded on it, kept until the
+// process ends).  Host code never uses the array's name as an address: the
+// per-device address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+static __device__ __align__(256) unsigned char scratch[PS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static ps_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(PS_ERR_UNSUPPORTED, "device %d: the static scratch serves devices 0..%d",
+                    dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || !aligned(p, 256))
+            return fail(PS_ERR_HIP, "static scratch of device %d has no usable address", dev);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PS_OK;
+}
+
+// The body of ps3_compute and ps3_compute_noalloc: `workspace` is the
+// caller's buffer or, with from_scratch, looked up after the argument checks:
+// the static scratch of the current device (ws_bytes is then its size).
+static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                         const double* s, const void* n2, int64_t j_begin, int64_t j_end,
+                         float* c3, void* workspace, size_t ws_bytes, bool from_scratch,
+                         const ps_opts* opts, hipStream_t stream) {
     ps_status st = check_matrix(V, dtype, n_f, n_v, ld);
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
@@ -445,6 +484,16 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (!c3) return fail(PS_ERR_ARG, "c3 is NULL");
     if (!aligned(c3, 4) || !aligned(n2, 4) || !aligned(s, 8))
         return fail(PS_ERR_ARG, "misaligned output, n2 or sums pointer");
+    if (from_scratch) {
+        const size_t need = ps3_workspace_size(dtype, n_f, n_v, s != nullptr, n2 != nullptr,
+                                               j_begin, j_end, opts);
+        if (need > ws_bytes)
+            return fail(PS_ERR_WORKSPACE,
+                        "ps3_compute_noalloc: this call needs %zu bytes of scratch, the static "
+                        "scratch holds %zu (pass s and n2, use a shorter j range, or call "
+                        "ps3_compute with a workspace)", need, ws_bytes);
+        if ((st = scratch_of_current_device(&workspace)) != PS_OK) return st;
+    }
     double* s_ws = nullptr;
     void* n2_ws = nullptr;
     int64_t* prefix = nullptr;
@@ -501,6 +550,26 @@ ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     e = launch_mg3_prefix(a, stream);
     if (e == hipSuccess) e = launch_mg3(kdt, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");
+}
+
+}  // namespace ps
+
+extern "C" {
+
+ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                      const double* s, const void* n2, int64_t j_begin, int64_t j_end,
+                      float* c3, void* workspace, size_t ws_bytes, const ps_opts* opts,
+                      hipStream_t stream) {
+    return ps3_run(V, dtype, n_f, n_v, ld, s, n2, j_begin, j_end, c3, workspace, ws_bytes,
+                   false, opts, stream);
+}
+
+ps_status ps3_compute_noalloc(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
+                              int64_t ld, const double* s, const void* n2, int64_t j_begin,
+                              int64_t j_end, float* c3, const ps_opts* opts,
+                              hipStream_t stream) {
+    return ps3_run(V, dtype, n_f, n_v, ld, s, n2, j_begin, j_end, c3, nullptr,
+                   (size_t)PS_NOALLOC_SCRATCH_BYTES, true, opts, stream);
 }
 
 }  // extern "C"

@@ -64,6 +64,8 @@ _sig("ps2_compute", ctypes.c_int,
 _sig("ps3_workspace_size", SZ, [I32, I64, I64, I32, I32, I64, I64, ctypes.POINTER(Opts)])
 _sig("ps3_compute", ctypes.c_int,
      [P, I32, I64, I64, I64, P, P, I64, I64, P, P, SZ, ctypes.POINTER(Opts), P])
+_sig("ps3_compute_noalloc", ctypes.c_int,
+     [P, I32, I64, I64, I64, P, P, I64, I64, P, ctypes.POINTER(Opts), P])
 _sig("ps3_stage_size", I64, [I64, I64, I64])
 _sig("ps2_batched_workspace_size", SZ, [ctypes.POINTER(Problem), I32, I32,
                                         ctypes.POINTER(Opts)])
@@ -209,6 +211,34 @@ def ps3(V: torch.Tensor, s: torch.Tensor | None = None, n2: torch.Tensor | None 
         _check(lib.ps3_compute(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(n2), j_begin,
                                j_end, c3.data_ptr() if m > 0 else None, ws.data_ptr(),
                                ws.numel(), ctypes.byref(o), _stream(stream)))
+    return c3
+
+
+def noalloc_scratch_bytes() -> int:
+    """PS_NOALLOC_SCRATCH_BYTES of include/ps.h: the static scratch per GPU
+    behind ps3_compute_noalloc."""
+    m = re.search(r"#define\s+PS_NOALLOC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)",
+                  open(HEADER).read())
+    return int(m.group(1)) << int(m.group(2))
+
+
+def ps3_noalloc(V: torch.Tensor, c3: torch.Tensor, s: torch.Tensor | None = None,
+                n2: torch.Tensor | None = None, j_begin: int = 1, j_end: int | None = None,
+                acc="auto", tile=0, path="auto", levels=0, stream=None) -> torch.Tensor:
+    """ps3 through ps3_compute_noalloc: the library takes its scratch from a
+    static per-GPU array instead of a workspace, and this wrapper allocates
+    nothing either (c3, and s / n2 if given, are the caller's).  Calls that
+    overlap on one GPU race on that array."""
+    dt, n_f, n_v, ld = _matrix(V)
+    if j_end is None:
+        j_end = max(n_v - 1, j_begin)
+    m = stage_size(n_v, j_begin, j_end)
+    if c3.dtype != torch.float32 or not c3.is_cuda or not c3.is_contiguous() or c3.numel() < m:
+        raise ValueError(f"c3 must be a contiguous float32 GPU tensor of >= {m} values")
+    o = _opts(acc, path, levels, tile)
+    _check(lib.ps3_compute_noalloc(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(n2), j_begin,
+                                   j_end, c3.data_ptr() if m > 0 else None, ctypes.byref(o),
+                                   _stream(stream)))
     return c3
 
 
@@ -360,5 +390,6 @@ def clock_probe(iters: int = 200000, stream=None) -> float:
 ps_vector_sums = vector_sums
 ps2_compute = ps2
 ps3_compute = ps3
+ps3_compute_noalloc = ps3_noalloc
 ps2_compute_batched = ps2_batched
 ps3_stage_size = stage_size

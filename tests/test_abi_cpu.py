@@ -167,6 +167,35 @@ def test_ps3_argument_errors(kw, status):
     assert call3(**kw) == status
 
 
+def call3_noalloc(V=FAKE, dt=0, n_f=10, n_v=6, ld=10, s=None, n2=None, jb=1, je=5, c3=FAKE,
+                  o=None):
+    return lib.ps3_compute_noalloc(V, dt, n_f, n_v, ld, s, n2, jb, je, c3, o, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(jb=0), ARG),
+    (dict(jb=4, je=3), ARG),
+    (dict(c3=None), ARG),
+    (dict(dt=5), DTYPE),
+    (dict(o=opts(path=2)), UNSUP),
+    (dict(dt=2, o=opts(path=2, levels=0)), ARG),
+    # the pair table of 4200 vectors (35 MB) does not fit the static scratch
+    (dict(n_f=8, ld=8, n_v=4200, je=2), WS),
+])
+def test_ps3_noalloc_argument_errors(kw, status):
+    """Checked before the static scratch is looked up, so no HIP call."""
+    assert call3_noalloc(**kw) == status
+
+
+def test_noalloc_scratch_size_is_the_header_constant():
+    assert ps.noalloc_scratch_bytes() == 32 << 20
+    g = lib.ps3_workspace_size
+    assert g(0, 8, 4200, 0, 0, 1, 2, None) > ps.noalloc_scratch_bytes()
+    assert call3_noalloc(n_f=8, ld=8, n_v=4200, je=2) == WS
+    assert "static scratch" in lib.ps_last_error().decode()
+    assert call3_noalloc(jb=3, je=3, c3=None) == OK        # empty stage: nothing to do
+
+
 def test_ps3_empty_cases_are_noops():
     assert call3(jb=3, je=3, c3=None, ws=None, ws_bytes=0) == OK
     assert call3(n_v=2, jb=1, je=1, c3=None, ws=None, ws_bytes=0) == OK
