@@ -66,7 +66,8 @@ int64_t mfma_row_bytes(int64_t n_f, int levels, int fmt) {
     return (int64_t)levels * (plane_fields(n_f, fmt) / fields_per_byte(fmt));
 }
 
-size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt) {
+size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt, int wide) {
+    if (mfma_fused(n_f, levels, fmt, wide)) return 0;
     return (size_t)n_v * (size_t)mfma_row_bytes(n_f, levels, fmt);
 }
 
@@ -430,6 +431,491 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_ke
 }
 
 // ---------------------------------------------------------------------------
+// Fused thermometer operands (int8).  The tiles hold V's own bytes and the
+// level planes are formed in registers from the LDS fragments, so V is read
+// once (no plane pass, no plane workspace) and a staged byte serves every
+// level: the LDS and L2 traffic per multiply-add drop by the number of
+// levels.  Two ways to form [v >= t] four bytes at a time:
+//   kLvPerm (levels <= 7): v_perm_b32 with v's bytes as selectors into an
+//     8-byte table whose byte k is [k >= t]; one instruction per word, both
+//     operands 0/1, int32 sums exact up to 2^31.
+//   kLvSub (levels 8..127): bytes staged as x = v | 0x80; x - t never
+//     borrows across bytes and has bit 7 set exactly when v >= t.  A
+//     fragments become -128 [v >= t] (sub, and), B fragments [v >= t] (sub,
+//     shift, and); the sums are -128 min(a, b) summed, exact while
+//     levels * n_f < 2^24.
+// For the 3-way slices the B rows are min(v_i, v_j) bytewise, formed while
+// staging ([min(a, b) >= t] = [a >= t][b >= t]).
+// ---------------------------------------------------------------------------
+constexpr int kLvMK = 128;   // fields per field tile (one byte each)
+enum { kLvPerm = 0, kLvSub = 1 };
+
+__host__ __device__ constexpr int lv_mode(int levels) { return levels <= 7 ? kLvPerm : kLvSub; }
+
+struct LvArgs {
+    const uint8_t* V;
+    int64_t ld, n_f, n_v;
+    int levels;
+    int64_t nk;           // field tiles
+    const double* s;
+    float* c2;
+    int32_t* n2;
+    int64_t nb, ntiles;
+    // 3-way
+    int64_t j_begin, j_end;
+    const int64_t* prefix;
+    uint32_t* c3;
+    int64_t item0;
+    int32_t mode, ob;
+};
+
+// Bytewise unsigned min of two words whose bytes all have bit 7 set.  Per
+// byte, a - (b AND 0x7f) = 0x80 + (a7 - b7) lies in [1, 255], so bit 7 says
+// a >= b and nothing borrows; the flags widen to 0xff bytes.
+__device__ __forceinline__ uint32_t bytemin_hi(uint32_t a, uint32_t b) {
+    const uint32_t ge = (a - (b & 0x7f7f7f7fu)) & 0x80808080u;
+    const uint32_t m = ge | (ge - (ge >> 7));
+    return (b & m) | (a & ~m);
+}
+
+// 16 bytes at byte offset `off` of a buffer: one b128 load when rows are
+// 16-byte aligned, else byte loads.
+template <bool ALIGNED>
+__device__ __forceinline__ uint4 lv_load16(__amdgpu_buffer_rsrc_t rs, int off) {
+    if constexpr (ALIGNED) {
+        const v4u_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            uint32_t x = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                x |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off + 4 * e + b, 0, 0)
+                     << (8 * b);
+            w[e] = x;
+        }
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Bytes of fields at or past n_f (nvalid = n_f - first field of the chunk)
+// cleared; kLvSub also ORs every byte with 0x80.
+template <int MODE>
+__device__ __forceinline__ uint4 lv_prep(uint4 v, int nvalid) {
+    if (nvalid < 16) {
+        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = nvalid - 4 * e;
+            w[e] &= k >= 4 ? 0xffffffffu : k <= 0 ? 0u : (1u << (8 * k)) - 1u;
+        }
+        v = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    if constexpr (MODE == kLvSub)
+        v = make_uint4(v.x | 0x80808080u, v.y | 0x80808080u, v.z | 0x80808080u,
+                       v.w | 0x80808080u);
+    return v;
+}
+
+// Bytewise min of staged words (the 3-way X_j rows).
+template <int MODE>
+__device__ __forceinline__ uint32_t lv_min(uint32_t a, uint32_t b) {
+    if constexpr (MODE == kLvSub) return bytemin_hi(a, b);
+    return bytemin_hi(a | 0x80808080u, b | 0x80808080u) & 0x7f7f7f7fu;
+}
+
+// Level t of a fragment.
+__device__ __forceinline__ v4i_t lv_perm(v4i_t f, uint32_t hi, uint32_t lo) {
+    v4i_t r;   // byte k of {hi, lo} for each selector byte k = v (0..7)
+    r.x = (int)__builtin_amdgcn_perm(hi, lo, (uint32_t)f.x);
+    r.y = (int)__builtin_amdgcn_perm(hi, lo, (uint32_t)f.y);
+    r.z = (int)__builtin_amdgcn_perm(hi, lo, (uint32_t)f.z);
+    r.w = (int)__builtin_amdgcn_perm(hi, lo, (uint32_t)f.w);
+    return r;
+}
+__device__ __forceinline__ v4i_t lv_suba(v4i_t f, uint32_t tt) {   // -128 [v >= t]
+    v4i_t r;
+    r.x = (int)(((uint32_t)f.x - tt) & 0x80808080u);
+    r.y = (int)(((uint32_t)f.y - tt) & 0x80808080u);
+    r.z = (int)(((uint32_t)f.z - tt) & 0x80808080u);
+    r.w = (int)(((uint32_t)f.w - tt) & 0x80808080u);
+    return r;
+}
+__device__ __forceinline__ v4i_t lv_subb(v4i_t f, uint32_t tt) {   // [v >= t]
+    v4i_t r;
+    r.x = (int)((((uint32_t)f.x - tt) >> 7) & 0x01010101u);
+    r.y = (int)((((uint32_t)f.y - tt) >> 7) & 0x01010101u);
+    r.z = (int)((((uint32_t)f.z - tt) >> 7) & 0x01010101u);
+    r.w = (int)((((uint32_t)f.w - tt) >> 7) & 0x01010101u);
+    return r;
+}
+
+// Main loop of one fused TB x TB tile: A rows a0 .. a0+TB-1 and B rows
+// b0 .. b0+TB-1 of V (rows at or past n_v read as zero through the buffer
+// bound); with MASK the B rows are min-ed with row mj.  Staging as in
+// mfma_tile: tile kt+1 goes from registers into the second LDS buffer while
+// tile kt is consumed, one barrier per field tile.  Inside a field tile the
+// fragments of k-step ks+1 are read while k-step ks runs; the compiler
+// interleaves the level transforms with the multiply-adds (measured: up to
+// about six independent VALU instructions per 32x32x32 MFMA run beside the
+// matrix core at no cost with two waves per SIMD, and an explicit
+// sched_group_barrier interleave of the transforms was 20% slower).  LC > 0
+// fixes the number of levels at compile time (0: a.levels at run time).  The
+// sums come out as counts.
+template <int WN, bool MASK, bool ALIGNED, int LC, int MODE, int TB = kMB>
+__device__ __forceinline__ void lv_tile(const LvArgs& a, int64_t a0, int64_t b0, int64_t mj,
+                                        bool active, int wr, int wc,
+                                        v16i_t (&acc)[TB / 64][WN], int8_t* lds) {
+    constexpr int WM = TB / 64;
+    constexpr int kMThreads = mfma_threads<WN, TB>();
+    constexpr int kMK = kLvMK;
+    constexpr int KS = kMK / 32;                   // k-steps per field tile
+    constexpr int kPitch = kMK + kPad;
+    constexpr int kRowChunks = kMK / 16;
+    constexpr int kStage = TB * kRowChunks / kMThreads;
+    constexpr int kRowStep = kMThreads / kRowChunks;
+    static_assert(TB * kRowChunks % kMThreads == 0, "staging must divide evenly");
+    auto As = [&](int buf) { return lds + (2 * buf) * (TB * kPitch); };
+    auto Bs = [&](int buf) { return lds + (2 * buf + 1) * (TB * kPitch); };
+    const int lane = threadIdx.x % 64;
+    const int L = LC > 0 ? LC : a.levels;
+
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int n = 0; n < WN; ++n) acc[m][n] = (v16i_t){};
+
+    // the host checks 256 * ld + 256 < 2^31, so a tile's rows take 32-bit offsets
+    auto rsrc = [&](int64_t r0) {
+        const int64_t rows = r0 < a.n_v ? (a.n_v - r0 < TB ? a.n_v - r0 : TB) : 0;
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(a.V + (rows > 0 ? r0 : 0) * a.ld),
+                                                 (short)0, (int)(rows * a.ld), kRsrcWord3);
+    };
+    const __amdgpu_buffer_rsrc_t rsa = rsrc(a0), rsb = rsrc(b0);
+    __amdgpu_buffer_rsrc_t rsm;
+    if constexpr (MASK)
+        rsm = __builtin_amdgcn_make_buffer_rsrc((void*)(a.V + mj * a.ld), (short)0, (int)a.n_f,
+                                                kRsrcWord3);
+    uint4 ra[kStage], rb[kStage];
+    const int ch = threadIdx.x % kRowChunks;
+    const int ldi = (int)a.ld;
+    const int voff = (threadIdx.x / kRowChunks) * ldi + ch * 16;
+    auto load = [&](int64_t kt) {
+        const int f0 = (int)kt * kMK + ch * 16;
+        const int nvalid = (int)a.n_f - f0;
+        uint4 mk = make_uint4(0, 0, 0, 0);
+        if constexpr (MASK) mk = lv_prep<MODE>(lv_load16<ALIGNED>(rsm, f0), nvalid);
+#pragma unroll
+        for (int c = 0; c < kStage; ++c) {
+            const int off = voff + c * kRowStep * ldi + (int)kt * kMK;
+            ra[c] = lv_prep<MODE>(lv_load16<ALIGNED>(rsa, off), nvalid);
+            rb[c] = lv_prep<MODE>(lv_load16<ALIGNED>(rsb, off), nvalid);
+            if constexpr (MASK) {
+                rb[c].x = lv_min<MODE>(rb[c].x, mk.x);
+                rb[c].y = lv_min<MODE>(rb[c].y, mk.y);
+                rb[c].z = lv_min<MODE>(rb[c].z, mk.z);
+                rb[c].w = lv_min<MODE>(rb[c].w, mk.w);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < kStage; ++c) {
+            const int row = (threadIdx.x + c * kMThreads) / kRowChunks;
+            *(uint4*)(As(buf) + row * kPitch + ch * 16) = ra[c];
+            *(uint4*)(Bs(buf) + row * kPitch + ch * 16) = rb[c];
+        }
+    };
+
+    const int64_t nk = a.nk;
+    load(0);
+    store(0);
+    __syncthreads();
+    if (nk > 1) load(1);
+    const int fr = lane % 32, fk = (lane / 32) * 16;
+    auto frag = [&](const int8_t* A, const int8_t* B, int ks, v4i_t (&fa)[WM], v4i_t (&fb)[WN]) {
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+            fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
+#pragma unroll
+        for (int n = 0; n < WN; ++n)
+            fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
+    };
+    auto level = [&](const v4i_t (&fa)[WM], const v4i_t (&fb)[WN], int t) {
+        v4i_t xa[WM], xb[WN];
+        if constexpr (MODE == kLvPerm) {
+            // table byte k = [k >= t], k = 0..7
+            const uint32_t lo = t <= 3 ? 0x01010101u << (8 * t) : 0u;
+            const uint32_t hi = t <= 4 ? 0x01010101u : 0x01010101u << (8 * (t - 4));
+#pragma unroll
+            for (int m = 0; m < WM; ++m) xa[m] = lv_perm(fa[m], hi, lo);
+#pragma unroll
+            for (int n = 0; n < WN; ++n) xb[n] = lv_perm(fb[n], hi, lo);
+        } else {
+            const uint32_t tt = (uint32_t)t * 0x01010101u;
+#pragma unroll
+            for (int m = 0; m < WM; ++m) xa[m] = lv_suba(fa[m], tt);
+#pragma unroll
+            for (int n = 0; n < WN; ++n) xb[n] = lv_subb(fb[n], tt);
+        }
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[m], xb[n], acc[m][n], 0, 0,
+                                                                  0);
+    };
+    auto step = [&](int64_t kt, int cur) {
+        const int8_t* A = As(cur);
+        const int8_t* B = Bs(cur);
+        v4i_t fa[2][WM], fb[2][WN];
+        frag(A, B, 0, fa[0], fb[0]);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks + 1 < KS) frag(A, B, ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
+#pragma unroll(LC > 0 ? LC : 1)
+            for (int t = 1; t <= L; ++t) level(fa[ks & 1], fb[ks & 1], t);
+        }
+        // tile kt+1 into the other buffer (after the last tile the write is
+        // stale and never read; unconditional, so it joins this block)
+        store(cur ^ 1);
+        __syncthreads();   // kt+1 visible; everyone is done reading kt
+        if (kt + 2 < nk) load(kt + 2);
+    };
+    if (active) {
+        for (int64_t kt = 0; kt < nk; ++kt) step(kt, (int)(kt & 1));
+    } else {
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) store((int)(kt & 1) ^ 1);
+            __syncthreads();
+            if (kt + 2 < nk) load(kt + 2);
+        }
+    }
+    if constexpr (MODE == kLvSub) {   // -128 * count -> count
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[m][n][r] = -acc[m][n][r] >> 7;
+    }
+}
+
+template <int WN, bool ALIGNED, int LC, int MODE>
+__global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_lv_kernel(LvArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[4 * kMB * (kLvMK + kPad)];
+    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                      blockIdx.x / kXcds;
+    if (t >= a.ntiles) return;
+    int64_t bi, bj;
+    grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
+    const int64_t i0 = bi * kMB, j0 = bj * kMB;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wr = (wave % 2) * 128;        // j offset of the wave's block (A rows)
+    const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
+    const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
+    v16i_t acc[4][WN];
+    lv_tile<WN, false, ALIGNED, LC, MODE>(a, j0, i0, 0, active, wr, wc, acc, lds);
+    if (!active) return;
+    MfmaArgs e{};
+    e.n_v = a.n_v;
+    e.s = a.s;
+    e.c2 = a.c2;
+    e.n2 = a.n2;
+    mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
+}
+
+template <int TB, bool ALIGNED, int LC, int MODE>
+__global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_lv_kernel(
+    LvArgs a) {
+    constexpr int WN = 2, WM = TB / 64;
+    __shared__ __attribute__((aligned(16))) int8_t lds[4 * TB * (kLvMK + kPad)];
+    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                      blockIdx.x / kXcds;
+    if (t >= a.ntiles) return;
+    int64_t lo = 0, hi = a.j_end - a.j_begin;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (a.prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int64_t j = a.j_begin + lo;
+    int64_t i0, k0;
+    slab_tile_origin(a.n_v, j, t - a.prefix[lo], TB, a.mode, a.ob, i0, k0);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wr = (wave % 2) * (TB / 2);   // k offset of the wave's block (A rows)
+    const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
+    const bool active = (k0 + wr < a.n_v) && (i0 + wc < j);
+    v16i_t acc[WM][WN];
+    lv_tile<WN, true, ALIGNED, LC, MODE, TB>(a, k0, i0, j, active, wr, wc, acc, lds);
+    if (!active) return;
+    // Eq. 1 on exact integers: n3 = n2(i,j) + n2(i,k) + n2(j,k) - n3', then
+    // c3 = 3 n3 / (2 (s_i + s_j + s_k)) in FP64, rounded once to FP32 (d = 0
+    // gives 0).  Every operand is an integer below 2^53, so the FP64 quotient
+    // is the correctly rounded one whatever the order of the sums.  The
+    // operands of a 32-row block are loaded together before any of its
+    // stores (the stores could alias them for all the compiler knows, which
+    // would otherwise serialise one load round trip per row).
+    const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin);
+    const int64_t ib = i0 + wc + (lane % 32);
+    const double* __restrict__ S = a.s;
+    const int32_t* __restrict__ N2 = a.n2;
+    float* __restrict__ c3 = (float*)a.c3;
+    const double sj = S[j];
+    const int64_t cj = j * (j - 1) / 2;   // n2(i, j) = N2[cj + i], i < j
+    double si[WN];
+    int64_t nij[WN];
+#pragma unroll
+    for (int n = 0; n < WN; ++n) {
+        const int64_t i = ib + n * 32;
+        si[n] = i < j ? S[i] : 0.0;
+        nij[n] = i < j ? N2[cj + i] : 0;
+    }
+    // rows of the accumulators in batches of RB: the loads of batch b+1 are
+    // issued before batch b is computed and stored (two register sets)
+    constexpr int RB = 4, NB = WM * 16 / RB;
+    struct Batch {
+        double sk[RB];
+        int32_t njk[RB], nik[RB][WN];
+    };
+    auto row_k = [&](int b, int q) {   // k of row q of batch b
+        const int m = b / (16 / RB), r = (b % (16 / RB)) * RB + q;
+        return k0 + wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
+    };
+    auto load_batch = [&](int b, Batch& o) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            int64_t k = row_k(b, q);
+            if (k >= a.n_v) k = a.n_v - 1;   // loaded but not stored
+            const int64_t ck = k * (k - 1) / 2;   // n2(x, k) = N2[ck + x], x < k
+            o.sk[q] = S[k];
+            o.njk[q] = N2[ck + j];
+#pragma unroll
+            for (int n = 0; n < WN; ++n) {
+                const int64_t i = ib + n * 32;
+                o.nik[q][n] = N2[ck + (i < j ? i : 0)];
+            }
+        }
+    };
+    auto store_batch = [&](int b, const Batch& o) {
+        const int m = b / (16 / RB);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = (b % (16 / RB)) * RB + q;
+            const int64_t k = row_k(b, q);
+            if (k >= a.n_v) continue;
+            float* row = c3 + base + (k - j - 1) * j;
+#pragma unroll
+            for (int n = 0; n < WN; ++n) {
+                const int64_t i = ib + n * 32;
+                if (i >= j) continue;
+                const int64_t n3 =
+                    nij[n] + (int64_t)o.nik[q][n] + (int64_t)o.njk[q] - (int64_t)acc[m][n][r];
+                const double d3 = (si[n] + sj) + o.sk[q];
+                row[i] = d3 > 0.0 ? (float)((3.0 * (double)n3) / (2.0 * d3)) : 0.0f;
+            }
+        }
+    };
+    Batch bt[2];
+    load_batch(0, bt[0]);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB) load_batch(b + 1, bt[(b + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        store_batch(b, bt[b & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+static LvArgs lv_args(const MfmaLaunch& m) {
+    LvArgs a{};
+    a.V = (const uint8_t*)m.V;
+    a.ld = m.ld;
+    a.n_f = m.n_f;
+    a.n_v = m.n_v;
+    a.levels = m.levels;
+    a.nk = (m.n_f + kLvMK - 1) / kLvMK;
+    if (a.nk < 1) a.nk = 1;
+    a.s = m.s;
+    a.c2 = m.c2;
+    a.n2 = (int32_t*)m.n2;
+    return a;
+}
+
+static bool lv_aligned(const MfmaLaunch& m) {
+    return (uintptr_t)m.V % 16 == 0 && m.ld % 16 == 0;
+}
+
+template <bool ALIGNED, int LC, int MODE>
+static hipError_t go_mfma2_lv(const MfmaLaunch& m, hipStream_t st) {
+    LvArgs a = lv_args(m);
+    a.nb = (m.n_v + kMB - 1) / kMB;
+    a.ntiles = a.nb * (a.nb + 1) / 2;
+    return launch_items(a.ntiles, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+        LvArgs b = a;
+        b.item0 = item0;
+        hipLaunchKernelGGL((ps_mfma2_lv_kernel<2, ALIGNED, LC, MODE>), dim3(grid),
+                           dim3(mfma_threads<2>()), 0, st, b);
+    });
+}
+
+template <bool ALIGNED, int LC, int MODE>
+static hipError_t go_mfma3_lv(const MfmaLaunch& m, hipStream_t st) {
+    constexpr int kEdge = kMB / 2;
+    hipError_t e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kMB, kSlabFull, kMB, m.prefix, st);
+    if (e == hipSuccess)
+        e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kEdge, kSlabEdge, kMB, m.edge_prefix, st);
+    if (e != hipSuccess) return e;
+    LvArgs a = lv_args(m);   // a.n2: the pair numerators of Eq. 1
+    a.j_begin = m.j_begin;
+    a.j_end = m.j_end;
+    a.c3 = (uint32_t*)m.c3;
+    a.prefix = m.prefix;
+    a.mode = kSlabFull;
+    a.ob = kMB;
+    a.ntiles = slab_tiles(m.n_v, m.j_begin, m.j_end, kMB, kSlabFull, kMB);
+    const int64_t T2 = slab_tiles(m.n_v, m.j_begin, m.j_end, kEdge, kSlabEdge, kMB);
+    if (a.ntiles > 0)
+        e = launch_items(a.ntiles, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+            LvArgs b = a;
+            b.item0 = item0;
+            hipLaunchKernelGGL((ps_mfma3_lv_kernel<kMB, ALIGNED, LC, MODE>), dim3(grid),
+                               dim3(mfma_threads<2>()), 0, st, b);
+        });
+    if (e != hipSuccess || T2 == 0) return e;
+    a.ntiles = T2;
+    a.prefix = m.edge_prefix;
+    a.mode = kSlabEdge;
+    return launch_items(T2, mfma_threads<2, kEdge>(), kXcds, [&](unsigned grid, int64_t item0) {
+        LvArgs b = a;
+        b.item0 = item0;
+        hipLaunchKernelGGL((ps_mfma3_lv_kernel<kEdge, ALIGNED, LC, MODE>), dim3(grid),
+                           dim3(mfma_threads<2, kEdge>()), 0, st, b);
+    });
+}
+
+// The fused launch for m: 16-byte row loads when V and its stride allow;
+// table lookups for levels <= 7 (three levels unrolled and scheduled at
+// compile time, the common case), the subtraction form above.
+template <int WAY, bool AL>
+static hipError_t go_lv_al(const MfmaLaunch& m, hipStream_t st) {
+    if (WAY == 2) {
+        if (m.levels == 3) return go_mfma2_lv<AL, 3, kLvPerm>(m, st);
+        if (m.levels <= 7) return go_mfma2_lv<AL, 0, kLvPerm>(m, st);
+        return go_mfma2_lv<AL, 0, kLvSub>(m, st);
+    }
+    if (m.levels == 3) return go_mfma3_lv<AL, 3, kLvPerm>(m, st);
+    if (m.levels <= 7) return go_mfma3_lv<AL, 0, kLvPerm>(m, st);
+    return go_mfma3_lv<AL, 0, kLvSub>(m, st);
+}
+
+template <int WAY>
+static hipError_t go_lv(const MfmaLaunch& m, hipStream_t st) {
+    return lv_aligned(m) ? go_lv_al<WAY, true>(m, st) : go_lv_al<WAY, false>(m, st);
+}
+
+// ---------------------------------------------------------------------------
 // LDS-direct variant (used for fp4): field tiles go from global memory
 // straight into LDS (global_load_lds_dwordx4: one wave instruction fills
 // 1 KB of LDS, lane l at byte 16 l), so no registers hold staged data and
@@ -654,11 +1140,13 @@ static hipError_t go_mfma3(const MfmaLaunch& m, hipStream_t st) {
 
 hipError_t launch_mfma3(const MfmaLaunch& m, hipStream_t st) {
     if (m.n_v < 3 || m.j_end <= m.j_begin) return hipSuccess;
+    if (mfma_fused(m.n_f, m.levels, m.fmt, 0)) return go_lv<3>(m, st);
     return m.fmt == kFmtF4 ? go_mfma3<kFmtF4>(m, st) : go_mfma3<kFmtI8>(m, st);
 }
 
 hipError_t launch_mfma2(const MfmaLaunch& m, hipStream_t st) {
     if (m.n_v < 2) return hipSuccess;
+    if (mfma_fused(m.n_f, m.levels, m.fmt, m.wide)) return go_lv<2>(m, st);
     if (m.wide)
         return m.fmt == kFmtF4 ? go_mfma2<kFmtF4, 4>(m, st) : go_mfma2<kFmtI8, 4>(m, st);
     return m.fmt == kFmtF4 ? go_mfma2<kFmtF4, 2>(m, st) : go_mfma2<kFmtI8, 2>(m, st);

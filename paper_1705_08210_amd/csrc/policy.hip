@@ -128,12 +128,13 @@ int64_t max_grid_blocks(int threads, int64_t multiple) {
 
 bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4; }
 
-int choose_path(int32_t dt, const ps_opts* o, int64_t n_f) {
+int choose_path(int32_t dt, const ps_opts* o, int64_t n_f, int64_t ld) {
     const int p = o ? o->path : PS_PATH_AUTO;
     if (p == PS_PATH_VALU || p == PS_PATH_MFMA || p == PS_PATH_MFMA_FP4 || p == PS_PATH_BITS)
         return p;
     if (dt == PS_U8 && o && o->levels >= 1 && o->levels <= 15 &&
-        mfma_row_fits(n_f, o->levels, 0))
+        (mfma_fused(n_f, o->levels, 0, o->tile == 2) ? mfma_ld_fits(ld)
+                                                     : mfma_row_fits(n_f, o->levels, 0)))
         return PS_PATH_MFMA;
     return PS_PATH_VALU;
 }

@@ -113,7 +113,8 @@ static bool is_bits(const ps_opts* o) { return o && o->path == PS_PATH_BITS; }
 
 // The thermometer paths take uint8 data with a bound on its values, and every
 // numerator (at most levels * n_f) must be exact in the accumulator.
-static ps_status check_mfma(int path, int32_t dtype, int levels, int64_t n_f) {
+static ps_status check_mfma(int path, int32_t dtype, int levels, int64_t n_f, int64_t ld,
+                            int wide) {
     if (!is_mfma(path)) return PS_OK;
     if (dtype != PS_U8) return fail(PS_ERR_UNSUPPORTED, "the MFMA path needs PS_U8 data");
     if (levels < 1) return fail(PS_ERR_ARG, "the MFMA path needs opts.levels >= max(V) >= 1");
@@ -123,7 +124,15 @@ static ps_status check_mfma(int path, int32_t dtype, int levels, int64_t n_f) {
     if (path == PS_PATH_MFMA && (int64_t)levels * n_f >= ((int64_t)1 << 31))
         return fail(PS_ERR_ARG, "int8 path: levels * n_f = %lld exceeds int32",
                     (long long)levels * n_f);
-    if (!mfma_row_fits(n_f, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0))
+    const int fmt = path == PS_PATH_MFMA_FP4 ? 1 : 0;
+    if (mfma_fused(n_f, levels, fmt, wide)) {
+        if (!mfma_ld_fits(ld))
+            return fail(PS_ERR_UNSUPPORTED,
+                        "int8 MFMA path: rows of %lld bytes are too long for 32-bit tile offsets "
+                        "(256 rows must span < 2^31 bytes); use the VALU path", (long long)ld);
+        return PS_OK;
+    }
+    if (!mfma_row_fits(n_f, levels, fmt))
         return fail(PS_ERR_UNSUPPORTED,
                     "MFMA path: plane rows of %lld bytes (levels * n_f = %lld) are too long for "
                     "32-bit tile offsets (256 rows must span < 2^31 bytes); use the VALU path",
@@ -164,7 +173,7 @@ static hipError_t launch_mgb(int32_t dt, const MgBatchLaunch& a, hipStream_t st)
 
 // Sizes of the 2-way workspace regions.  Returns total bytes.
 static size_t ws2_layout(int32_t dt, int64_t n_f, int64_t n_v, int32_t s_given, int path,
-                         int levels, int32_t nchunks, void* ws, double** s_ws,
+                         int levels, int wide, int32_t nchunks, void* ws, double** s_ws,
                          int8_t** planes, float** partial) {
     Carver c(ws);
     double* s = nullptr;
@@ -173,7 +182,7 @@ static size_t ws2_layout(int32_t dt, int64_t n_f, int64_t n_v, int32_t s_given, 
     float* part = nullptr;
     if (is_mfma(path) && dt == PS_U8)
         pl = (int8_t*)c.take(
-            mfma_workspace_bytes(n_f, n_v, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0));
+            mfma_workspace_bytes(n_f, n_v, levels, path == PS_PATH_MFMA_FP4 ? 1 : 0, wide));
     else if (path == PS_PATH_BITS && dt == PS_U8)   // the packed bits
         pl = (int8_t*)c.take(bits_bytes(n_f, n_v));
     else if (nchunks > 1)
@@ -220,13 +229,13 @@ ps_status ps_vector_sums(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
 size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_given,
                           const ps_opts* opts) {
     if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
-    const int path = choose_path(dtype, opts, n_f);
+    const int path = choose_path(dtype, opts, n_f, n_f);
     const Split sp = path == PS_PATH_BITS
                          ? Split{1, 0}
                          : plan_split(dtype, n_f, n_v,
                                       choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
-    return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0, sp.nchunks,
-                      nullptr, nullptr, nullptr, nullptr);
+    return ws2_layout(dtype, n_f, n_v, s_given, path, opts ? opts->levels : 0,
+                      opts && opts->tile == 2, sp.nchunks, nullptr, nullptr, nullptr, nullptr);
 }
 
 ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
@@ -240,9 +249,10 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (!aligned(c2, 4) || !aligned(n2, 4) || !aligned(s, 8))
         return fail(PS_ERR_ARG, "misaligned output or sums pointer");
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
-    const int path = choose_path(dtype, opts, n_f);
+    const int path = choose_path(dtype, opts, n_f, ld);
     const int levels = opts ? opts->levels : 0;
-    if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
+    const int wide = opts && opts->tile == 2;
+    if ((st = check_mfma(path, dtype, levels, n_f, ld, wide)) != PS_OK) return st;
     if ((st = check_int_range(path, dtype, n_f)) != PS_OK) return st;
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
@@ -251,8 +261,8 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     const int cfg = bits ? choose_cfg(PS_B1, 2, PS_PATH_BITS, n_f, n_v, opts)
                          : choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
     const Split sp = bits ? Split{1, 0} : plan_split(dtype, n_f, n_v, cfg, opts);
-    const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, sp.nchunks,
-                                   workspace, &s_ws, &planes, &partial);
+    const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, wide,
+                                   sp.nchunks, workspace, &s_ws, &planes, &partial);
     if (ws_bytes < need || (need && !workspace))
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
     if (!aligned(workspace, 256)) return fail(PS_ERR_ARG, "workspace is not 256-byte aligned");
@@ -265,8 +275,7 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (is_mfma(path)) {
         // opts.tile: 0 or 1 -> 4x2 blocks per wave, 2 -> 4x4 blocks per wave
         MfmaLaunch m{V, n_f, n_v, ld, levels, s, c2, n2, planes,
-                     path == PS_PATH_MFMA_FP4 ? 1 : 0, (opts && opts->tile == 2) ? 1 : 0,
-                     1, 0, 0, nullptr, nullptr};
+                     path == PS_PATH_MFMA_FP4 ? 1 : 0, wide, 1, 0, 0, nullptr, nullptr};
         e = launch_mfma2(m, stream);
         if (e == hipErrorNotSupported)
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this library");
@@ -330,7 +339,7 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
     float* partial = nullptr;
     uint32_t* planes = nullptr;
     const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, 4, 1, 1, stage,
-                                   mfma_workspace_bytes(n_f, n_v, levels, fmt), workspace,
+                                   mfma_workspace_bytes(n_f, n_v, levels, fmt, 0), workspace,
                                    &s_ws, &n2_ws, &prefix, &partial, &planes);
     if (ws_bytes < need || !workspace)
         return fail(PS_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
@@ -351,8 +360,10 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
         n2 = n2_ws;
         m.expand = 0;
     }
+    m.n2 = (void*)n2;   // the pair numerators of Eq. 1
     e = launch_mfma3(m, stream);
     if (e != hipSuccess) return hip_fail(e, "3-way mfma launch");
+    if (mfma_fused(n_f, levels, fmt, 0)) return PS_OK;   // Eq. 1 applied in the slices
     Mg3Launch f{V,        n_f,     n_v, ld, s,  n2,      j_begin, j_end, c3, prefix, 0, 0, 1,
                 0,        nullptr, kSlabAll, 0, -1, nullptr, 0,       0};
     e = launch_c3_finish_int(f, stream);
@@ -369,11 +380,11 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (is_bits(opts))
         return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage, bits_bytes(n_f, n_v), nullptr,
                           nullptr, nullptr, nullptr, nullptr, nullptr);
-    const int path = choose_path(dtype, opts, n_f);
+    const int path = choose_path(dtype, opts, n_f, n_f);
     if (is_mfma(path) && dtype == PS_U8)
         return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage,
                           mfma_workspace_bytes(n_f, n_v, opts ? opts->levels : 0,
-                                               path == PS_PATH_MFMA_FP4 ? 1 : 0),
+                                               path == PS_PATH_MFMA_FP4 ? 1 : 0, 0),
                           nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     const Split sp2 =
         plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
@@ -472,9 +483,9 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
-    const int path = choose_path(dtype, opts, n_f);
+    const int path = choose_path(dtype, opts, n_f, ld);
     const int levels = opts ? opts->levels : 0;
-    if ((st = check_mfma(path, dtype, levels, n_f)) != PS_OK) return st;
+    if ((st = check_mfma(path, dtype, levels, n_f, ld, 0)) != PS_OK) return st;
     if ((st = check_int_range(path, dtype, n_f)) != PS_OK) return st;
     if (n_v < 3) return PS_OK;
     if (j_begin < 1 || j_end > n_v - 1 || j_begin > j_end)

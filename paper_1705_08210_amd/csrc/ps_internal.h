@@ -185,8 +185,9 @@ int64_t chunk_tiles(int32_t dt, int cfg);
 Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o);
 bool is_mfma(int path);
 // AUTO takes the int8 MFMA path for PS_U8 data with 1 <= levels <= 15 whose
-// plane rows fit mfma_row_fits().
-int choose_path(int32_t dt, const ps_opts* o, int64_t n_f);
+// rows fit the 32-bit tile offsets (mfma_ld_fits on the fused path,
+// mfma_row_fits on planes); ld is the row stride (n_f in size queries).
+int choose_path(int32_t dt, const ps_opts* o, int64_t n_f, int64_t ld);
 int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o);
 
 // Arguments of one 2-way launch over the upper-triangle tile list.
@@ -332,13 +333,27 @@ struct MfmaLaunch {
     int fmt;                     // 0: int8 planes, 1: fp4 (e2m1) planes
     int wide;                    // 0: 4x2 MFMA blocks per wave, 1: 4x4
     int expand;                  // 1: write the planes first; 0: planes already hold V's
-    // 3-way slices (launch_mfma3): raw n3' of the stage into c3 (int32 bits)
+    // 3-way slices (launch_mfma3): n2 holds the pair numerators; the fused
+    // path (mfma_fused) writes the metric c3 of the stage, the plane path raw
+    // n3' (int32 bits) for launch_c3_finish_int
     int64_t j_begin, j_end;
     int64_t* prefix;             // workspace: j_end - j_begin + 1 int64
     float* c3;
     int64_t* edge_prefix;        // 3-way: the edge tiles' slab prefix, as prefix
 };
-size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt);
+// The int8 thermometer kernels with the 4x2 wave layout threshold V's bytes
+// in registers (no plane pass and no plane workspace) when the sums fit
+// int32: as counts for levels <= 7 (levels * n_f < 2^31), as -128 counts
+// for more levels (levels * n_f < 2^24).  The others read planes.
+inline bool mfma_fused(int64_t n_f, int levels, int fmt, int wide) {
+    return fmt == 0 && !wide &&
+           (int64_t)levels * n_f < ((int64_t)1 << (levels <= 7 ? 31 : 24));
+}
+// The fused kernels address a 256-row tile of V with 32-bit buffer offsets
+// (the last row's field offsets reach at most ld + 127 past its start).
+inline bool mfma_ld_fits(int64_t ld) { return 256 * ld + 256 < ((int64_t)1 << 31); }
+// Plane workspace of a thermometer launch (0 on the fused path).
+size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt, int wide);
 // Bytes of one thermometer plane row (all levels) of an n_f-field vector.
 int64_t mfma_row_bytes(int64_t n_f, int levels, int fmt);
 hipError_t launch_mfma2(const MfmaLaunch& a, hipStream_t st);

@@ -96,7 +96,10 @@ def call2(V=FAKE, dt=0, n_f=10, n_v=5, ld=10, s=None, c2=FAKE, n2=None, ws=FAKE,
     (dict(o=opts(path=3, levels=3)), UNSUP),           # fp4 MFMA needs uint8 data
     (dict(dt=2, n_f=6_000_000, ld=6_000_000, o=opts(path=3, levels=3)), ARG),  # > 2^24
     # int8 MFMA: 256 plane rows of 3 x 3M bytes exceed 32-bit tile offsets
-    (dict(dt=2, n_f=3_000_000, ld=3_000_000, o=opts(path=2, levels=3)), UNSUP),
+    # int8 planes (levels * n_f >= 2^24): 256 plane rows past 2^31 bytes
+    (dict(dt=2, n_f=3_000_000, ld=3_000_000, o=opts(path=2, levels=15)), UNSUP),
+    # fused int8 (levels * n_f < 2^24): 256 rows of V past 2^31 bytes
+    (dict(dt=2, n_f=1000, ld=9_000_000, o=opts(path=2, levels=3)), UNSUP),
     (dict(o=opts(path=4)), UNSUP),                     # bits need uint8 data
     (dict(dt=2, o=opts(path=4, levels=0)), ARG),       # bits need levels = 1
     (dict(dt=2, o=opts(path=4, levels=2)), ARG),
@@ -161,7 +164,10 @@ def call3(V=FAKE, dt=0, n_f=10, n_v=6, ld=10, s=None, n2=None, jb=1, je=5, c3=FA
     (dict(dt=2, o=opts(path=4, levels=3)), ARG),
     (dict(dt=2, o=opts(path=2, levels=0)), ARG),       # MFMA needs levels
     (dict(dt=2, n_f=6_000_000, ld=6_000_000, o=opts(path=3, levels=3)), ARG),  # > 2^24
-    (dict(dt=2, n_f=3_000_000, ld=3_000_000, o=opts(path=2, levels=3)), UNSUP),
+    # int8 planes (levels * n_f >= 2^24): 256 plane rows past 2^31 bytes
+    (dict(dt=2, n_f=3_000_000, ld=3_000_000, o=opts(path=2, levels=15)), UNSUP),
+    # fused int8 (levels * n_f < 2^24): 256 rows of V past 2^31 bytes
+    (dict(dt=2, n_f=1000, ld=9_000_000, o=opts(path=2, levels=3)), UNSUP),
 ])
 def test_ps3_argument_errors(kw, status):
     assert call3(**kw) == status
@@ -224,11 +230,21 @@ def test_workspace_sizes():
     # bits: the packed matrix, 32 fields per word in whole 16-byte chunks
     words = math.ceil(math.ceil(9000 / 32) / 4) * 4
     assert f(2, 9000, 1000, 1, opts(path=4, levels=1)) == math.ceil(1000 * words * 4 / 256) * 256
-    # auto with levels 1..15: int8 MFMA planes (3 levels x 1024 padded fields per
-    # vector), unless 256 plane rows would exceed 32-bit offsets (then VALU)
-    assert f(2, 1000, 1000, 1, opts(levels=3)) == math.ceil(1000 * 3 * 1024 / 256) * 256
-    assert f(2, 3_000_000, 1000, 1, opts(levels=3)) == f(2, 3_000_000, 1000, 1,
-                                                         opts(path=1, levels=3)) == 0
+    # auto with levels 1..15: the int8 MFMA path thresholds V's bytes in
+    # registers, no plane workspace; the 4x4 wave layout (tile 2) and fp4 read
+    # planes (3 levels x 1024 padded fields per vector, 2 fields per byte for fp4)
+    assert f(2, 1000, 1000, 1, opts(levels=3)) == 0
+    assert f(2, 1000, 1000, 1, opts(path=2, levels=3, tile=2)) == \
+        math.ceil(1000 * 3 * 1024 / 256) * 256
+    assert f(2, 1000, 1000, 1, opts(path=3, levels=3)) == \
+        math.ceil(1000 * 3 * 1024 / 2 / 256) * 256
+    # more than 7 levels with levels * n_f >= 2^24: int8 planes, unless 256
+    # plane rows exceed 32-bit offsets (then AUTO takes the VALU path)
+    assert f(2, 6_000_000, 100, 1, opts(path=2, levels=9)) == \
+        100 * 9 * math.ceil(6_000_000 / 128) * 128
+    assert f(2, 6_000_000, 100, 1, opts(path=2, levels=7)) == 0   # counts up to 2^31
+    assert f(2, 3_000_000, 1000, 1, opts(levels=15)) == f(2, 3_000_000, 1000, 1,
+                                                          opts(path=1, levels=3)) == 0
 
 
 @pytest.mark.parametrize("n_v", [3, 4, 7, 20])

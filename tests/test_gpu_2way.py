@@ -253,20 +253,36 @@ def test_mfma_auto_path_and_unaligned_rows():
     check_exact_f32(host(c2), oracle.c2_all(V), "c2")
 
 
-def test_mfma_plane_rows_beyond_32bit_tile_offsets():
-    """levels * n_f too large for 32-bit offsets over 256 plane rows: an
-    explicit MFMA path is refused (PS_ERR_UNSUPPORTED) and AUTO takes the
-    VALU path, still exact."""
+def test_mfma_rows_beyond_32bit_tile_offsets():
+    """Rows too long for 32-bit offsets over a 256-row tile: an explicit MFMA
+    path is refused (PS_ERR_UNSUPPORTED) and AUTO takes the VALU path, still
+    exact.  The int8 path that thresholds V in registers is bound by the row
+    stride of V (256 ld < 2^31); with levels * n_f >= 2^24 it reads planes,
+    bound by the plane-row length (256 levels kpad < 2^31)."""
+    import torch
     from paper_1705_08210_amd import ps
-    n_f = 2_900_000                       # 3 levels: 8.7e6 plane bytes per row
+    n_f = 2_900_000
     V = workloads.levels(3, n_f, seed=43)
-    announce(f"2-way mfma limit n_f={n_f}")
     Vd = to_dev(V)
+    ref = oracle.c2_all(V)
+    announce(f"2-way mfma n_f={n_f} in registers")
+    c2, _ = ps.ps2(Vd, path="mfma", levels=3)     # 3 n_f < 2^24, stride 2.9e6 fits
+    check_exact_f32(host(c2), ref, "c2 int8 in registers")
+    announce(f"2-way mfma planes limit n_f={n_f} levels=15")
     with pytest.raises(ps.PSError) as e:
-        ps.ps2(Vd, path="mfma", levels=3)
+        ps.ps2(Vd, path="mfma", levels=15)          # planes: 4.4e7 bytes per row
     assert e.value.status == 5
-    c2, _ = ps.ps2(Vd, levels=3)
-    check_exact_f32(host(c2), oracle.c2_all(V), "c2")
+    c2, _ = ps.ps2(Vd, levels=15)
+    check_exact_f32(host(c2), ref, "c2 auto levels=15")
+    announce("2-way mfma stride limit ld=9e6")
+    big = torch.zeros((3, 9_000_000), dtype=torch.uint8, device=Vd.device)
+    big[:, :1000] = Vd[:, :1000]
+    view = big[:, :1000]                            # n_f = 1000, ld = 9e6
+    with pytest.raises(ps.PSError) as e:
+        ps.ps2(view, path="mfma", levels=3)
+    assert e.value.status == 5
+    c2, _ = ps.ps2(view, levels=3)
+    check_exact_f32(host(c2), oracle.c2_all(np.ascontiguousarray(V[:, :1000])), "c2 auto ld")
 
 
 # ------------------------------------------ blocked (field-chunk) split ----
