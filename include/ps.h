@@ -95,17 +95,24 @@ typedef enum {
 
 /* Compute path for the pair numerators. */
 typedef enum {
-    PS_PATH_AUTO = 0,    /* U8 with 1 <= levels <= 15 and plane rows within the
-                            MFMA limit below: MFMA; otherwise VALU */
+    PS_PATH_AUTO = 0,    /* U8 with 1 <= levels <= 15 and rows within the MFMA
+                            limits below: MFMA; otherwise VALU */
     PS_PATH_VALU = 1,    /* register-blocked min/add on the vector ALUs */
     PS_PATH_MFMA = 2,    /* alias PS_PATH_MFMA_THERMO.  U8 only:
-                            min(a,b) = sum_{t=1..levels} [a>=t][b>=t], an exact int8 matrix-core contraction with int32
-                            accumulation; needs levels >= max(V).  Both MFMA
-                            paths address 256 plane rows (levels x n_f rounded
-                            up to 128 fields, one byte per field for int8, half
-                            a byte for FP4) with 32-bit offsets: 256 rows must
-                            span < 2^31 bytes (int8: levels * n_f below about
-                            8.4e6), else PS_ERR_UNSUPPORTED */
+                            min(a,b) = sum_{t=1..levels} [a>=t][b>=t], an
+                            exact int8 matrix-core contraction with int32
+                            accumulation; needs levels >= max(V).  With the
+                            default wave layout (opts.tile != 2) the level
+                            planes are formed in registers from V's bytes (no
+                            plane workspace) when levels * n_f < 2^31 for
+                            levels <= 7, < 2^24 for more levels; a tile of 256
+                            rows of V is addressed with 32-bit offsets, so
+                            256 * ld + 256 < 2^31 bytes.  Otherwise the
+                            planes are written to the workspace first (levels
+                            x n_f rounded up to 128 fields per row, one byte
+                            per value for int8, half a byte for FP4) and 256
+                            plane rows must span < 2^31 bytes.  Beyond these
+                            limits: PS_ERR_UNSUPPORTED */
     PS_PATH_MFMA_FP4 = 3, /* U8 only: the same 0/1 planes as FP4 (e2m1) operands
                             of the scaled matrix-core instruction, FP32
                             accumulation (exact: sums are integers < 2^24,
@@ -272,6 +279,19 @@ ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs,
                                  int32_t n, int32_t dtype, const ps_opts* opts,
                                  void* workspace, size_t ws_bytes,
                                  hipStream_t stream);
+/* A captured 3-way stage: the whole launch sequence of ps3_compute for these
+ * arguments (sums and pair numerators when not given, slab prefixes, the
+ * slices over [j_begin, j_end), Eq. 1) in a HIP graph, for campaigns that
+ * replay a stage shape many times (Section 4.2 staging; Section 3.2 slices).
+ * Arguments as for ps3_compute; they are checked while capturing and every
+ * pointer is baked into the graph, so V, s, n2, c3 and the workspace must
+ * stay valid (their contents may change between replays) until
+ * ps_plan_destroy.  Nothing is launched at creation.  Errors: those of
+ * ps3_compute, or PS_ERR_HIP when capture fails. */
+ps_status ps_plan_create_3way(ps_plan** plan, const void* V, int32_t dtype, int64_t n_f,
+                              int64_t n_v, int64_t ld, const double* s, const void* n2,
+                              int64_t j_begin, int64_t j_end, float* c3,
+                              void* workspace, size_t ws_bytes, const ps_opts* opts);
 /* Replays the captured graph on `stream`. */
 ps_status ps_plan_execute(ps_plan* plan, hipStream_t stream);
 void ps_plan_destroy(ps_plan* plan);

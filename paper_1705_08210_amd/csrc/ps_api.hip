@@ -840,6 +840,22 @@ ps_status ps_plan_create_batched(ps_plan** plan, const ps_problem* probs, int32_
     });
 }
 
+ps_status ps_plan_create_3way(ps_plan** plan, const void* V, int32_t dtype, int64_t n_f,
+                              int64_t n_v, int64_t ld, const double* s, const void* n2,
+                              int64_t j_begin, int64_t j_end, float* c3, void* ws,
+                              size_t ws_bytes, const ps_opts* opts) {
+    if (!plan) return fail(PS_ERR_ARG, "plan is NULL");
+    *plan = nullptr;
+    // the options are read now: the captured launches keep their values
+    ps_opts o{};
+    if (opts) o = *opts;
+    const ps_opts* op = opts ? &o : nullptr;
+    return capture_plan(plan, [&](hipStream_t cs) {
+        return ps3_run(V, dtype, n_f, n_v, ld, s, n2, j_begin, j_end, c3, ws, ws_bytes, false,
+                       op, cs);
+    });
+}
+
 ps_status ps_plan_execute(ps_plan* plan, hipStream_t stream) {
     if (!plan || !plan->exec) return fail(PS_ERR_ARG, "plan is NULL or empty");
     hipError_t e = hipGraphLaunch(plan->exec, stream);

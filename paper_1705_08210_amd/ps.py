@@ -73,6 +73,8 @@ _sig("ps2_compute_batched", ctypes.c_int,
      [ctypes.POINTER(Problem), I32, I32, P, SZ, ctypes.POINTER(Opts), P])
 _sig("ps_plan_create_batched", ctypes.c_int,
      [ctypes.POINTER(P), ctypes.POINTER(Problem), I32, I32, ctypes.POINTER(Opts), P, SZ, P])
+_sig("ps_plan_create_3way", ctypes.c_int,
+     [ctypes.POINTER(P), P, I32, I64, I64, I64, P, P, I64, I64, P, P, SZ, ctypes.POINTER(Opts)])
 _sig("ps_plan_execute", ctypes.c_int, [P, P])
 _sig("ps_plan_destroy", None, [P])
 _sig("ps_tile_config", I32, [I32, I32, I32, I32, ctypes.POINTER(I32),
@@ -308,6 +310,50 @@ class BatchedPlan:
             self.ws.record_stream(s)
         _check(lib.ps_plan_execute(self._h, s.cuda_stream))
         return self.outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.ps_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan3:
+    """A 3-way stage captured into a HIP graph (ps_plan_create_3way); run()
+    replays it.  V, s, n2 and c3 are kept alive by the plan; their contents
+    may change between replays."""
+
+    def __init__(self, V, s=None, n2=None, j_begin: int = 1, j_end: int | None = None,
+                 acc="auto", tile=0, path="auto", levels=0, c3=None):
+        dt, n_f, n_v, ld = _matrix(V)
+        if j_end is None:
+            j_end = max(n_v - 1, j_begin)
+        m = stage_size(n_v, j_begin, j_end)
+        self.V, self.s, self.n2 = V, s, n2
+        self.c3 = c3 if c3 is not None else torch.empty(m, dtype=torch.float32, device=V.device)
+        o = _opts(acc, path, levels, tile)
+        ws_n = lib.ps3_workspace_size(dt, n_f, n_v, int(s is not None), int(n2 is not None),
+                                      j_begin, j_end, ctypes.byref(o))
+        self.ws = _workspace(ws_n, V.device)
+        self._home = torch.cuda.current_stream(V.device)
+        h = P()
+        _check(lib.ps_plan_create_3way(ctypes.byref(h), V.data_ptr(), dt, n_f, n_v, ld, _ptr(s),
+                                       _ptr(n2), j_begin, j_end,
+                                       self.c3.data_ptr() if m > 0 else None,
+                                       self.ws.data_ptr(), self.ws.numel(), ctypes.byref(o)))
+        self._h = h
+
+    def run(self, stream=None):
+        s = torch.cuda.current_stream() if stream is None else stream
+        if s != self._home:
+            self.ws.record_stream(s)
+        _check(lib.ps_plan_execute(self._h, s.cuda_stream))
+        return self.c3
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

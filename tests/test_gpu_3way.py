@@ -282,3 +282,41 @@ def test_mfma_whole_and_edge_tiles(path, n_v):
     assert np.array_equal(np.concatenate(parts).view(np.uint32), got.view(np.uint32))
     i, j, k = sample_triples(n_v, 2048, seed=n_v + 8)
     check_exact_f32(got[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), "c3")
+
+
+@pytest.mark.parametrize("kind", ["f32", "u8_mfma", "f32_stage_given"])
+def test_3way_plan_replays_match_eager(kind):
+    """A 3-way stage captured into a HIP graph (ps_plan_create_3way) replays
+    the eager result bit for bit, three times, with other eager work and
+    synchronisations between the replays."""
+    import torch
+    from paper_1705_08210_amd import ps
+    n_v = 300
+    if kind == "u8_mfma":
+        V = workloads.levels(n_v, 1500, seed=82)
+        kw = dict(path="mfma", levels=3)
+    else:
+        V = workloads.sparse_uniform(n_v, 1500, seed=81)
+        kw = {}
+    Vd = to_dev(V)
+    jb, je = (50, 220) if kind == "f32_stage_given" else (1, n_v - 1)
+    s = n2 = None
+    if kind == "f32_stage_given":
+        s, _ = ps.vector_sums(Vd)
+        _, n2 = ps.ps2(Vd, s=s, want_c2=False, want_n2=True)
+    announce(f"3-way plan {kind}")
+    eager = host(ps.ps3(Vd, s=s, n2=n2, j_begin=jb, j_end=je, **kw))
+    plan = ps.Plan3(Vd, s=s, n2=n2, j_begin=jb, j_end=je, **kw)
+    for rep in range(3):
+        plan.c3.fill_(float("nan"))
+        ps.ps2(Vd)                     # other eager work between replays
+        torch.cuda.synchronize()
+        got = host(plan.run())
+        assert np.array_equal(got.view(np.uint32), eager.view(np.uint32)), rep
+    plan.close()
+    lo = ps.stage_size(n_v, 1, jb)
+    ref = oracle.c3_all(V)[lo:lo + eager.size]
+    if kind == "u8_mfma":
+        check_exact_f32(eager, ref, "c3")
+    else:
+        check_rel(eager, ref, FP32_TOL, "c3")
