@@ -343,6 +343,52 @@ hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Exclusive prefix of the column-tile counts of the flattened row tiles
+// (one workgroup; 1024 threads each own a contiguous run of row tiles).
+__global__ __launch_bounds__(1024) void ps_prefix3_flat_kernel(int64_t n_v, int64_t jb,
+                                                               int64_t je, int bm,
+                                                               int64_t* prefix) {
+    __shared__ int64_t part[1024];
+    const int64_t nr = flat_row_tiles(jb, je, bm);
+    const int64_t per = (nr + 1023) / 1024;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    const int64_t hi = lo + per < nr ? lo + per : nr;
+    int64_t sum = 0;
+    for (int64_t t = lo; t < hi; ++t) sum += flat_col_tiles(n_v, jb, bm, t);
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t t = lo; t < hi; ++t) {
+        prefix[t] = run;
+        run += flat_col_tiles(n_v, jb, bm, t);
+    }
+    if (hi == nr && lo < hi) prefix[nr] = run;
+    if (nr == 0 && threadIdx.x == 0) prefix[0] = 0;
+}
+
+hipError_t launch_prefix3_flat(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(ps_prefix3_flat_kernel, dim3(1), dim3(1024), 0, st, n_v, jb, je, bm,
+                       prefix);
+    return hipGetLastError();
+}
+
+int64_t flat_tiles(int64_t n_v, int64_t jb, int64_t je, int bm) {
+    int64_t t = 0;
+    const int64_t nr = flat_row_tiles(jb, je, bm);
+    for (int64_t rt = 0; rt < nr; ++rt) t += flat_col_tiles(n_v, jb, bm, rt);
+    return t;
+}
+
 hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob,
                           int64_t* prefix, hipStream_t st) {
     hipLaunchKernelGGL(ps_prefix3_kernel, dim3(1), dim3(1024), 0, st, n_v, jb, je, bm, mode, ob,
@@ -352,6 +398,7 @@ hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode,
 
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
     const int bm = kValuCfgs[a.cfg].bm();
+    if (a.mode == kSlabFlat) return launch_prefix3_flat(a.n_v, a.j_begin, a.j_end, bm, a.prefix, st);
     hipError_t e = launch_prefix3(a.n_v, a.j_begin, a.j_end, bm, a.mode, bm, a.prefix, st);
     if (e != hipSuccess || a.mode != kSlabFull) return e;
     return launch_prefix3(a.n_v, a.j_begin, a.j_end, kValuCfgs[a.edge_cfg].bm(), kSlabEdge, bm,

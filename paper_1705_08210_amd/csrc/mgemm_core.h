@@ -195,6 +195,27 @@ struct Stager {
         }
     }
 
+    // Rows given per chunk (the flattened 3-way rows): roff[c] is the byte
+    // offset of chunk c's row (< 0: no row, zero fill) and, with XJ, xoff[c]
+    // the offset of the row v_j it is min-ed with.
+    template <int DT, bool XJ>
+    __device__ __forceinline__ void load_rows(const char* Vb, const int64_t (&roff)[kCh],
+                                              const int64_t (&xoff)[kCh], int64_t kb0,
+                                              int64_t nbytes, bool vec) {
+        constexpr int ESZ = Ops<DT>::kEsz;
+#pragma unroll
+        for (int c = 0; c < kCh; ++c) {
+            const int ch = (threadIdx.x + c * kThreads) / BM;
+            const int64_t b0 = kb0 + ch * 16;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (roff[c] >= 0) {
+                v = load_chunk<ESZ>(Vb + roff[c], b0, nbytes, vec);
+                if (XJ) v = xmin_chunk<DT>(v, load_chunk<ESZ>(Vb + xoff[c], b0, nbytes, vec));
+            }
+            r[c] = v;
+        }
+    }
+
     __device__ __forceinline__ void store(Word* S) const {
 #pragma unroll
         for (int c = 0; c < kCh; ++c) {
@@ -287,6 +308,72 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
             sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
             sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
         }
+        if (!active) continue;
+        constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
+#pragma unroll kUnroll
+        for (int w = 0; w < BKW; ++w) {
+            Word a[TM], b[TN];
+#pragma unroll
+            for (int g = 0; g < TM / 4; ++g)
+#pragma unroll
+                for (int h = 0; h < kV; ++h)
+                    ((uint4*)&a[4 * g])[h] = ((const uint4*)&As[w * SA::kLd + ar + g * 32])[h];
+#pragma unroll
+            for (int g = 0; g < TN / 4; ++g)
+#pragma unroll
+                for (int h = 0; h < kV; ++h)
+                    ((uint4*)&b[4 * g])[h] = ((const uint4*)&Bs[w * SB::kLd + bc + g * 32])[h];
+#pragma unroll
+            for (int r = 0; r < TM; ++r)
+#pragma unroll
+                for (int c = 0; c < TN; ++c)
+                    acc[r][c] = Ops<DT>::step(acc[r][c], a[r], b[c]);
+        }
+    }
+}
+
+// run_tile for the flattened 3-way slices: the A rows are given per staged
+// chunk (aoff / xoff as in Stager::load_rows; X_j formed per row), the B rows
+// are [b_row0, b_row0 + BN) valid below b_end.  Each field tile is loaded
+// just before it is staged (the X_j rows add loads; the other resident
+// workgroups cover the latency).
+template <int DT, int TM, int TN, int BKW>
+__device__ __forceinline__ void run_tile_flat(
+    const char* Vb, int64_t ldb, int64_t nbytes, bool vec,
+    const int64_t (&aoff)[Stager<16 * TM, BKW, typename Ops<DT>::Word>::kCh],
+    const int64_t (&xoff)[Stager<16 * TM, BKW, typename Ops<DT>::Word>::kCh], int64_t b_row0,
+    int64_t b_end, bool active, typename Ops<DT>::Word* As, typename Ops<DT>::Word* Bs,
+    typename Ops<DT>::Acc (&acc)[TM][TN], int64_t kt0 = 0, int64_t kt1 = -1) {
+    using Acc = typename Ops<DT>::Acc;
+    using Word = typename Ops<DT>::Word;
+    constexpr int BM = 16 * TM, BN = 16 * TN;
+    using SA = Stager<BM, BKW, Word>;
+    using SB = Stager<BN, BKW, Word>;
+    constexpr int kV = (int)sizeof(Word) / 4;
+    const int wave = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int lx = lane % 8, ly = lane / 8;
+    const int ar = (wave & 1) * (8 * TM) + lx * 4;
+    const int bc = (wave >> 1) * (8 * TN) + ly * 4;
+
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int c = 0; c < TN; ++c) acc[r][c] = Acc(0);
+
+    const int64_t tile_bytes = (int64_t)BKW * (int64_t)sizeof(Word);
+    const int64_t nk_all = (nbytes + tile_bytes - 1) / tile_bytes;
+    const int64_t nk = kt1 < 0 || kt1 > nk_all ? nk_all : kt1;
+    SA sa;
+    SB sb;
+    for (int64_t kt = kt0; kt < nk; ++kt) {
+        const int64_t kb = kt * tile_bytes;
+        sa.template load_rows<DT, true>(Vb, aoff, xoff, kb, nbytes, vec);
+        sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
+        __syncthreads();  // previous tile's LDS reads are done
+        sa.store(As);
+        sb.store(Bs);
+        __syncthreads();
         if (!active) continue;
         constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
 #pragma unroll kUnroll

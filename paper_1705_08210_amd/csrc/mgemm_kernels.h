@@ -154,6 +154,92 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launc
     }
 }
 
+// 3-way over the flattened rows (kSlabFlat): one workgroup per (row tile of
+// BM consecutive pairs (i, j) in colex order, column tile of BM k's from the
+// row tile's first j + 1), field chunk.  The A operand row of pair (i, j) is
+// X_j's column i, min(v_i, v_j), formed while staging; entries with k <= j
+// are computed by waves that also hold wanted ones and never stored.
+template <int DT, int TM>
+__device__ __forceinline__ void store_slice_flat(const typename Ops<DT>::Acc (&acc)[TM][TM],
+                                                 int64_t p0, int64_t pend, int64_t col0,
+                                                 const Mg3Launch& a, uint32_t* out) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lx = lane % 8, ly = lane / 8;
+    const int64_t obase = slab_offset(a.n_v, a.j_begin);
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+        const int64_t p = p0 + lane_row<TM>(wave, lx, r);
+        if (p >= pend) continue;
+        const int64_t j = pair_j(p);
+        const int64_t i = p - j * (j - 1) / 2;
+        // index of (i, j, k) = off(j) - off(jb) + (k - j - 1) j + i
+        const int64_t base = slab_offset(a.n_v, j) - obase - (j + 1) * j + i;
+#pragma unroll
+        for (int c = 0; c < TM; ++c) {
+            const int64_t k = col0 + lane_col<TM>(wave, ly, c);
+            if (k >= a.n_v || k <= j) continue;
+            if constexpr (DT == PS_F64)
+                ((double*)out)[base + k * j] = acc[r][c];
+            else
+                out[base + k * j] = __builtin_bit_cast(uint32_t, acc[r][c]);
+        }
+    }
+}
+
+template <int DT, int TM, int BKW>
+__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3f_kernel(Mg3Launch a,
+                                                                       int64_t item0) {
+    using Acc = typename Ops<DT>::Acc;
+    constexpr int BM = 16 * TM;
+    using Word = typename Ops<DT>::Word;
+    using SA = Stager<BM, BKW, Word>;
+    __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
+    __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
+    const int64_t w = item0 + xcd_remap(blockIdx.x, gridDim.x);
+    if (w >= a.ntiles * a.nchunks) return;
+    const int64_t chunk = w / a.ntiles, t = w % a.ntiles;
+    // row tile: largest rt with prefix[rt] <= t
+    int64_t lo = 0, hi = flat_row_tiles(a.j_begin, a.j_end, BM);
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (a.prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int64_t pb = a.j_begin * (a.j_begin - 1) / 2;
+    const int64_t pend = a.j_end * (a.j_end - 1) / 2;
+    const int64_t p0 = pb + lo * BM;
+    const int64_t col0 = pair_j(p0) + 1 + (t - a.prefix[lo]) * BM;
+    const int wave = threadIdx.x / 64;
+    // this wave's quadrant: pairs from pq, columns [cq, cq + 8 TM); it holds a
+    // wanted entry iff its smallest j is below its largest k
+    const int64_t pq = p0 + (wave & 1) * 8 * TM;
+    const int64_t cq = col0 + (wave >> 1) * 8 * TM;
+    const int64_t kq = cq + 8 * TM - 1 < a.n_v - 1 ? cq + 8 * TM - 1 : a.n_v - 1;
+    const bool active = pq < pend && cq < a.n_v && pair_j(pq) < kq;
+    const int64_t ldb = a.ld * Ops<DT>::kEsz;
+    const int64_t nbytes = a.n_f * Ops<DT>::kEsz;
+    int64_t aoff[SA::kCh], xoff[SA::kCh];
+#pragma unroll
+    for (int c = 0; c < SA::kCh; ++c) {
+        const int64_t p = p0 + (threadIdx.x + c * kThreads) % BM;
+        const int64_t j = p < pend ? pair_j(p) : 0;
+        aoff[c] = p < pend ? (p - j * (j - 1) / 2) * ldb : -1;
+        xoff[c] = j * ldb;
+    }
+    Acc acc[TM][TM];
+    const int64_t kt0 = a.nchunks > 1 ? chunk * a.chunk_tiles : 0;
+    const int64_t kt1 = a.nchunks > 1 ? kt0 + a.chunk_tiles : -1;
+    run_tile_flat<DT, TM, TM, BKW>((const char*)a.V, ldb, nbytes, rows_vec_ok<DT>(a.V, a.ld),
+                                   aoff, xoff, col0, a.n_v, active, As, Bs, acc, kt0, kt1);
+    if (active) {
+        uint32_t* dst = DT == PS_F64 ? (uint32_t*)a.partial   // stage doubles, never split
+                        : a.nchunks > 1
+                            ? (uint32_t*)a.partial +
+                                  chunk * (slab_offset(a.n_v, a.j_end) - slab_offset(a.n_v, a.j_begin))
+                            : (uint32_t*)a.c3;
+        store_slice_flat<DT, TM>(acc, p0, pend, col0, a, dst);
+    }
+}
+
 // 3-way, second half of the epilogue (Eq. 1, Section 2.2): one workgroup per
 // slice j; the triples of the slice are contiguous in the j-slab layout, with
 // i fastest.  n3 = ((n2(i,j) + n2(i,k)) + n2(j,k)) - n3', d3 = (s_i + s_j) + s_k,
@@ -312,8 +398,12 @@ template <int DT, int TM, int BKW>
 hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
     return launch_items(a.ntiles * a.nchunks, kThreads, kXcds, [&](unsigned grid, int64_t item0) {
-        hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,
-                           item0);
+        if (a.mode == kSlabFlat)
+            hipLaunchKernelGGL((ps_mg3f_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st,
+                               a, item0);
+        else
+            hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st,
+                               a, item0);
     });
 }
 

@@ -297,9 +297,17 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
 
 // The field-split partials of the pair prepass and of the slices run one
 // after the other on the stream and share one region.
-static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int n2_bytes,
-                         int32_t nchunks2, int32_t nchunks3, int64_t stage, size_t packed_bytes,
-                         void* ws,
+// Prefix entries of a 3-way stage [jb, je): two slab prefixes of n_v + 1
+// (whole and edge tiles of the matrix-core slices, the finish's ranges), or
+// the flattened row tiles of the VALU slices at the smallest tile edge (64).
+static int64_t prefix3_entries(int64_t n_v, int64_t jb, int64_t je) {
+    const int64_t flat = flat_row_tiles(jb, je, 64) + 1;
+    return 2 * (n_v + 1) > flat ? 2 * (n_v + 1) : flat;
+}
+
+static size_t ws3_layout(int64_t n_v, int64_t npre, int32_t s_given, int32_t n2_given,
+                         int n2_bytes, int32_t nchunks2, int32_t nchunks3, int64_t stage,
+                         size_t packed_bytes, void* ws,
                          double** s_ws, void** n2_ws, int64_t** prefix, float** partial,
                          uint32_t** packed) {
     Carver c(ws);
@@ -310,8 +318,7 @@ static size_t ws3_layout(int64_t n_v, int32_t s_given, int32_t n2_given, int n2_
     else if (packed_bytes) c.take(packed_bytes);
     if (!s_given) s = (double*)c.take((size_t)n_v * sizeof(double));
     if (!n2_given) n2 = c.take((size_t)(n_v * (n_v - 1) / 2) * (size_t)n2_bytes);
-    // two slab prefixes of n_v + 1 entries: the launch's tiles, then its edge tiles
-    int64_t* pre = (int64_t*)c.take((size_t)2 * (n_v + 1) * sizeof(int64_t));
+    int64_t* pre = (int64_t*)c.take((size_t)npre * sizeof(int64_t));
     const int64_t need2 = (!n2_given && nchunks2 > 1) ? nchunks2 * (n_v * (n_v - 1) / 2) : 0;
     // floats of the slice sums: FP32 chunk partials, or (nchunks3 < 0) FP64 raw sums
     const int64_t need3 = nchunks3 < 0 ? 2 * stage : nchunks3 > 1 ? nchunks3 * stage : 0;
@@ -338,7 +345,8 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
     int64_t* prefix = nullptr;
     float* partial = nullptr;
     uint32_t* planes = nullptr;
-    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, 4, 1, 1, stage,
+    const size_t need = ws3_layout(n_v, prefix3_entries(n_v, j_begin, j_end), s != nullptr,
+                                   n2 != nullptr, 4, 1, 1, stage,
                                    mfma_workspace_bytes(n_f, n_v, levels, fmt, 0), workspace,
                                    &s_ws, &n2_ws, &prefix, &partial, &planes);
     if (ws_bytes < need || !workspace)
@@ -377,18 +385,19 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (j_begin < 1) j_begin = 1;
     if (j_end > n_v - 1) j_end = n_v - 1;
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
+    const int64_t npre = prefix3_entries(n_v, j_begin, j_end);
     if (is_bits(opts))
-        return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage, bits_bytes(n_f, n_v), nullptr,
-                          nullptr, nullptr, nullptr, nullptr, nullptr);
+        return ws3_layout(n_v, npre, s_given, n2_given, 4, 1, 1, stage, bits_bytes(n_f, n_v),
+                          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     const int path = choose_path(dtype, opts, n_f, n_f);
     if (is_mfma(path) && dtype == PS_U8)
-        return ws3_layout(n_v, s_given, n2_given, 4, 1, 1, stage,
+        return ws3_layout(n_v, npre, s_given, n2_given, 4, 1, 1, stage,
                           mfma_workspace_bytes(n_f, n_v, opts ? opts->levels : 0,
                                                path == PS_PATH_MFMA_FP4 ? 1 : 0, 0),
                           nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     const Split sp2 =
         plan_split(dtype, n_f, n_v, choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts), opts);
-    return ws3_layout(n_v, s_given, n2_given, dtype == PS_F64 ? 8 : 4, sp2.nchunks,
+    return ws3_layout(n_v, npre, s_given, n2_given, dtype == PS_F64 ? 8 : 4, sp2.nchunks,
                       dtype == PS_F64 ? -1 : split_chunks(dtype, n_f, choose_acc(n_f, opts)),
                       stage, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
@@ -518,7 +527,8 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     const int32_t nchunks = bits ? 1 : split_chunks(dtype, n_f, choose_acc(n_f, opts));
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
     uint32_t* packed = nullptr;
-    const size_t need = ws3_layout(n_v, s != nullptr, n2 != nullptr, dtype == PS_F64 ? 8 : 4,
+    const size_t need = ws3_layout(n_v, prefix3_entries(n_v, j_begin, j_end), s != nullptr,
+                                   n2 != nullptr, dtype == PS_F64 ? 8 : 4,
                                    sp2.nchunks, dtype == PS_F64 ? -1 : nchunks, stage,
                                    bits ? bits_bytes(n_f, n_v) : 0, workspace, &s_ws, &n2_ws,
                                    &prefix, &partial, &packed);
@@ -550,14 +560,10 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     }
     const int cfg = choose_cfg(kdt, 3, bits ? PS_PATH_BITS : PS_PATH_VALU, n_f, n_v, opts);
     const int bm = kValuCfgs[cfg].bm();
-    const int ecfg = edge_cfg3(cfg, opts);   // >= 0: whole tiles, then the edges in ecfg tiles
-    const int mode = ecfg >= 0 ? kSlabFull : kSlabAll;
+    // one launch over the flattened (pair, k) tiles of the stage
     Mg3Launch a{KV, kn_f, n_v, kld, s, n2, j_begin, j_end, c3, prefix,
-                slab_tiles(n_v, j_begin, j_end, bm, mode, bm), cfg, nchunks,
-                bits ? 0 : chunk_tiles(dtype, cfg), partial, mode, bm, ecfg, prefix + (n_v + 1),
-                ecfg >= 0 ? slab_tiles(n_v, j_begin, j_end, kValuCfgs[ecfg].bm(), kSlabEdge, bm)
-                          : 0,
-                ecfg >= 0 && !bits ? chunk_tiles(dtype, ecfg) : 0};
+                flat_tiles(n_v, j_begin, j_end, bm), cfg, nchunks,
+                bits ? 0 : chunk_tiles(dtype, cfg), partial, kSlabFlat, bm, -1, nullptr, 0, 0};
     e = launch_mg3_prefix(a, stream);
     if (e == hipSuccess) e = launch_mg3(kdt, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");

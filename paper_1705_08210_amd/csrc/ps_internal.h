@@ -75,7 +75,34 @@ __host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
 // rectangle exactly once, with edge waste at the bm granularity only.
 // kSlabRange counts ranges of bm consecutive outputs of the slab instead
 // (the elementwise 3-way finish).
-enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2, kSlabRange = 3 };
+// kSlabFlat (the VALU slices) does not tile slab by slab: see flat_* below.
+enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2, kSlabRange = 3, kSlabFlat = 4 };
+
+// Pair (i, j), i < j, has colex index p = j (j - 1) / 2 + i.  pair_j(p) is
+// its j: the largest j with j (j - 1) / 2 <= p.
+__host__ __device__ inline int64_t pair_j(int64_t p) {
+    int64_t j = (int64_t)((1.0 + __builtin_sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+    while (j > 1 && j * (j - 1) / 2 > p) --j;
+    while ((j + 1) * j / 2 <= p) ++j;
+    return j;
+}
+
+// Flattened 3-way tiling (kSlabFlat).  The rows of the slices of a stage
+// [jb, je) are the pairs (i, j), i < j, jb <= j < je, in colex order: slab
+// after slab, so a row tile of bm consecutive pairs spans one slab or a few.
+// Row tile rt (pairs P(jb) + rt bm .. + bm, P(j) = j (j - 1) / 2) is paired
+// with the column tiles k in [jmin + 1 + c bm, + bm), jmin = j of its first
+// pair, up to n_v.  Entries with k <= j are not stored; every triple of the
+// stage lies in exactly one tile.
+__host__ __device__ inline int64_t flat_row_tiles(int64_t jb, int64_t je, int bm) {
+    const int64_t rows = je * (je - 1) / 2 - jb * (jb - 1) / 2;
+    return rows > 0 ? (rows + bm - 1) / bm : 0;
+}
+__host__ __device__ inline int64_t flat_col_tiles(int64_t n_v, int64_t jb, int bm, int64_t rt) {
+    const int64_t jmin = pair_j(jb * (jb - 1) / 2 + rt * bm);
+    const int64_t w = n_v - 1 - jmin;
+    return w > 0 ? (w + bm - 1) / bm : 0;
+}
 
 __host__ __device__ inline int64_t slab_tile_count(int64_t n_v, int64_t j, int bm, int mode,
                                                    int ob) {
@@ -221,7 +248,8 @@ struct Mg3Launch {
     int32_t nchunks;             // field-chunk split as for Mg2Launch; partial
     int64_t chunk_tiles;         // holds nchunks * stage-size FP32 values (for
     float* partial;              // PS_F64: stage-size doubles of raw n3', no split)
-    int32_t mode;                // tile set of this launch (kSlabAll / kSlabFull / kSlabEdge)
+    int32_t mode;                // tile set of this launch (kSlabAll / kSlabFull / kSlabEdge,
+                                 // or kSlabFlat: prefix over flattened row tiles)
     int32_t ob;                  // kSlabEdge: edge of the whole tiles around which it runs
     // kSlabFull: a second launch covers the slab edges with configuration
     // edge_cfg (kSlabEdge around the cfg tiles); its slab prefix is edge_prefix
@@ -368,6 +396,12 @@ hipError_t launch_mfma3(const MfmaLaunch& a, hipStream_t st);
 // prefix[t] = tiles of slabs jb .. jb+t-1 in a tile set, t = 0 .. je - jb.
 hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob,
                           int64_t* prefix, hipStream_t st);
+// prefix[rt] = column tiles of the flattened row tiles 0 .. rt-1,
+// rt = 0 .. flat_row_tiles(jb, je, bm).
+hipError_t launch_prefix3_flat(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
+                               hipStream_t st);
+// Tiles of the flattened tiling (host loop over the row tiles).
+int64_t flat_tiles(int64_t n_v, int64_t jb, int64_t je, int bm);
 // Output reduction (reduce.hip).
 hipError_t launch_quantize_u8(const float* c, int64_t n, uint8_t* q, hipStream_t st);
 int64_t select_tiles(int64_t n);

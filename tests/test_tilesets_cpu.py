@@ -1,8 +1,9 @@
-"""Host logic of the 3-way work lists: the slab tile sets of the slice
-launches (whole tiles plus edge tiles, or every tile) cover each slab
-rectangle i < j < k exactly once, and the finish's output ranges cover each
-slab.  The check is a small host program compiled against the library's
-internal header (no GPU)."""
+"""Host logic of the 3-way work lists: the flattened (pair row, k column)
+tiles of the VALU slices cover every triple of a stage exactly once; the
+slab tile sets of the matrix-core slices (whole tiles plus edge tiles, or
+every tile) cover each slab rectangle i < j < k exactly once, and the
+finish's output ranges cover each slab.  The check is a small host program
+compiled against the library's internal header (no GPU)."""
 
 import os
 import shutil

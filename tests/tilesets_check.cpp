@@ -1,8 +1,10 @@
-// Host check of the 3-way slab tile sets (slab_tile_count / slab_tile_origin):
-// for every slab j of n_v in a range of sizes, the whole tiles plus the edge
-// tiles, and the single set of all tiles, cover the rectangle i < j < k
-// exactly once, with every tile origin inside it; the finish's output ranges
-// cover each slab exactly once.  Prints "ok" and exits 0 on success.
+// Host check of the 3-way tile sets: the flattened (pair row, k column) tiles
+// of the VALU slices cover every triple of a stage exactly once (pair_j
+// inverts the colex pair offset); for every slab j of n_v in a range of
+// sizes, the matrix-core slices' whole tiles plus edge tiles, and the single
+// set of all tiles, cover the rectangle i < j < k exactly once, with every
+// tile origin inside it; the finish's output ranges cover each slab exactly
+// once.  Prints "ok" and exits 0 on success.
 #include <cstdio>
 #include <vector>
 
@@ -27,8 +29,50 @@ static long cover(int64_t n, int64_t j, int mode, int bm, int ob, std::vector<in
     return bad;
 }
 
+// The flattened tiling of a stage [jb, je): every triple (i, j, k) with
+// jb <= j < je lies in exactly one (row tile, column tile), and no tile
+// reaches outside the stage's rows or past n_v.
+static long cover_flat(int64_t n, int64_t jb, int64_t je, int bm) {
+    const int64_t pb = jb * (jb - 1) / 2, pe = je * (je - 1) / 2;
+    std::vector<int> cov((size_t)((pe - pb) * n), 0);
+    long bad = 0;
+    const int64_t nr = flat_row_tiles(jb, je, bm);
+    if (nr * bm < pe - pb || (nr > 0 && (nr - 1) * bm >= pe - pb)) ++bad;
+    for (int64_t rt = 0; rt < nr; ++rt) {
+        const int64_t p0 = pb + rt * bm;
+        const int64_t jmin = pair_j(p0);
+        if (jmin < jb || jmin >= je) ++bad;
+        for (int64_t c = 0; c < flat_col_tiles(n, jb, bm, rt); ++c) {
+            const int64_t k0 = jmin + 1 + c * bm;
+            if (k0 >= n) ++bad;
+            for (int64_t p = p0; p < p0 + bm && p < pe; ++p) {
+                const int64_t j = pair_j(p), i = p - j * (j - 1) / 2;
+                if (i < 0 || i >= j) ++bad;
+                for (int64_t k = k0; k < k0 + bm && k < n; ++k)
+                    if (k > j) cov[(size_t)((p - pb) * n + k)]++;
+            }
+        }
+    }
+    for (int64_t p = pb; p < pe; ++p) {
+        const int64_t j = pair_j(p);
+        for (int64_t k = 0; k < n; ++k) bad += cov[(size_t)((p - pb) * n + k)] != (k > j ? 1 : 0);
+    }
+    return bad;
+}
+
 int main() {
     long bad = 0, slabs = 0;
+    for (int64_t p = 0; p < 2000000; p += 7) {   // pair_j inverts the colex offset
+        const int64_t j = pair_j(p);
+        bad += !(j * (j - 1) / 2 <= p && p < j * (j + 1) / 2);
+    }
+    for (int64_t n : {3, 4, 5, 17, 64, 65, 130, 257, 300})
+        for (int bm : {64, 128})
+            for (int64_t jb = 1; jb < n - 1; jb += (n > 100 ? 37 : 1))
+                for (int64_t je = jb; je <= n - 1; je += (n > 100 ? 53 : 1)) {
+                    bad += cover_flat(n, jb, je, bm);
+                    bad += cover_flat(n, jb, n - 1, bm);
+                }
     for (int64_t n = 3; n <= 700; n += (n < 300 ? 1 : 37)) {
         for (int64_t j = 1; j < n - 1; ++j) {
             const size_t m = (size_t)(j * (n - 1 - j));
