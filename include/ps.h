@@ -255,10 +255,11 @@ size_t ps2_batched_workspace_size(const ps_problem* probs, int32_t n,
 
 /*
  * Many independent uneven 2-way problems in one launch over a combined list
- * of (problem, tile, field chunk) work items ordered longest first (the
- * load-balancing idea of Section 4.1 applied to the tiles of one GPU); the
- * hardware hands items to free slots in list order, a greedy longest-first
- * schedule.  A finish pass forms every problem's c2 (and n2).  The problem
+ * of (problem, tile, field chunk) work items (the load-balancing idea of
+ * Section 4.1 applied to the tiles of one GPU): the (problem, field chunk)
+ * groups are packed onto the GPU's dies by cost and each die takes its list
+ * longest item first as slots free up.  A finish pass forms every problem's
+ * c2 (and n2).  The problem
  * table and the list's groups travel to the workspace as kernel arguments
  * and a kernel expands the list there, so the call returns without waiting
  * for anything and the host arrays may be freed at once.  All problems share

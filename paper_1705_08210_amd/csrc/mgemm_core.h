@@ -141,8 +141,8 @@ struct Stager {
     static_assert(BM * kCpr % kThreads == 0, "tile not divisible");
     uint4 r[kCh];
 
-    // Load one 16-byte chunk that may straddle the end of the fields, or sit
-    // on a row that is not 16-byte aligned, element by element (zero fill).
+    // Load the 16-byte chunk that straddles the end of the fields, element by
+    // element (zero fill past the end).
     template <int ESZ>
     __device__ __forceinline__ static uint4 load_slow(const char* p, int64_t nbytes_left) {
         union {
@@ -165,10 +165,24 @@ struct Stager {
         return u.v;
     }
 
+    // A whole 16-byte chunk of a row that is not 16-byte aligned: four
+    // 32-bit loads when 4-byte aligned (always for FP32), else element loads.
+    // (Two aligned 16-byte loads shifted into place measured 35% slower on
+    // the batched workload: twice the bytes through the L1.)
+    template <int ESZ>
+    __device__ __forceinline__ static uint4 load_unaligned(const char* p) {
+        if (ESZ >= 4 || (uintptr_t)p % 4 == 0) {
+            const uint32_t* w = (const uint32_t*)p;
+            return make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        return load_slow<ESZ>(p, 16);
+    }
+
     template <int ESZ>
     __device__ __forceinline__ static uint4 load_chunk(const char* row_base, int64_t b0,
                                                        int64_t nbytes, bool vec) {
-        if (b0 + 16 <= nbytes && vec) return *(const uint4*)(row_base + b0);
+        if (b0 + 16 <= nbytes)
+            return vec ? *(const uint4*)(row_base + b0) : load_unaligned<ESZ>(row_base + b0);
         if (b0 < nbytes) return load_slow<ESZ>(row_base + b0, nbytes - b0);
         return make_uint4(0, 0, 0, 0);
     }

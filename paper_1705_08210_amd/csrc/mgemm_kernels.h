@@ -333,22 +333,14 @@ hipError_t go_c3_finish(const Mg3Launch& a, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // Batched 2-way: one launch over (problem, tile, field chunk) items of many
-// problems, listed longest first on the host.  Workgroups are dispatched in
-// index order as slots free up, which is the greedy longest-first schedule;
-// a persistent loop over an atomic work counter measured the same schedule
-// but needed ~70 more registers (2 instead of 4 waves per SIMD).
+// problems.  The host packs the (problem, field chunk) groups onto the 8
+// XCDs by cost and lists each XCD's groups longest first; an XCD's blocks
+// take its list in order as slots free up (greedy longest-first within the
+// XCD), and an XCD works through whole groups, so the rows a tile column
+// shares stay in that XCD's L2.  A persistent loop over an atomic work
+// counter measured the same schedule but needed ~70 more registers (2
+// instead of 4 waves per SIMD).
 // ---------------------------------------------------------------------------
-// Block index -> position in an ordered work list, for a grid that is a
-// multiple of kXcds * kRun: blocks are dealt to the XCDs round-robin, so
-// XCD x receives positions in runs of kRun consecutive entries while all
-// XCDs advance through the list together (its order is kept to within
-// kXcds * kRun entries).
-constexpr int64_t kRun = 16;   // measured: 1.5x less L2-miss traffic than kRun = 1
-__device__ __forceinline__ int64_t run_remap(int64_t b) {
-    const int64_t x = b % kXcds, r = b / kXcds;
-    return (r / kRun) * (kXcds * kRun) + x * kRun + r % kRun;
-}
-
 template <int DT, int TM, int BKW>
 __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchLaunch a,
                                                                       int64_t item0) {
@@ -357,8 +349,12 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchL
     using Word = typename Ops<DT>::Word;
     __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
     __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
-    const int64_t t = item0 + run_remap(blockIdx.x);
-    if (t >= a.ntiles) return;
+    // block b runs on XCD b % kXcds: its position b / kXcds in that XCD's list
+    const int64_t b = item0 + blockIdx.x;
+    const int x = (int)(b % kXcds);
+    const int64_t r = b / kXcds;
+    if (r >= a.xcd_len[x]) return;
+    const int64_t t = a.xcd_start[x] + r;
     const int wave = threadIdx.x / 64;
     const BatchTile bt = a.tiles[t];
     const DevProblem p = a.probs[bt.prob];
@@ -425,7 +421,9 @@ hipError_t go_mg3_all(const Mg3Launch& a, Dispatch dispatch, hipStream_t st) {
 template <int DT, int TM, int BKW>
 hipError_t go_mgb(const MgBatchLaunch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    return launch_items(a.ntiles, kThreads, kXcds * kRun, [&](unsigned grid, int64_t item0) {
+    int64_t longest = 0;
+    for (int x = 0; x < kXcds; ++x) longest = a.xcd_len[x] > longest ? a.xcd_len[x] : longest;
+    return launch_items(kXcds * longest, kThreads, kXcds, [&](unsigned grid, int64_t item0) {
         hipLaunchKernelGGL((ps_mgb_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,
                            item0);
     });

@@ -691,14 +691,16 @@ static ps_status check_batch(const ps_problem* probs, int32_t n, int32_t dt, con
 }
 
 // Host-side tables of a batch: device problem records (with workspace sums
-// and chunk partials where needed) and the groups of the work list, longest
-// first.  An item's cost is the number of fields its chunk covers; the groups
-// are stably sorted by it, so equal costs keep problem and chunk order, and
-// each group lists its problem's tiles in column-major order.
+// and chunk partials where needed) and the groups of the work list.  A group
+// is one field chunk of one problem; it lists the problem's tiles in
+// column-major order, each item costing the fields its chunk covers.  The
+// groups are packed onto the XCDs by total cost (largest first, to the least
+// loaded), and each XCD's list holds its groups longest item first.
 struct BatchTables {
     std::vector<DevProblem> dp;
     std::vector<BatchGroup> groups;
     int64_t ntiles = 0, max_nv = 0, max_pairs = 0;
+    int64_t xcd_start[kXcds] = {}, xcd_len[kXcds] = {};
 };
 
 static BatchTables batch_tables(const ps_problem* probs, int32_t n, int32_t dt, const ps_opts* o,
@@ -721,7 +723,7 @@ static BatchTables batch_tables(const ps_problem* probs, int32_t n, int32_t dt, 
         }
         T.max_nv = std::max(T.max_nv, p.n_v);
     }
-    struct G { int64_t cost, tiles; BatchGroup g; };
+    struct G { int64_t cost, tiles; BatchGroup g; int x; };
     std::vector<G> gs;
     for (int32_t pi = 0; pi < n; ++pi) {
         if (probs[pi].n_v < 2) continue;
@@ -729,16 +731,37 @@ static BatchTables batch_tables(const ps_problem* probs, int32_t n, int32_t dt, 
         for (int32_t c = 0; c < nch; ++c) {
             const int64_t f0 = nch > 1 ? c * kChunkFields : 0;
             const int64_t f1 = nch > 1 ? std::min(probs[pi].n_f, f0 + kChunkFields) : probs[pi].n_f;
-            gs.push_back(G{f1 - f0, tri_tiles(probs[pi].n_v, bm), BatchGroup{pi, c, 0}});
+            gs.push_back(G{f1 - f0, tri_tiles(probs[pi].n_v, bm), BatchGroup{pi, c, 0}, 0});
         }
     }
-    std::stable_sort(gs.begin(), gs.end(), [](const G& a, const G& b) { return a.cost > b.cost; });
+    // groups onto XCDs: largest total cost first, each to the least loaded
+    // XCD (ties: the lower index, so the packing is deterministic)
+    std::vector<size_t> by_total(gs.size());
+    for (size_t k = 0; k < gs.size(); ++k) by_total[k] = k;
+    std::stable_sort(by_total.begin(), by_total.end(), [&](size_t a, size_t b) {
+        return gs[a].cost * gs[a].tiles > gs[b].cost * gs[b].tiles;
+    });
+    int64_t load[kXcds] = {};
+    for (size_t k : by_total) {
+        int x = 0;
+        for (int y = 1; y < kXcds; ++y)
+            if (load[y] < load[x]) x = y;
+        gs[k].x = x;
+        load[x] += gs[k].cost * gs[k].tiles;
+    }
+    // each XCD's list: its groups by the fields of their items, longest
+    // first (stable: problem and chunk order otherwise)
+    std::stable_sort(gs.begin(), gs.end(), [](const G& a, const G& b) {
+        return a.x != b.x ? a.x < b.x : a.cost > b.cost;
+    });
     T.groups.resize(gs.size());
     for (size_t k = 0; k < gs.size(); ++k) {
         T.groups[k] = gs[k].g;
         T.groups[k].start = T.ntiles;
+        T.xcd_len[gs[k].x] += gs[k].tiles;
         T.ntiles += gs[k].tiles;
     }
+    for (int x = 1; x < kXcds; ++x) T.xcd_start[x] = T.xcd_start[x - 1] + T.xcd_len[x - 1];
     return T;
 }
 
@@ -754,7 +777,11 @@ static ps_status batch_enqueue(const BatchLayout& L, const BatchTables& T, int32
         e = launch_batch_expand(L.groups, (int32_t)T.groups.size(), L.tiles, T.ntiles, st);
     if (e == hipSuccess) e = launch_batched_sums(L.probs, n, dt, T.max_nv, st);
     if (e == hipSuccess) {
-        MgBatchLaunch a{L.probs, L.tiles, T.ntiles, cfg, chunk_tiles(dt, cfg)};
+        MgBatchLaunch a{L.probs, L.tiles, T.ntiles, cfg, chunk_tiles(dt, cfg), {}, {}};
+        for (int x = 0; x < kXcds; ++x) {
+            a.xcd_start[x] = T.xcd_start[x];
+            a.xcd_len[x] = T.xcd_len[x];
+        }
         e = launch_mgb(dt, a, st);
     }
     if (e == hipSuccess) e = launch_finish2_batched(dt, L.probs, n, T.max_pairs, st);

@@ -299,10 +299,14 @@ struct BatchGroup {
 
 struct MgBatchLaunch {
     const DevProblem* probs;
-    const BatchTile* tiles;      // work items, longest first
+    const BatchTile* tiles;      // work items: one list per XCD, back to back
     int64_t ntiles;
     int cfg;
     int64_t chunk_tiles;         // field tiles per chunk (same for all problems)
+    // the list of XCD x: tiles[xcd_start[x] .. xcd_start[x] + xcd_len[x]),
+    // run by the blocks b with b % kXcds == x (hardware deals blocks to the
+    // XCDs round-robin), longest first
+    int64_t xcd_start[kXcds], xcd_len[kXcds];
 };
 
 // Tiles of the 2-way upper triangle for n_v vectors and output tile `bm`.
