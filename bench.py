@@ -77,6 +77,9 @@ def parse(argv=None):
     ap.add_argument("--counter-summary", nargs=2, metavar=("PMC_DIR", "KERNEL"),
                     help="no benchmark: per-dispatch means of every counter of one "
                          "rocprofv3 --pmc run for KERNEL, with busy fractions")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_LOG"),
+                    help="no benchmark: the kernel table of one rocprofv3 --kernel-trace "
+                         "--stats run of this script (csv) with the bench line it printed")
     ap.add_argument("--pmc-command", action="append", default=[],
                     help="command line recorded in the --pmc-summary output")
     return ap.parse_args(argv)
@@ -159,13 +162,16 @@ def cpu_baseline(V, n_f, seconds, way, seed=123):
 CSRC = os.path.join(ROOT, "paper_1705_08210_amd", "csrc")
 _VALU_SOURCES = ["ps_internal.h", "mgemm_core.h", "mgemm_kernels.h", "mg_common.hip",
                  "mg_f32.hip", "mg_f16.hip", "mg_u8.hip", "policy.hip"]
+_MFMA_SOURCES = ["ps_internal.h", "mfma.hip", "policy.hip"]
 KERNEL_SOURCES = {
     "ps_mg2_kernel": _VALU_SOURCES,
-    "ps_mg3_kernel": _VALU_SOURCES,
+    "ps_mg3f_kernel": _VALU_SOURCES,
     "ps_mgb_kernel": _VALU_SOURCES,
-    "ps_mfma2_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
-    "ps_mfma2_dma_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
-    "ps_mfma3_kernel": ["ps_internal.h", "mfma.hip", "policy.hip"],
+    "ps_mfma2_lv_kernel": _MFMA_SOURCES,
+    "ps_mfma2_kernel": _MFMA_SOURCES,
+    "ps_mfma2_dma_kernel": _MFMA_SOURCES,
+    "ps_mfma3_lv_kernel": _MFMA_SOURCES,
+    "ps_mfma3_kernel": _MFMA_SOURCES,
 }
 PROFILES = os.path.join(ROOT, "profiles")
 GIB = 1 << 30
@@ -320,11 +326,53 @@ def counter_summary(d, kernel, commands):
     return "\n".join(lines) + "\n"
 
 
+def trace_summary(d, log, commands):
+    """The kernel statistics of a rocprofv3 --kernel-trace --stats csv run
+    and the bench line of the same run (with the clock it measured)."""
+    import csv
+    import glob
+    lines = [f"command: {c}" for c in commands]
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        lines += ["", f"rocprofv3 kernel stats ({os.path.basename(f)}):",
+                  f"{'kernel':<72}{'calls':>7}{'avg_us':>13}{'min_us':>13}{'max_us':>13}{'pct':>7}"]
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                lines.append(f"{r['Name'][:71]:<72}{int(r['Calls']):>7}"
+                             f"{float(r['AverageNs']) / 1e3:>13.1f}"
+                             f"{float(r['MinNs']) / 1e3:>13.1f}{float(r['MaxNs']) / 1e3:>13.1f}"
+                             f"{float(r['Percentage']):>7.2f}")
+    bench = None
+    with open(log) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                bench = json.loads(line)
+    if bench is not None:
+        def brief(b):
+            return (f"value={b['value']:.4g} {b['unit']} ms_per_step={b['ms_per_step']:.3f} "
+                    f"config={json.dumps(b['config'])} roofline={json.dumps(b['roofline'])}")
+        lines += ["", "bench line (same run): " + brief(bench)]
+        if "three_way" in bench:
+            lines.append("  three_way: " + brief(bench["three_way"]))
+        lines.append(f"GPU clock (bench clock probe, same run): {bench.get('gpu_clock_ghz')} GHz")
+    return "\n".join(lines) + "\n"
+
+
 def traffic_key(args, wl):
     """Workload and operand type of a run: names its traffic file."""
     if wl in ("levels_8192x32768", "binary_8192x32768", "levels_4096x1024"):
         return wl + {"mfma_fp4": "_fp4", "bits": "_bits"}.get(args.path, "_u8")
     return wl + {"f16": "_f16", "f64": "_f64"}.get(args.storage, "_f32")
+
+
+def resolved_path(args, V, way):
+    """The path the library runs for this input and --path (AUTO resolved by
+    the library's own policy and tuning table)."""
+    import numpy as np
+    from paper_1705_08210_amd import ps
+    levels = int(V.max()) if V.dtype == np.uint8 else 0
+    code = ps.path_choice(V.dtype, way, V.shape[1], V.shape[0], path=args.path, levels=levels,
+                          tile=args.tile)
+    return {v: k for k, v in ps.PATH.items()}[code]
 
 
 def _parity_pairs(Vh, c2_dev, n_v, m, seed, dev_to_host):
@@ -404,17 +452,16 @@ def measure(args, wl, K, W, with_cpu=True):
                 timer.add(a, timer.mark())
 
         cmp = n_f * m
-        use_mfma = V.dtype == np.uint8 and (args.path == "mfma" or
-                                            (args.path == "auto" and 1 <= levels <= 15))
-        if V.dtype == np.uint8 and args.path == "bits":   # v_and + v_bcnt per 32 comparisons
+        path = resolved_path(args, V, 2)
+        if path == "bits":   # v_and + v_bcnt per 32 comparisons
             dtype, bound, ops_per_cmp, peak = "b1", "alu", 2.0 / 32, HALF_RATE_OPS_TOPS
             kernel = "ps_mg2_kernel"
-        elif V.dtype == np.uint8 and args.path == "mfma_fp4":   # e2m1 planes, FP32 sums
+        elif path == "mfma_fp4":   # e2m1 planes, FP32 sums
             dtype, bound, ops_per_cmp, peak = "fp4", "mfma", 2.0 * levels, FP4_MFMA_PEAK_TOPS
             kernel = "ps_mfma2_dma_kernel"
-        elif use_mfma:   # thermometer planes: `levels` int8 MACs (2 ops) per comparison
+        elif path == "mfma":   # thermometer levels: `levels` int8 MACs (2 ops) per comparison
             dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
-            kernel = "ps_mfma2_kernel"
+            kernel = "ps_mfma2_kernel" if args.tile == 2 else "ps_mfma2_lv_kernel"
         elif V.dtype == np.uint8:   # v_sad_u8: 4 comparisons per op
             dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
             kernel = "ps_mg2_kernel"
@@ -427,7 +474,7 @@ def measure(args, wl, K, W, with_cpu=True):
         else:                        # min + add per comparison
             dtype, bound, ops_per_cmp, peak = "f32", "alu", 2.0, FP32_LANE_OPS_TOPS
             kernel = "ps_mg2_kernel"
-        config = {"workload": wl, "way": 2, "n_f": n_f, "n_v": n_v}
+        config = {"workload": wl, "way": 2, "n_f": n_f, "n_v": n_v, "path": path}
         cpu = (lambda: cpu_baseline(V, n_f, args.cpu_seconds, 2))
 
         def parity():
@@ -487,25 +534,24 @@ def measure(args, wl, K, W, with_cpu=True):
             parity = None
 
         cmp = n_f * math.comb(n_v, 3)
-        use_mfma = V.dtype == np.uint8 and (args.path in ("mfma", "mfma_fp4") or
-                                            (args.path == "auto" and 1 <= levels <= 15))
-        if use_mfma and args.path == "mfma_fp4":   # e2m1 planes: `levels` MACs per comparison
+        path = resolved_path(args, V, 3)
+        if path == "mfma_fp4":   # e2m1 planes: `levels` MACs per comparison
             dtype, bound, ops_per_cmp, peak = "fp4", "mfma", 2.0 * levels, FP4_MFMA_PEAK_TOPS
             kernel = "ps_mfma3_kernel"
-        elif use_mfma:
+        elif path == "mfma":
             dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
-            kernel = "ps_mfma3_kernel"
+            kernel = "ps_mfma3_lv_kernel"
         elif V.dtype == np.uint8:
             dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
-            kernel = "ps_mg3_kernel"
+            kernel = "ps_mg3f_kernel"
         else:
             dtype = {np.dtype(np.float16): "f16", np.dtype(np.float64): "f64"}.get(V.dtype, "f32")
             bound = "alu"
             ops_per_cmp, peak = {"f16": (1.0, HALF_RATE_OPS_TOPS),
                                  "f64": (2.0, HALF_RATE_OPS_TOPS)}.get(dtype,
                                                                     (2.0, FP32_LANE_OPS_TOPS))
-            kernel = "ps_mg3_kernel"
-        config = {"workload": wl, "way": 3, "n_f": n_f, "n_v": n_v}
+            kernel = "ps_mg3f_kernel"
+        config = {"workload": wl, "way": 3, "n_f": n_f, "n_v": n_v, "path": path}
         cpu = (lambda: cpu_baseline(V, n_f, args.cpu_seconds, 3))
     elif wl == "batched_64_uneven":
         Vs_np = workloads.batched_64_uneven(0)
@@ -587,6 +633,10 @@ def main(argv=None):
     if args.counter_summary:
         sys.stdout.write(counter_summary(args.counter_summary[0], args.counter_summary[1],
                                          args.pmc_command))
+        return 0
+    if args.trace_summary:
+        sys.stdout.write(trace_summary(args.trace_summary[0], args.trace_summary[1],
+                                       args.pmc_command))
         return 0
     if args.pmc_summary:
         fetch_dir, write_dir, kernel = args.pmc_summary

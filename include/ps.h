@@ -301,16 +301,34 @@ void ps_plan_destroy(ps_plan* plan);
  * Tile configurations (for tuning).  `way` is 2 or 3.  Returns the number of
  * compiled configurations for (dtype, way, path); when idx is in range
  * writes the output-tile rows/cols and field-tile depth of configuration idx.
+ * VALU and BITS paths: the tile shapes that opts.tile = 1 + idx selects.
+ * PS_PATH_MFMA (PS_U8, way 2): the tile orders of the int8 matrix-core
+ * kernel, all 256 x 256 x 128: configuration idx walks the upper triangle in
+ * groups of 2^idx block columns (tiles running side by side share rows in
+ * L2); chosen through ps_tune_register only.
  */
 int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx,
                        int32_t* bm, int32_t* bn, int32_t* bk);
 
-/* Register a tuned choice: for (dtype, way, path) and problems with
- * n_f in [nf_lo, nf_hi) and n_v in [nv_lo, nv_hi), use tile configuration
- * `idx`.  Later registrations take precedence.  Host-side table only. */
+/* Register a tuned choice for problems with n_f in [nf_lo, nf_hi) and n_v in
+ * [nv_lo, nv_hi); later registrations take precedence.  Host-side table only.
+ *   path VALU / BITS, way 2, 3 (or 0: batched): idx = the tile configuration
+ *     the library uses when opts.tile = 0;
+ *   path MFMA, way 2, PS_U8: idx = the matrix-core tile order (above);
+ *   path AUTO, way 2 or 3, PS_U8: idx = the ps_path (VALU, MFMA or
+ *     MFMA_FP4) that opts.path = AUTO takes for integer levels (1..15), used
+ *     when that path can take the shape.
+ * Errors: PS_ERR_DTYPE, PS_ERR_ARG (way, path or idx out of range). */
 ps_status ps_tune_register(int32_t dtype, int32_t way, int32_t path,
                            int64_t nf_lo, int64_t nf_hi, int64_t nv_lo,
                            int64_t nv_hi, int32_t idx);
+/* The path (a ps_path value other than AUTO) that ps2_compute (way 2) or
+ * ps3_compute (way 3) takes for these arguments: opts.path itself unless it
+ * is AUTO, else the library's choice (policy and tuning table).  -1 for an
+ * unknown dtype or way. */
+int32_t ps_path_choice(int32_t dtype, int32_t way, int64_t n_f, int64_t n_v, int64_t ld,
+                       const ps_opts* opts);
+
 /* Forget all registered choices. */
 void ps_tune_clear(void);
 

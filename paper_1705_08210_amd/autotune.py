@@ -1,10 +1,17 @@
-"""Tile tuner for the VALU min-product kernels.
+"""Tuner of the library's launch choices.
 
-Times every compiled tile configuration (``ps_tile_config``) through the C ABI
-on seeded synthetic inputs of representative shapes, and keeps the fastest per
-(storage type, way, n_f bucket, n_v bucket) in a JSON cache.  ``load()``
-registers a cache with the library (``ps_tune_register``), after which
-``opts.tile = 0`` picks the tuned configuration.  Runs off the timed path.
+Times the alternatives through the C ABI on seeded synthetic inputs of
+representative shapes and keeps the fastest per (storage type, way, n_f
+bucket, n_v bucket) in a JSON cache:
+  - the VALU tile configuration (``ps_tile_config``) of 2-way, 3-way and
+    batched launches (entries with path "valu");
+  - the path AUTO takes for integer levels (VALU, int8 or fp4 matrix cores;
+    path "auto", the entry's "tile" is the chosen ps_path code);
+  - the tile order of the 2-way int8 matrix-core kernel: block columns
+    walked in groups of 2^idx (path "mfma").
+``load()`` registers a cache with the library (``ps_tune_register``), after
+which the library's own choices (``opts.tile = 0``, ``opts.path = AUTO``)
+follow it.  Runs off the timed path.
 
     python -m paper_1705_08210_amd.autotune [--quick] [--out FILE]
 """
@@ -36,7 +43,15 @@ REPS = {
     3: {(0, 0): (1024, 256), (1, 0): (4096, 384), (2, 0): (12000, 256),
         (0, 1): (1024, 1024), (1, 1): (4096, 1024), (2, 1): (12000, 1024)},
 }
+# integer-level shapes for the path and matrix-core tile-order choices
+PATH_REPS = {
+    2: {(1, 0): (4096, 512), (1, 1): (4096, 2048), (1, 2): (8192, 8192),
+        (2, 1): (16384, 2048)},
+    3: {(1, 0): (4096, 384), (0, 1): (1024, 1024), (1, 1): (4096, 1024)},
+}
+LEVELS = 3
 DTYPES = {"f32": torch.float32, "f16": torch.float16, "u8": torch.uint8}
+PATH_CODES = {"valu": 1, "mfma": 2, "mfma_fp4": 3}
 
 
 def _input(n_v, n_f, dt, seed=0):
@@ -63,6 +78,52 @@ def _time(fn, reps):
     return best
 
 
+def _entry(dname, way, path, fb, vb, shape, idx, times):
+    return {"dtype": dname, "way": way, "path": path, "nf": list(NF_BUCKETS[fb]),
+            "nv": list(NV_BUCKETS[vb]), "shape": list(shape), "tile": idx,
+            "ms": [round(t, 4) for t in times]}
+
+
+def tune_paths(ways=(2, 3), reps=3, quick=False, log=print):
+    """For uint8 levels (0..3): the fastest of the VALU, int8 and fp4
+    matrix-core paths per bucket (the choice AUTO then takes), and for the
+    2-way int8 kernel the fastest tile order."""
+    out = []
+    dt = torch.uint8
+    for way in ways:
+        for (fb, vb), (n_f, n_v) in PATH_REPS[way].items():
+            if quick and (fb, vb) not in ((1, 1), (1, 0)):
+                continue
+            V = _input(n_v, n_f, dt)
+            s, _ = ps.vector_sums(V, want_bad=False)
+            if way == 2:
+                c2 = torch.empty(n_v * (n_v - 1) // 2, device="cuda")
+                run = (lambda p: ps.ps2(V, s=s, c2=c2, path=p, levels=LEVELS))
+            else:
+                _, n2 = ps.ps2(V, s=s, want_c2=False, want_n2=True)
+                c3 = torch.empty(math.comb(n_v, 3), device="cuda")
+                run = (lambda p: ps.ps3(V, s=s, n2=n2, c3=c3, path=p, levels=LEVELS))
+            names = list(PATH_CODES)
+            times = [_time(lambda p=p: run(p), reps) for p in names]
+            best = names[int(np.argmin(times))]
+            rec = _entry("u8", way, "auto", fb, vb, (n_f, n_v), PATH_CODES[best], times)
+            log(json.dumps(rec))
+            out.append(rec)
+            if way == 2:   # tile order of the int8 matrix-core kernel
+                times = []
+                for idx in range(len(ps.tile_configs(dt, 2, "mfma"))):
+                    ps.tune_clear()
+                    ps.tune_register(dt, 2, "mfma", (0, 1 << 40), (0, 1 << 40), idx)
+                    times.append(_time(lambda: run("mfma"), reps))
+                ps.tune_clear()
+                rec = _entry("u8", 2, "mfma", fb, vb, (n_f, n_v), int(np.argmin(times)), times)
+                log(json.dumps(rec))
+                out.append(rec)
+            del V
+            torch.cuda.empty_cache()
+    return out
+
+
 def _batch_inputs(dt, count=24, seed=0):
     """A representative uneven batch: shapes log-uniform like the batched
     workload (n_v in [500, 8000], n_f in [1000, 20000]), scaled down in count."""
@@ -75,17 +136,17 @@ def _batch_inputs(dt, count=24, seed=0):
     return Vs
 
 
-def tune_batched(dname, reps=3, log=print):
+def tune_batched(dname, reps=3, log=print, count=24):
     """One entry for batched launches (way 0, any shape): the configuration
     that runs a representative uneven batch fastest as one launch."""
     dt = DTYPES[dname]
-    Vs = _batch_inputs(dt)
+    Vs = _batch_inputs(dt, count)
     outs = ps._batch_outputs(Vs)
     ncfg = len(ps.tile_configs(dt, 2))
     times = [_time(lambda i=idx: ps.ps2_batched(Vs, outs=outs, tile=i + 1), reps)
              for idx in range(ncfg)]
     best = int(np.argmin(times))
-    rec = {"dtype": dname, "way": 0, "nf": [0, 1 << 40], "nv": [0, 1 << 40],
+    rec = {"dtype": dname, "way": 0, "path": "valu", "nf": [0, 1 << 40], "nv": [0, 1 << 40],
            "shape": [len(Vs), "uneven"], "tile": best, "ms": [round(t, 4) for t in times]}
     log(json.dumps(rec))
     del Vs, outs
@@ -93,11 +154,13 @@ def tune_batched(dname, reps=3, log=print):
     return rec
 
 
-def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3, 0), reps=3, quick=False, log=print):
+def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3, 0), reps=3, quick=False, log=print,
+         batch_count=24):
+    ps.tune_clear()    # time the alternatives, not earlier choices
     out = []
     for dname in dtypes:
         if 0 in ways:
-            out.append(tune_batched(dname, reps, log))
+            out.append(tune_batched(dname, reps, log, batch_count))
     for dname in dtypes:
         dt = DTYPES[dname]
         ncfg = len(ps.tile_configs(dt, 2))
@@ -117,25 +180,27 @@ def tune(dtypes=("f32", "f16", "u8"), ways=(2, 3, 0), reps=3, quick=False, log=p
                     if way == 2:
                         f = (lambda i=idx: ps.ps2(V, s=s, c2=c2, path="valu", tile=i + 1))
                     else:
-                        # as the library runs a tuned choice (opts.tile = 0): the
-                        # 128-wide configurations over whole slab tiles, with
-                        # 64-wide tiles at the slab edges
-                        ps.tune_clear()
-                        ps.tune_register(dt, 3, "valu", (0, 1 << 40), (0, 1 << 40), idx)
-                        f = (lambda: ps.ps3(V, s=s, n2=n2, c3=c3))
+                        f = (lambda i=idx: ps.ps3(V, s=s, n2=n2, c3=c3, path="valu",
+                                                  tile=i + 1))
                     times.append(_time(f, reps))
-                best = int(np.argmin(times))
-                rec = {"dtype": dname, "way": way, "nf": list(NF_BUCKETS[fb]),
-                       "nv": list(NV_BUCKETS[vb]), "shape": [n_f, n_v], "tile": best,
-                       "ms": [round(t, 4) for t in times]}
+                rec = _entry(dname, way, "valu", fb, vb, (n_f, n_v), int(np.argmin(times)),
+                             times)
                 log(json.dumps(rec))
                 out.append(rec)
                 del V
                 torch.cuda.empty_cache()
+    if "u8" in dtypes and (2 in ways or 3 in ways):
+        out += tune_paths(tuple(w for w in (2, 3) if w in ways), reps, quick, log)
     ps.tune_clear()      # the library now follows the new choices
     for e in out:
-        ps.tune_register(DTYPES[e["dtype"]], e["way"], "valu", e["nf"], e["nv"], e["tile"])
+        register(e)
     return {"device": torch.cuda.get_device_name(0), "time": time.time(), "entries": out}
+
+
+def register(e) -> None:
+    """One cache entry into the library's tuning table."""
+    ps.tune_register(DTYPES[e["dtype"]], e["way"], e.get("path", "valu"), e["nf"], e["nv"],
+                     e["tile"])
 
 
 def save(cache, path=CACHE):
@@ -151,7 +216,7 @@ def load(path=CACHE) -> int:
         cache = json.load(f)
     n = 0
     for e in cache.get("entries", []):
-        ps.tune_register(DTYPES[e["dtype"]], e["way"], "valu", e["nf"], e["nv"], e["tile"])
+        register(e)
         n += 1
     return n
 

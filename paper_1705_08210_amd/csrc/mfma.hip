@@ -456,6 +456,7 @@ struct LvArgs {
     const uint8_t* V;
     int64_t ld, n_f, n_v;
     int levels;
+    int group;            // 2-way: block columns per tile-order group
     int64_t nk;           // field tiles
     const double* s;
     float* c2;
@@ -710,7 +711,7 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_lv_kernel(LvAr
                       blockIdx.x / kXcds;
     if (t >= a.ntiles) return;
     int64_t bi, bj;
-    grouped_tri_decode<kGroup>(t, a.nb, bi, bj);
+    grouped_tri_decode_rt(t, a.nb, a.group, bi, bj);
     const int64_t i0 = bi * kMB, j0 = bj * kMB;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int wr = (wave % 2) * 128;        // j offset of the wave's block (A rows)
@@ -835,6 +836,7 @@ static LvArgs lv_args(const MfmaLaunch& m) {
     a.n_f = m.n_f;
     a.n_v = m.n_v;
     a.levels = m.levels;
+    a.group = m.group >= 1 && m.group <= 64 ? m.group : kGroup;
     a.nk = (m.n_f + kLvMK - 1) / kLvMK;
     if (a.nk < 1) a.nk = 1;
     a.s = m.s;

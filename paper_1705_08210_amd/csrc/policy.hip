@@ -128,15 +128,40 @@ int64_t max_grid_blocks(int threads, int64_t multiple) {
 
 bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4; }
 
-int choose_path(int32_t dt, const ps_opts* o, int64_t n_f, int64_t ld) {
+// Whether a matrix-core path can take the shape (exact sums, 32-bit offsets).
+static bool mfma_can(int path, int64_t n_f, int levels, int wide, int64_t ld) {
+    if (path == PS_PATH_MFMA_FP4)
+        return (int64_t)levels * n_f < ((int64_t)1 << 24) && mfma_row_fits(n_f, levels, 1);
+    if (mfma_fused(n_f, levels, 0, wide)) return mfma_ld_fits(ld);
+    return (int64_t)levels * n_f < ((int64_t)1 << 31) && mfma_row_fits(n_f, levels, 0);
+}
+
+// A tuned entry for (dt, way, path) covering the shape, or -1.
+static int tuned(int32_t dt, int way, int32_t path, int64_t n_f, int64_t n_v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+        if (it->dt == dt && it->way == way && it->path == path && n_f >= it->nf_lo &&
+            n_f < it->nf_hi && n_v >= it->nv_lo && n_v < it->nv_hi)
+            return it->idx;
+    return -1;
+}
+
+int choose_path(int32_t dt, const ps_opts* o, int way, int64_t n_f, int64_t n_v, int64_t ld) {
     const int p = o ? o->path : PS_PATH_AUTO;
     if (p == PS_PATH_VALU || p == PS_PATH_MFMA || p == PS_PATH_MFMA_FP4 || p == PS_PATH_BITS)
         return p;
-    if (dt == PS_U8 && o && o->levels >= 1 && o->levels <= 15 &&
-        (mfma_fused(n_f, o->levels, 0, o->tile == 2) ? mfma_ld_fits(ld)
-                                                     : mfma_row_fits(n_f, o->levels, 0)))
-        return PS_PATH_MFMA;
-    return PS_PATH_VALU;
+    if (dt != PS_U8 || !o || o->levels < 1 || o->levels > 15) return PS_PATH_VALU;
+    const int wide = o->tile == 2;
+    const int t = tuned(dt, way, PS_PATH_AUTO, n_f, n_v);
+    if (t == PS_PATH_VALU) return PS_PATH_VALU;
+    if ((t == PS_PATH_MFMA || t == PS_PATH_MFMA_FP4) && mfma_can(t, n_f, o->levels, wide, ld))
+        return t;
+    return mfma_can(PS_PATH_MFMA, n_f, o->levels, wide, ld) ? PS_PATH_MFMA : PS_PATH_VALU;
+}
+
+int mfma_group(int64_t n_f, int64_t n_v) {
+    const int t = tuned(PS_U8, 2, PS_PATH_MFMA, n_f, n_v);
+    return 1 << (t >= 0 ? t : 2);
 }
 
 }  // namespace ps
@@ -147,7 +172,17 @@ extern "C" {
 
 int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx, int32_t* bm,
                        int32_t* bn, int32_t* bk) {
-    if (elem_size(dtype) == 0 || (way != 2 && way != 3) || is_mfma(path)) return 0;
+    if (elem_size(dtype) == 0 || (way != 2 && way != 3)) return 0;
+    if (path == PS_PATH_MFMA) {   // tile orders of the 2-way int8 kernel, 256 x 256 x 128
+        if (dtype != PS_U8 || way != 2) return 0;
+        if (idx >= 0 && idx < kNumMfmaCfgs) {
+            if (bm) *bm = kMfmaTile;
+            if (bn) *bn = kMfmaTile;
+            if (bk) *bk = 128;
+        }
+        return kNumMfmaCfgs;
+    }
+    if (is_mfma(path)) return 0;
     if (idx >= 0 && idx < kNumValuCfgs) {
         if (bm) *bm = kValuCfgs[idx].bm();
         if (bn) *bn = kValuCfgs[idx].bn();
@@ -161,10 +196,26 @@ ps_status ps_tune_register(int32_t dtype, int32_t way, int32_t path, int64_t nf_
     if (elem_size(dtype) == 0) return fail(PS_ERR_DTYPE, "unknown dtype %d", dtype);
     if (way != 0 && way != 2 && way != 3)
         return fail(PS_ERR_ARG, "way must be 2, 3 (or 0 for batched)");
-    if (idx < 0 || idx >= kNumValuCfgs) return fail(PS_ERR_ARG, "tile index %d out of range", idx);
+    if (path == PS_PATH_AUTO) {   // the path AUTO takes for integer data
+        if (dtype != PS_U8 || way == 0)
+            return fail(PS_ERR_ARG, "path choices are tuned for PS_U8, way 2 or 3");
+        if (idx != PS_PATH_VALU && idx != PS_PATH_MFMA && idx != PS_PATH_MFMA_FP4)
+            return fail(PS_ERR_ARG, "path choice %d is not VALU, MFMA or MFMA_FP4", idx);
+    } else if (path == PS_PATH_MFMA) {
+        if (idx < 0 || idx >= kNumMfmaCfgs)
+            return fail(PS_ERR_ARG, "MFMA tile order %d out of range", idx);
+    } else if (idx < 0 || idx >= kNumValuCfgs) {
+        return fail(PS_ERR_ARG, "tile index %d out of range", idx);
+    }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.push_back(TuneEntry{dtype, way, path, nf_lo, nf_hi, nv_lo, nv_hi, idx});
     return PS_OK;
+}
+
+int32_t ps_path_choice(int32_t dtype, int32_t way, int64_t n_f, int64_t n_v, int64_t ld,
+                       const ps_opts* opts) {
+    if (elem_size(dtype) == 0 || (way != 2 && way != 3) || n_f < 0 || n_v < 0) return -1;
+    return choose_path(dtype, opts, way, n_f, n_v, ld < n_f ? n_f : ld);
 }
 
 void ps_tune_clear(void) {

@@ -229,7 +229,7 @@ ps_status ps_vector_sums(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
 size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_given,
                           const ps_opts* opts) {
     if (elem_size(dtype) == 0 || n_f < 0 || n_v < 0) return 0;
-    const int path = choose_path(dtype, opts, n_f, n_f);
+    const int path = choose_path(dtype, opts, 2, n_f, n_v, n_f);
     const Split sp = path == PS_PATH_BITS
                          ? Split{1, 0}
                          : plan_split(dtype, n_f, n_v,
@@ -249,7 +249,7 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     if (!aligned(c2, 4) || !aligned(n2, 4) || !aligned(s, 8))
         return fail(PS_ERR_ARG, "misaligned output or sums pointer");
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
-    const int path = choose_path(dtype, opts, n_f, ld);
+    const int path = choose_path(dtype, opts, 2, n_f, n_v, ld);
     const int levels = opts ? opts->levels : 0;
     const int wide = opts && opts->tile == 2;
     if ((st = check_mfma(path, dtype, levels, n_f, ld, wide)) != PS_OK) return st;
@@ -274,8 +274,8 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     }
     if (is_mfma(path)) {
         // opts.tile: 0 or 1 -> 4x2 blocks per wave, 2 -> 4x4 blocks per wave
-        MfmaLaunch m{V, n_f, n_v, ld, levels, s, c2, n2, planes,
-                     path == PS_PATH_MFMA_FP4 ? 1 : 0, wide, 1, 0, 0, nullptr, nullptr};
+        MfmaLaunch m{V,    n_f,  n_v, ld, levels, s, c2, n2, planes, path == PS_PATH_MFMA_FP4 ? 1 : 0,
+                     wide, mfma_group(n_f, n_v), 1, 0, 0, nullptr, nullptr};
         e = launch_mfma2(m, stream);
         if (e == hipErrorNotSupported)
             return fail(PS_ERR_UNSUPPORTED, "MFMA path not available in this library");
@@ -358,8 +358,8 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
         if (e != hipSuccess) return hip_fail(e, "sums launch");
         s = s_ws;
     }
-    MfmaLaunch m{V,       n_f,     n_v,   ld, levels, s,      nullptr, nullptr, (int8_t*)planes,
-                 fmt,     0,       1,     j_begin, j_end, prefix, c3, prefix + (n_v + 1)};
+    MfmaLaunch m{V,   n_f, n_v, ld, levels, s, nullptr, nullptr, (int8_t*)planes, fmt, 0,
+                 mfma_group(n_f, n_v), 1, j_begin, j_end, prefix, c3, prefix + (n_v + 1)};
     if (!n2) {   // pair numerators; this launch also writes the planes
         MfmaLaunch m2 = m;
         m2.n2 = n2_ws;
@@ -389,7 +389,7 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
     if (is_bits(opts))
         return ws3_layout(n_v, npre, s_given, n2_given, 4, 1, 1, stage, bits_bytes(n_f, n_v),
                           nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
-    const int path = choose_path(dtype, opts, n_f, n_f);
+    const int path = choose_path(dtype, opts, 3, n_f, n_v, n_f);
     if (is_mfma(path) && dtype == PS_U8)
         return ws3_layout(n_v, npre, s_given, n2_given, 4, 1, 1, stage,
                           mfma_workspace_bytes(n_f, n_v, opts ? opts->levels : 0,
@@ -492,7 +492,7 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
     if ((st = check_bits(dtype, opts)) != PS_OK) return st;
-    const int path = choose_path(dtype, opts, n_f, ld);
+    const int path = choose_path(dtype, opts, 3, n_f, n_v, ld);
     const int levels = opts ? opts->levels : 0;
     if ((st = check_mfma(path, dtype, levels, n_f, ld, 0)) != PS_OK) return st;
     if ((st = check_int_range(path, dtype, n_f)) != PS_OK) return st;

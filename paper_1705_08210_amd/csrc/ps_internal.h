@@ -145,6 +145,35 @@ __host__ __device__ inline void slab_tile_origin(int64_t n_v, int64_t j, int64_t
 // position of t; the search inside a group is bounded by G rows.
 template <int G>
 __device__ __forceinline__ void grouped_tri_decode(int64_t t, int64_t nb, int64_t& bi,
+                                                   int64_t& bj);
+// The same with the group width G chosen at run time (1 <= G <= 64).
+__device__ __forceinline__ void grouped_tri_decode_rt(int64_t t, int64_t nb, int G, int64_t& bi,
+                                                      int64_t& bj) {
+    int64_t j = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (j * (j + 1) / 2 > t) --j;
+    while ((j + 1) * (j + 2) / 2 <= t) ++j;
+    const int64_t g0 = j / G * G;
+    const int64_t g1 = g0 + G < nb ? g0 + G : nb;
+    const int64_t w = g1 - g0;
+    int64_t u = t - g0 * (g0 + 1) / 2;
+    if (u < g0 * w) {
+        bi = u / w;
+        bj = g0 + u % w;
+        return;
+    }
+    u -= g0 * w;
+    for (int64_t r = g0; r < g1; ++r) {
+        if (u < g1 - r) {
+            bi = r;
+            bj = r + u;
+            return;
+        }
+        u -= g1 - r;
+    }
+    bi = bj = 0;
+}
+template <int G>
+__device__ __forceinline__ void grouped_tri_decode(int64_t t, int64_t nb, int64_t& bi,
                                                    int64_t& bj) {
     int64_t j = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (j * (j + 1) / 2 > t) --j;
@@ -211,10 +240,17 @@ int32_t split_chunks(int32_t dt, int64_t n_f, int acc);
 int64_t chunk_tiles(int32_t dt, int cfg);
 Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o);
 bool is_mfma(int path);
-// AUTO takes the int8 MFMA path for PS_U8 data with 1 <= levels <= 15 whose
-// rows fit the 32-bit tile offsets (mfma_ld_fits on the fused path,
-// mfma_row_fits on planes); ld is the row stride (n_f in size queries).
-int choose_path(int32_t dt, const ps_opts* o, int64_t n_f, int64_t ld);
+// AUTO for PS_U8 data with 1 <= levels <= 15: the path a tuned entry
+// (dtype, way, PS_PATH_AUTO) registers for the shape, when that path can
+// take it; else the int8 MFMA path when its rows fit the 32-bit tile offsets
+// (mfma_ld_fits on the fused path, mfma_row_fits on planes); else VALU.  ld
+// is the row stride (n_f in size queries).
+int choose_path(int32_t dt, const ps_opts* o, int way, int64_t n_f, int64_t n_v, int64_t ld);
+// Tile order of the fused 2-way int8 MFMA kernel: block columns are walked in
+// groups of mfma_group(...) columns (a tuned entry for path MFMA registers
+// idx, the group being 2^idx; default 4).
+constexpr int kNumMfmaCfgs = 5;
+int mfma_group(int64_t n_f, int64_t n_v);
 int batch_cfg(const ps_problem* p, int32_t n, int32_t dt, const ps_opts* o);
 
 // Arguments of one 2-way launch over the upper-triangle tile list.
@@ -364,6 +400,7 @@ struct MfmaLaunch {
     int8_t* planes;              // workspace: mfma_workspace_bytes()
     int fmt;                     // 0: int8 planes, 1: fp4 (e2m1) planes
     int wide;                    // 0: 4x2 MFMA blocks per wave, 1: 4x4
+    int group;                   // fused 2-way: block columns per tile-order group
     int expand;                  // 1: write the planes first; 0: planes already hold V's
     // 3-way slices (launch_mfma3): n2 holds the pair numerators; the fused
     // path (mfma_fused) writes the metric c3 of the stage, the plane path raw

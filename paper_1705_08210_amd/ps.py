@@ -81,6 +81,7 @@ _sig("ps_tile_config", I32, [I32, I32, I32, I32, ctypes.POINTER(I32),
                              ctypes.POINTER(I32), ctypes.POINTER(I32)])
 _sig("ps_tune_register", ctypes.c_int, [I32, I32, I32, I64, I64, I64, I64, I32])
 _sig("ps_tune_clear", None, [])
+_sig("ps_path_choice", I32, [I32, I32, I64, I64, I64, ctypes.POINTER(Opts)])
 _sig("ps_quantize_u8", ctypes.c_int, [P, I64, P, P])
 _sig("ps_threshold_workspace_size", SZ, [I64])
 _sig("ps_threshold", ctypes.c_int, [P, I64, ctypes.c_float, I64, P, P, I64, P, P, SZ, P])
@@ -387,6 +388,20 @@ def tune_register(dtype, way, path, nf_range, nv_range, idx) -> None:
 
 def tune_clear() -> None:
     lib.ps_tune_clear()
+
+
+def path_choice(dtype, way: int, n_f: int, n_v: int, ld: int | None = None, path="auto",
+                levels=0, tile=0, acc="auto") -> int:
+    """The ps_path code that ps2 (way 2) / ps3 (way 3) run for these
+    arguments (AUTO resolved by the library's policy and tuning table).
+    dtype: a torch or numpy dtype."""
+    import numpy as np
+    dt = DTYPES[dtype] if dtype in DTYPES else {np.dtype(np.float32): PS_F32,
+                                                 np.dtype(np.float16): PS_F16,
+                                                 np.dtype(np.uint8): PS_U8,
+                                                 np.dtype(np.float64): PS_F64}[np.dtype(dtype)]
+    o = _opts(acc, path, levels, tile)
+    return int(lib.ps_path_choice(dt, way, n_f, n_v, n_f if ld is None else ld, ctypes.byref(o)))
 
 
 def quantize_u8(c: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

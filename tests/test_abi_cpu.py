@@ -268,7 +268,34 @@ def test_tile_configs_and_tuning_table():
     assert lib.ps_tune_register(0, 2, 1, 0, 10, 0, 10, 99) == ARG
     assert lib.ps_tune_register(0, 4, 1, 0, 10, 0, 10, 0) == ARG
     assert lib.ps_tune_register(0, 2, 1, 0, 10, 0, 10, 1) == OK
+    # matrix-core tile orders (uint8, 2-way) and the AUTO path for integer levels
+    assert lib.ps_tile_config(2, 2, 2, 0, None, None, None) == 5
+    assert lib.ps_tile_config(2, 3, 2, 0, None, None, None) == 0
+    assert lib.ps_tile_config(0, 2, 3, 0, None, None, None) == 0
+    assert lib.ps_tune_register(2, 2, 2, 0, 10, 0, 10, 4) == OK
+    assert lib.ps_tune_register(2, 2, 2, 0, 10, 0, 10, 5) == ARG
+    for code in (1, 2, 3):
+        assert lib.ps_tune_register(2, 3, 0, 0, 10, 0, 10, code) == OK
+    assert lib.ps_tune_register(2, 2, 0, 0, 10, 0, 10, 4) == ARG    # BITS is not a choice
+    assert lib.ps_tune_register(0, 2, 0, 0, 10, 0, 10, 2) == ARG    # float data: no path choice
     lib.ps_tune_clear()
+
+
+def test_tuned_auto_path_changes_the_workspace_query():
+    """A registered AUTO choice of the VALU path for a uint8 shape removes
+    the matrix-core path from the workspace query (AUTO with levels 1..15
+    otherwise takes the int8 path; the fp4 choice needs its planes)."""
+    f = lib.ps2_workspace_size
+    o3 = opts(levels=3)
+    base = f(2, 5000, 300, 1, o3)                 # int8 in registers: no planes
+    assert base == 0
+    assert lib.ps_tune_register(2, 2, 0, 0, 1 << 40, 0, 1 << 40, 3) == OK   # fp4
+    assert f(2, 5000, 300, 1, o3) == math.ceil(300 * 3 * math.ceil(5000 / 256) * 128 / 256) * 256
+    assert lib.ps_tune_register(2, 2, 0, 0, 1 << 40, 0, 1 << 40, 1) == OK   # VALU
+    assert f(2, 5000, 300, 1, o3) == 0
+    lib.ps_tune_clear()
+    import paper_1705_08210_amd.autotune as at
+    at.load()
 
 
 def test_batched_argument_errors():
