@@ -178,11 +178,14 @@ struct Stager {
         return load_slow<ESZ>(p, 16);
     }
 
-    template <int ESZ>
+    // VEC: rows are 16-byte aligned.  A compile-time choice, taken once per
+    // tile loop (run_tile): with both forms in one loop the compiler merges
+    // them into the 32-bit loads, which then serve aligned rows too.
+    template <int ESZ, bool VEC>
     __device__ __forceinline__ static uint4 load_chunk(const char* row_base, int64_t b0,
-                                                       int64_t nbytes, bool vec) {
+                                                       int64_t nbytes) {
         if (b0 + 16 <= nbytes)
-            return vec ? *(const uint4*)(row_base + b0) : load_unaligned<ESZ>(row_base + b0);
+            return VEC ? *(const uint4*)(row_base + b0) : load_unaligned<ESZ>(row_base + b0);
         if (b0 < nbytes) return load_slow<ESZ>(row_base + b0, nbytes - b0);
         return make_uint4(0, 0, 0, 0);
     }
@@ -190,10 +193,10 @@ struct Stager {
     // rows [row0, row0 + BM) of V, valid below row_end; field-tile byte
     // offset kb0; nbytes = n_f * element size; ldb = row pitch in bytes.
     // XJ: replace each word by min(word, word of row xrow) (X_j staging).
-    template <int DT, bool XJ>
+    template <int DT, bool XJ, bool VEC>
     __device__ __forceinline__ void load(const char* Vb, int64_t ldb, int64_t row0,
                                          int64_t row_end, int64_t kb0, int64_t nbytes,
-                                         bool vec, const char* xrow) {
+                                         const char* xrow) {
         constexpr int ESZ = Ops<DT>::kEsz;
 #pragma unroll
         for (int c = 0; c < kCh; ++c) {
@@ -203,8 +206,8 @@ struct Stager {
             const int64_t grow = row0 + row;
             const int64_t b0 = kb0 + ch * 16;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (grow < row_end) v = load_chunk<ESZ>(Vb + grow * ldb, b0, nbytes, vec);
-            if (XJ) v = xmin_chunk<DT>(v, load_chunk<ESZ>(xrow, b0, nbytes, vec));
+            if (grow < row_end) v = load_chunk<ESZ, VEC>(Vb + grow * ldb, b0, nbytes);
+            if (XJ) v = xmin_chunk<DT>(v, load_chunk<ESZ, VEC>(xrow, b0, nbytes));
             r[c] = v;
         }
     }
@@ -212,10 +215,10 @@ struct Stager {
     // Rows given per chunk (the flattened 3-way rows): roff[c] is the byte
     // offset of chunk c's row (< 0: no row, zero fill) and, with XJ, xoff[c]
     // the offset of the row v_j it is min-ed with.
-    template <int DT, bool XJ>
+    template <int DT, bool XJ, bool VEC>
     __device__ __forceinline__ void load_rows(const char* Vb, const int64_t (&roff)[kCh],
                                               const int64_t (&xoff)[kCh], int64_t kb0,
-                                              int64_t nbytes, bool vec) {
+                                              int64_t nbytes) {
         constexpr int ESZ = Ops<DT>::kEsz;
 #pragma unroll
         for (int c = 0; c < kCh; ++c) {
@@ -223,8 +226,8 @@ struct Stager {
             const int64_t b0 = kb0 + ch * 16;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (roff[c] >= 0) {
-                v = load_chunk<ESZ>(Vb + roff[c], b0, nbytes, vec);
-                if (XJ) v = xmin_chunk<DT>(v, load_chunk<ESZ>(Vb + xoff[c], b0, nbytes, vec));
+                v = load_chunk<ESZ, VEC>(Vb + roff[c], b0, nbytes);
+                if (XJ) v = xmin_chunk<DT>(v, load_chunk<ESZ, VEC>(Vb + xoff[c], b0, nbytes));
             }
             r[c] = v;
         }
@@ -267,14 +270,14 @@ __device__ __forceinline__ int lane_col(int wave, int ly, int c) {
 //   active: whether this wave does the arithmetic.
 //   [kt0, kt1): the field tiles summed (kt1 < 0: all of them).
 // ---------------------------------------------------------------------------
-template <int DT, int TM, int TN, int BKW, bool XJ>
-__device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nbytes,
-                                         bool vec, int64_t a_row0, int64_t a_end,
-                                         int64_t b_row0, int64_t b_end, const char* xrow,
-                                         bool active, typename Ops<DT>::Word* As,
-                                         typename Ops<DT>::Word* Bs,
-                                         typename Ops<DT>::Acc (&acc)[TM][TN],
-                                         int64_t kt0 = 0, int64_t kt1 = -1) {
+template <int DT, int TM, int TN, int BKW, bool XJ, bool VEC>
+__device__ __forceinline__ void run_tile_body(const char* Vb, int64_t ldb, int64_t nbytes,
+                                              int64_t a_row0, int64_t a_end, int64_t b_row0,
+                                              int64_t b_end, const char* xrow, bool active,
+                                              typename Ops<DT>::Word* As,
+                                              typename Ops<DT>::Word* Bs,
+                                              typename Ops<DT>::Acc (&acc)[TM][TN],
+                                              int64_t kt0, int64_t kt1) {
     using Acc = typename Ops<DT>::Acc;
     using Word = typename Ops<DT>::Word;
     constexpr int BM = 16 * TM, BN = 16 * TN;
@@ -304,14 +307,14 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
     SB sb;
     if (kPrefetch && kt0 < nk) {
         const int64_t kb = kt0 * tile_bytes;
-        sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
-        sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
+        sa.template load<DT, XJ, VEC>(Vb, ldb, a_row0, a_end, kb, nbytes, xrow);
+        sb.template load<DT, false, VEC>(Vb, ldb, b_row0, b_end, kb, nbytes, nullptr);
     }
     for (int64_t kt = kt0; kt < nk; ++kt) {
         if (!kPrefetch) {
             const int64_t kb = kt * tile_bytes;
-            sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
-            sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
+            sa.template load<DT, XJ, VEC>(Vb, ldb, a_row0, a_end, kb, nbytes, xrow);
+            sb.template load<DT, false, VEC>(Vb, ldb, b_row0, b_end, kb, nbytes, nullptr);
         }
         __syncthreads();  // previous tile's LDS reads are done
         sa.store(As);
@@ -319,8 +322,8 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
         __syncthreads();
         if (kPrefetch && kt + 1 < nk) {  // prefetch the next field tile into registers
             const int64_t kb = (kt + 1) * tile_bytes;
-            sa.template load<DT, XJ>(Vb, ldb, a_row0, a_end, kb, nbytes, vec, xrow);
-            sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
+            sa.template load<DT, XJ, VEC>(Vb, ldb, a_row0, a_end, kb, nbytes, xrow);
+            sb.template load<DT, false, VEC>(Vb, ldb, b_row0, b_end, kb, nbytes, nullptr);
         }
         if (!active) continue;
         constexpr int kUnroll = DT == PS_U8 ? PS_UNROLL_PLAIN / 2 : PS_UNROLL_PLAIN;
@@ -346,18 +349,36 @@ __device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nb
     }
 }
 
+// One output tile; the row alignment picks the staging loads once for the
+// whole field loop (see Stager::load_chunk).
+template <int DT, int TM, int TN, int BKW, bool XJ>
+__device__ __forceinline__ void run_tile(const char* Vb, int64_t ldb, int64_t nbytes,
+                                         bool vec, int64_t a_row0, int64_t a_end,
+                                         int64_t b_row0, int64_t b_end, const char* xrow,
+                                         bool active, typename Ops<DT>::Word* As,
+                                         typename Ops<DT>::Word* Bs,
+                                         typename Ops<DT>::Acc (&acc)[TM][TN],
+                                         int64_t kt0 = 0, int64_t kt1 = -1) {
+    if (vec)
+        run_tile_body<DT, TM, TN, BKW, XJ, true>(Vb, ldb, nbytes, a_row0, a_end, b_row0, b_end,
+                                                 xrow, active, As, Bs, acc, kt0, kt1);
+    else
+        run_tile_body<DT, TM, TN, BKW, XJ, false>(Vb, ldb, nbytes, a_row0, a_end, b_row0,
+                                                  b_end, xrow, active, As, Bs, acc, kt0, kt1);
+}
+
 // run_tile for the flattened 3-way slices: the A rows are given per staged
 // chunk (aoff / xoff as in Stager::load_rows; X_j formed per row), the B rows
 // are [b_row0, b_row0 + BN) valid below b_end.  Each field tile is loaded
 // just before it is staged (the X_j rows add loads; the other resident
 // workgroups cover the latency).
-template <int DT, int TM, int TN, int BKW>
-__device__ __forceinline__ void run_tile_flat(
-    const char* Vb, int64_t ldb, int64_t nbytes, bool vec,
+template <int DT, int TM, int TN, int BKW, bool VEC>
+__device__ __forceinline__ void run_tile_flat_body(
+    const char* Vb, int64_t ldb, int64_t nbytes,
     const int64_t (&aoff)[Stager<16 * TM, BKW, typename Ops<DT>::Word>::kCh],
     const int64_t (&xoff)[Stager<16 * TM, BKW, typename Ops<DT>::Word>::kCh], int64_t b_row0,
     int64_t b_end, bool active, typename Ops<DT>::Word* As, typename Ops<DT>::Word* Bs,
-    typename Ops<DT>::Acc (&acc)[TM][TN], int64_t kt0 = 0, int64_t kt1 = -1) {
+    typename Ops<DT>::Acc (&acc)[TM][TN], int64_t kt0, int64_t kt1) {
     using Acc = typename Ops<DT>::Acc;
     using Word = typename Ops<DT>::Word;
     constexpr int BM = 16 * TM, BN = 16 * TN;
@@ -382,8 +403,8 @@ __device__ __forceinline__ void run_tile_flat(
     SB sb;
     for (int64_t kt = kt0; kt < nk; ++kt) {
         const int64_t kb = kt * tile_bytes;
-        sa.template load_rows<DT, true>(Vb, aoff, xoff, kb, nbytes, vec);
-        sb.template load<DT, false>(Vb, ldb, b_row0, b_end, kb, nbytes, vec, nullptr);
+        sa.template load_rows<DT, true, VEC>(Vb, aoff, xoff, kb, nbytes);
+        sb.template load<DT, false, VEC>(Vb, ldb, b_row0, b_end, kb, nbytes, nullptr);
         __syncthreads();  // previous tile's LDS reads are done
         sa.store(As);
         sb.store(Bs);
@@ -410,6 +431,21 @@ __device__ __forceinline__ void run_tile_flat(
                     acc[r][c] = Ops<DT>::step(acc[r][c], a[r], b[c]);
         }
     }
+}
+
+template <int DT, int TM, int TN, int BKW>
+__device__ __forceinline__ void run_tile_flat(
+    const char* Vb, int64_t ldb, int64_t nbytes, bool vec,
+    const int64_t (&aoff)[Stager<16 * TM, BKW, typename Ops<DT>::Word>::kCh],
+    const int64_t (&xoff)[Stager<16 * TM, BKW, typename Ops<DT>::Word>::kCh], int64_t b_row0,
+    int64_t b_end, bool active, typename Ops<DT>::Word* As, typename Ops<DT>::Word* Bs,
+    typename Ops<DT>::Acc (&acc)[TM][TN], int64_t kt0 = 0, int64_t kt1 = -1) {
+    if (vec)
+        run_tile_flat_body<DT, TM, TN, BKW, true>(Vb, ldb, nbytes, aoff, xoff, b_row0, b_end,
+                                                  active, As, Bs, acc, kt0, kt1);
+    else
+        run_tile_flat_body<DT, TM, TN, BKW, false>(Vb, ldb, nbytes, aoff, xoff, b_row0, b_end,
+                                                   active, As, Bs, acc, kt0, kt1);
 }
 
 // Block index -> work index so that each XCD receives one contiguous run of
