@@ -171,6 +171,7 @@ KERNEL_SOURCES = {
     "ps_mfma2_kernel": _MFMA_SOURCES,
     "ps_mfma2_dma_kernel": _MFMA_SOURCES,
     "ps_mfma3_lv_kernel": _MFMA_SOURCES,
+    "ps_mfma3_lvs_kernel": _MFMA_SOURCES,
     "ps_mfma3_kernel": _MFMA_SOURCES,
 }
 PROFILES = os.path.join(ROOT, "profiles")
@@ -540,7 +541,8 @@ def measure(args, wl, K, W, with_cpu=True):
             kernel = "ps_mfma3_kernel"
         elif path == "mfma":
             dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
-            kernel = "ps_mfma3_lv_kernel"
+            # opts.tile 2: per-slab tiles; else the split tiling (pairs x vectors)
+            kernel = "ps_mfma3_lv_kernel" if args.tile == 2 else "ps_mfma3_lvs_kernel"
         elif V.dtype == np.uint8:
             dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
             kernel = "ps_mg3f_kernel"

@@ -107,7 +107,8 @@ typedef enum {
                             plane workspace) when levels * n_f < 2^31 for
                             levels <= 7, < 2^24 for more levels; a tile of 256
                             rows of V is addressed with 32-bit offsets, so
-                            256 * ld + 256 < 2^31 bytes.  Otherwise the
+                            256 * ld + 256 < 2^31 bytes (3-way also
+                            n_v < 2^21).  Otherwise the
                             planes are written to the workspace first (levels
                             x n_f rounded up to 128 fields per row, one byte
                             per value for int8, half a byte for FP4) and 256
@@ -306,6 +307,14 @@ void ps_plan_destroy(ps_plan* plan);
  * kernel, all 256 x 256 x 128: configuration idx walks the upper triangle in
  * groups of 2^idx block columns (tiles running side by side share rows in
  * L2); chosen through ps_tune_register only.
+ * PS_PATH_MFMA (PS_U8, way 3, register-formed levels): two tilings of the
+ * slices, both of 256 x 256 output tiles with 128-field tiles; opts.tile =
+ * 1 + idx selects one.  idx 0 (also opts.tile = 0): the split tiling, whose
+ * rows are the pairs (i, j) of slabs j < 2 n_v / 5 with columns k, and the
+ * pairs (j, k) of the later slabs with columns i, so every tile is whole;
+ * it needs n_v ld < 2^31 bytes and a pair table below 2^31 bytes, else
+ * idx 1 runs.  idx 1: per-slab tiles, whole 256 x 256 tiles inside each
+ * slab and 128 x 128 tiles over its ragged edges.
  */
 int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx,
                        int32_t* bm, int32_t* bn, int32_t* bk);

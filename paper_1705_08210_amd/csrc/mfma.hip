@@ -468,6 +468,13 @@ struct LvArgs {
     uint32_t* c3;
     int64_t item0;
     int32_t mode, ob;
+    int32_t f32div;       // 3-way: the Eq. 1 quotient is exact in FP32
+    // split 3-way tiling, part p = 0, 1: its tiles, row tiles, the prefix of
+    // their column-tile counts, and its pairs [r_begin, r_end) (colex indices
+    // for the (i, j) part, lex indices for the (j, k) part); tiles
+    // [0, nt[0]) of a launch are part 0's, the next nt[1] part 1's
+    int64_t nt[2], nrt[2], r_begin[2], r_end[2];
+    const int64_t* pre[2];
 };
 
 // Bytewise unsigned min of two words whose bytes all have bit 7 set.  Per
@@ -553,9 +560,87 @@ __device__ __forceinline__ v4i_t lv_subb(v4i_t f, uint32_t tt) {   // [v >= t]
     return r;
 }
 
-// Main loop of one fused TB x TB tile: A rows a0 .. a0+TB-1 and B rows
-// b0 .. b0+TB-1 of V (rows at or past n_v read as zero through the buffer
-// bound); with MASK the B rows are min-ed with row mj.  Staging as in
+// Staging geometry of a fused tile: each thread stages kStage 16-byte chunks
+// of each operand per field tile, chunk ch of rows row0 + c kRowStep.
+template <int WN, int TB>
+struct LvGeom {
+    static constexpr int kMThreads = mfma_threads<WN, TB>();
+    static constexpr int kRowChunks = kLvMK / 16;
+    static constexpr int kStage = TB * kRowChunks / kMThreads;
+    static constexpr int kRowStep = kMThreads / kRowChunks;
+    static_assert(TB * kRowChunks % kMThreads == 0, "staging must divide evenly");
+    __device__ static int ch() { return threadIdx.x % kRowChunks; }
+    __device__ static int row(int c) { return threadIdx.x / kRowChunks + c * kRowStep; }
+};
+
+// Row sources of the staging.  LvRows: TB consecutive rows of V from r0 (rows
+// at or past n_v read as zero through the buffer bound); with MASK each row
+// is min-ed bytewise with row mj (the 3-way X_j rows).  The host checks
+// 256 ld + 256 < 2^31, so a tile's rows take 32-bit offsets.
+template <int WN, int TB, bool ALIGNED, int MODE, bool MASK>
+struct LvRows {
+    using G = LvGeom<WN, TB>;
+    __amdgpu_buffer_rsrc_t rs, rm;
+    int voff, step;
+    uint4 mk;
+    __device__ LvRows(const LvArgs& a, int64_t r0, int64_t mj) {
+        const int64_t rows = r0 < a.n_v ? (a.n_v - r0 < TB ? a.n_v - r0 : TB) : 0;
+        rs = __builtin_amdgcn_make_buffer_rsrc((void*)(a.V + (rows > 0 ? r0 : 0) * a.ld),
+                                               (short)0, (int)(rows * a.ld), kRsrcWord3);
+        if constexpr (MASK)
+            rm = __builtin_amdgcn_make_buffer_rsrc((void*)(a.V + mj * a.ld), (short)0,
+                                                   (int)a.n_f, kRsrcWord3);
+        voff = G::row(0) * (int)a.ld + G::ch() * 16;
+        step = G::kRowStep * (int)a.ld;
+    }
+    // once per field tile (ko: its first field); nvalid = n_f - this chunk's first field
+    __device__ void prep(int ko, int nvalid) {
+        if constexpr (MASK) mk = lv_prep<MODE>(lv_load16<ALIGNED>(rm, ko + G::ch() * 16), nvalid);
+    }
+    __device__ uint4 load(int c, int ko, int nvalid) const {
+        uint4 v = lv_prep<MODE>(lv_load16<ALIGNED>(rs, voff + c * step + ko), nvalid);
+        if constexpr (MASK) {
+            v.x = lv_min<MODE>(v.x, mk.x);
+            v.y = lv_min<MODE>(v.y, mk.y);
+            v.z = lv_min<MODE>(v.z, mk.z);
+            v.w = lv_min<MODE>(v.w, mk.w);
+        }
+        return v;
+    }
+};
+
+// LvPairs: row r of the tile is a pair of rows (x, y) of V, staged as
+// min(v_x, v_y) (the 3-way rows X_y's column x, or X_x's column y).  The
+// rows come through one buffer resource over all of V (the host checks
+// n_v ld + 256 < 2^31); pair(r, x, y) gives each staged row's pair.
+template <int WN, int TB, bool ALIGNED, int MODE>
+struct LvPairs {
+    using G = LvGeom<WN, TB>;
+    __amdgpu_buffer_rsrc_t rs;
+    int ox[G::kStage], oy[G::kStage];
+    template <class F>
+    __device__ LvPairs(const LvArgs& a, F pair) {
+        rs = __builtin_amdgcn_make_buffer_rsrc((void*)a.V, (short)0, (int)(a.n_v * a.ld),
+                                               kRsrcWord3);
+#pragma unroll
+        for (int c = 0; c < G::kStage; ++c) {
+            int64_t x, y;
+            pair(G::row(c), x, y);
+            ox[c] = (int)(x * a.ld) + G::ch() * 16;
+            oy[c] = (int)(y * a.ld) + G::ch() * 16;
+        }
+    }
+    __device__ void prep(int, int) {}
+    __device__ uint4 load(int c, int ko, int nvalid) const {
+        const uint4 x = lv_prep<MODE>(lv_load16<ALIGNED>(rs, ox[c] + ko), nvalid);
+        const uint4 y = lv_prep<MODE>(lv_load16<ALIGNED>(rs, oy[c] + ko), nvalid);
+        return make_uint4(lv_min<MODE>(x.x, y.x), lv_min<MODE>(x.y, y.y),
+                          lv_min<MODE>(x.z, y.z), lv_min<MODE>(x.w, y.w));
+    }
+};
+
+// Main loop of one fused TB x TB tile: the A operand's rows (output rows)
+// from source sa, the B operand's (output columns) from sb.  Staging as in
 // mfma_tile: tile kt+1 goes from registers into the second LDS buffer while
 // tile kt is consumed, one barrier per field tile.  Inside a field tile the
 // fragments of k-step ks+1 are read while k-step ks runs; the compiler
@@ -565,19 +650,17 @@ __device__ __forceinline__ v4i_t lv_subb(v4i_t f, uint32_t tt) {   // [v >= t]
 // sched_group_barrier interleave of the transforms was 20% slower).  LC > 0
 // fixes the number of levels at compile time (0: a.levels at run time).  The
 // sums come out as counts.
-template <int WN, bool MASK, bool ALIGNED, int LC, int MODE, int TB = kMB>
-__device__ __forceinline__ void lv_tile(const LvArgs& a, int64_t a0, int64_t b0, int64_t mj,
-                                        bool active, int wr, int wc,
-                                        v16i_t (&acc)[TB / 64][WN], int8_t* lds) {
+template <int WN, bool ALIGNED, int LC, int MODE, int TB, class SA, class SB>
+__device__ __forceinline__ void lv_tile(const LvArgs& a, SA& sa, SB& sb, bool active, int wr,
+                                        int wc, v16i_t (&acc)[TB / 64][WN], int8_t* lds) {
+    using G = LvGeom<WN, TB>;
     constexpr int WM = TB / 64;
-    constexpr int kMThreads = mfma_threads<WN, TB>();
     constexpr int kMK = kLvMK;
     constexpr int KS = kMK / 32;                   // k-steps per field tile
     constexpr int kPitch = kMK + kPad;
-    constexpr int kRowChunks = kMK / 16;
-    constexpr int kStage = TB * kRowChunks / kMThreads;
-    constexpr int kRowStep = kMThreads / kRowChunks;
-    static_assert(TB * kRowChunks % kMThreads == 0, "staging must divide evenly");
+    constexpr int kStage = G::kStage;
+    constexpr int kMThreads = G::kMThreads;
+    constexpr int kRowChunks = G::kRowChunks;
     auto As = [&](int buf) { return lds + (2 * buf) * (TB * kPitch); };
     auto Bs = [&](int buf) { return lds + (2 * buf + 1) * (TB * kPitch); };
     const int lane = threadIdx.x % 64;
@@ -588,37 +671,17 @@ __device__ __forceinline__ void lv_tile(const LvArgs& a, int64_t a0, int64_t b0,
 #pragma unroll
         for (int n = 0; n < WN; ++n) acc[m][n] = (v16i_t){};
 
-    // the host checks 256 * ld + 256 < 2^31, so a tile's rows take 32-bit offsets
-    auto rsrc = [&](int64_t r0) {
-        const int64_t rows = r0 < a.n_v ? (a.n_v - r0 < TB ? a.n_v - r0 : TB) : 0;
-        return __builtin_amdgcn_make_buffer_rsrc((void*)(a.V + (rows > 0 ? r0 : 0) * a.ld),
-                                                 (short)0, (int)(rows * a.ld), kRsrcWord3);
-    };
-    const __amdgpu_buffer_rsrc_t rsa = rsrc(a0), rsb = rsrc(b0);
-    __amdgpu_buffer_rsrc_t rsm;
-    if constexpr (MASK)
-        rsm = __builtin_amdgcn_make_buffer_rsrc((void*)(a.V + mj * a.ld), (short)0, (int)a.n_f,
-                                                kRsrcWord3);
     uint4 ra[kStage], rb[kStage];
-    const int ch = threadIdx.x % kRowChunks;
-    const int ldi = (int)a.ld;
-    const int voff = (threadIdx.x / kRowChunks) * ldi + ch * 16;
+    const int ch = G::ch();
     auto load = [&](int64_t kt) {
-        const int f0 = (int)kt * kMK + ch * 16;
-        const int nvalid = (int)a.n_f - f0;
-        uint4 mk = make_uint4(0, 0, 0, 0);
-        if constexpr (MASK) mk = lv_prep<MODE>(lv_load16<ALIGNED>(rsm, f0), nvalid);
+        const int ko = (int)kt * kMK;
+        const int nvalid = (int)a.n_f - ko - ch * 16;
+        sa.prep(ko, nvalid);
+        sb.prep(ko, nvalid);
 #pragma unroll
         for (int c = 0; c < kStage; ++c) {
-            const int off = voff + c * kRowStep * ldi + (int)kt * kMK;
-            ra[c] = lv_prep<MODE>(lv_load16<ALIGNED>(rsa, off), nvalid);
-            rb[c] = lv_prep<MODE>(lv_load16<ALIGNED>(rsb, off), nvalid);
-            if constexpr (MASK) {
-                rb[c].x = lv_min<MODE>(rb[c].x, mk.x);
-                rb[c].y = lv_min<MODE>(rb[c].y, mk.y);
-                rb[c].z = lv_min<MODE>(rb[c].z, mk.z);
-                rb[c].w = lv_min<MODE>(rb[c].w, mk.w);
-            }
+            ra[c] = sa.load(c, ko, nvalid);
+            rb[c] = sb.load(c, ko, nvalid);
         }
     };
     auto store = [&](int buf) {
@@ -718,7 +781,8 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_lv_kernel(LvAr
     const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
     const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
     v16i_t acc[4][WN];
-    lv_tile<WN, false, ALIGNED, LC, MODE>(a, j0, i0, 0, active, wr, wc, acc, lds);
+    LvRows<WN, kMB, ALIGNED, MODE, false> sa(a, j0, 0), sb(a, i0, 0);
+    lv_tile<WN, ALIGNED, LC, MODE, kMB>(a, sa, sb, active, wr, wc, acc, lds);
     if (!active) return;
     MfmaArgs e{};
     e.n_v = a.n_v;
@@ -726,6 +790,125 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_lv_kernel(LvAr
     e.c2 = a.c2;
     e.n2 = a.n2;
     mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
+}
+
+// Eq. 1 on exact integers for one 3-way tile (rows k0 .. k0+TB-1, columns
+// i0 .. i0+TB-1 of slab j): n3 = n2(i,j) + n2(i,k) + n2(j,k) - n3', then
+// c3 = 3 n3 / (2 (s_i + s_j + s_k)), rounded once to FP32, 0 where the
+// denominator is 0.  The operands are integers; F32 is taken when
+// 6 levels n_f < 2^24, so numerator and denominator are exact FP32 integers
+// and the correctly rounded FP32 quotient equals the FP32 rounding of the
+// FP64 quotient (double rounding through 53 bits is innocuous for a
+// quotient of 24-bit operands); otherwise the quotient is taken in FP64 and
+// rounded to FP32.  The numerator is summed modulo 2^32 (the intermediate
+// sum can pass 2^31; n3 itself is below 2^31).
+//
+// 2 s_k and n2(j, k) of the tile's rows are staged in LDS once; n2(i, k)
+// comes through a buffer resource over the tile's rows of the pair table,
+// and the stores through one over the tile's rows of the slab: rows past
+// n_v and columns i >= j fall outside (loads read 0, stores are dropped),
+// so no branch guards an element.  Loads run one batch of rows ahead of the
+// arithmetic and stores.
+template <int TB, bool F32>
+__device__ __forceinline__ void lv3_epilogue(const LvArgs& a, const v16i_t (&acc)[TB / 64][2],
+                                             int64_t j, int64_t k0, int64_t i0, int wr, int wc,
+                                             bool active, int8_t* lds) {
+    using R = typename std::conditional<F32, float, double>::type;
+    constexpr int WN = 2, WM = TB / 64;
+    const int lane = threadIdx.x % 64;
+    const double* __restrict__ S = a.s;
+    const int32_t* __restrict__ N2 = a.n2;
+    R* rs2 = (R*)lds;                        // 2 s_k
+    int32_t* rnj = (int32_t*)(lds + TB * sizeof(R));   // n2(j, k)
+    const int64_t kend = k0 + TB < a.n_v ? k0 + TB : a.n_v;   // rows of the tile below n_v
+    if (threadIdx.x < TB) {
+        const int64_t k = k0 + threadIdx.x;
+        const bool in = k < kend;
+        rs2[threadIdx.x] = in ? (R)(2.0 * S[k]) : (R)0;
+        rnj[threadIdx.x] = in ? N2[k * (k - 1) / 2 + j] : 0;
+    }
+    __syncthreads();
+    if (!active) return;
+    // pair-table rows k0 .. kend-1: entry (k, x) at element k (k-1)/2 - c(k0) + x
+    const int64_t ck0 = k0 * (k0 - 1) / 2;
+    const __amdgpu_buffer_rsrc_t rn2 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(N2 + ck0), (short)0, (int)((kend * (kend - 1) / 2 - ck0) * 4), kRsrcWord3);
+    // slab rows k0 .. kend-1: triple (i, j, k) at element (k - k0) j + i
+    const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin) + (k0 - j - 1) * j;
+    const __amdgpu_buffer_rsrc_t rc3 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.c3 + base), (short)0, (int)((kend - k0) * j * 4), kRsrcWord3);
+    const int jj = (int)j, ki = (int)k0;
+    const R sj = (R)S[j];
+    const int64_t cj = j * (j - 1) / 2;   // n2(i, j) = N2[cj + i], i < j
+    R ls2[WN];            // 2 (s_i + s_j)
+    uint32_t nij[WN];     // n2(i, j)
+    int ioff[WN];         // byte offset of column i; out of range when i >= j
+    int icol[WN];         // column i (pair-table offset within a row)
+#pragma unroll
+    for (int n = 0; n < WN; ++n) {
+        const int64_t i = i0 + wc + n * 32 + lane % 32;
+        const bool vi = i < j;
+        ls2[n] = vi ? (R)2 * ((R)S[i] + sj) : (R)0;
+        nij[n] = vi ? (uint32_t)N2[cj + i] : 0u;
+        icol[n] = (int)i;
+        ioff[n] = vi ? (int)i * 4 : (int)0x80000000;
+    }
+    // row q of batch b: accumulator row r of block m, tile row dk
+    constexpr int RB = 8, NB = WM * 16 / RB;
+    auto row_dk = [&](int b, int q) {
+        const int m = b / (16 / RB), r = (b % (16 / RB)) * RB + q;
+        return wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
+    };
+    auto load_batch = [&](int b, uint32_t (&o)[RB][WN]) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int dk = row_dk(b, q);
+            // c(k0 + dk) - c(k0) = dk (dk + 2 k0 - 1) / 2
+            const int roff = (int)(((uint32_t)dk * (uint32_t)(dk + 2 * ki - 1)) >> 1);
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+                o[q][n] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                    rn2, (roff + icol[n]) * 4, 0, 0);
+        }
+    };
+    auto store_batch = [&](int b, const uint32_t (&o)[RB][WN]) {
+        const int m = b / (16 / RB);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = (b % (16 / RB)) * RB + q;
+            const int dk = row_dk(b, q);
+            const R rk = rs2[dk];
+            const uint32_t njk = (uint32_t)rnj[dk];
+            const int soff = dk * jj * 4;
+#pragma unroll
+            for (int n = 0; n < WN; ++n) {
+                const uint32_t n3 = nij[n] + njk + o[q][n] - (uint32_t)acc[m][n][r];
+                // denominators are even integers: d = 0 or d >= 2; the
+                // quotient is formed unconditionally (no branch) and d = 0
+                // selects 0
+                const R d = ls2[n] + rk;
+                const R dd = d > (R)0 ? d : (R)1;
+                float q;
+                if constexpr (F32)
+                    q = (float)(3u * n3) / dd;
+                else
+                    q = (float)((3.0 * (double)n3) / dd);
+                const float c = d > (R)0 ? q : 0.0f;
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, c), rc3,
+                                                      (int)((uint32_t)soff + (uint32_t)ioff[n]),
+                                                      0, 0);
+            }
+        }
+    };
+    uint32_t bt[2][RB][WN];
+    load_batch(0, bt[0]);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB) load_batch(b + 1, bt[(b + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        store_batch(b, bt[b & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 template <int TB, bool ALIGNED, int LC, int MODE>
@@ -749,53 +932,98 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_lv
     const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
     const bool active = (k0 + wr < a.n_v) && (i0 + wc < j);
     v16i_t acc[WM][WN];
-    lv_tile<WN, true, ALIGNED, LC, MODE, TB>(a, k0, i0, j, active, wr, wc, acc, lds);
-    if (!active) return;
-    // Eq. 1 on exact integers: n3 = n2(i,j) + n2(i,k) + n2(j,k) - n3', then
-    // c3 = 3 n3 / (2 (s_i + s_j + s_k)) in FP64, rounded once to FP32 (d = 0
-    // gives 0).  Every operand is an integer below 2^53, so the FP64 quotient
-    // is the correctly rounded one whatever the order of the sums.  The
-    // operands of a 32-row block are loaded together before any of its
-    // stores (the stores could alias them for all the compiler knows, which
-    // would otherwise serialise one load round trip per row).
-    const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin);
-    const int64_t ib = i0 + wc + (lane % 32);
+    LvRows<WN, TB, ALIGNED, MODE, false> sa(a, k0, 0);
+    LvRows<WN, TB, ALIGNED, MODE, true> sb(a, i0, j);
+    lv_tile<WN, ALIGNED, LC, MODE, TB>(a, sa, sb, active, wr, wc, acc, lds);
+    // The main loop ended on a barrier after its last LDS read, so the LDS is
+    // free: the per-row operands of Eq. 1 for the tile's TB rows k go there
+    // (every wave takes part in the staging and its barrier).
+    if (a.f32div)
+        lv3_epilogue<TB, true>(a, acc, j, k0, i0, wr, wc, active, lds);
+    else
+        lv3_epilogue<TB, false>(a, acc, j, k0, i0, wr, wc, active, lds);
+}
+
+
+// ---------------------------------------------------------------------------
+// Split tiling of the fused 3-way slices (mfma3_split): every tile is a whole
+// 256 x 256 tile of pairs x single vectors, so no slab edge needs narrower
+// tiles.  Part 0: output columns are the colex pairs (i, j), j < js, staged
+// as min(v_i, v_j); output rows are k from the row tile's smallest j + 1.
+// Part 1: output rows are the lex pairs (j, k), j >= js, staged as
+// min(v_j, v_k); output columns are i from 0 below the row tile's largest j.
+// Entries outside i < j < k < n_v are computed by waves that also hold wanted
+// ones and are never stored (a wave with none skips the multiply-adds).
+// ---------------------------------------------------------------------------
+
+// Part 0 epilogue (Eq. 1 as in lv3_epilogue): a lane's two columns are pairs
+// (i, j) with their own j, so n2(j, k) is gathered per element like n2(i, k);
+// 2 s_k of the tile's rows is staged in LDS.  Stores go through a buffer
+// resource from the tile's first entry (0, jmin, k0) to the end of the last
+// pair's slab; an element outside i < j < k < n_v gets an offset past it.
+template <bool F32>
+__device__ __forceinline__ void lvs_epilogue0(const LvArgs& a, const v16i_t (&acc)[4][2],
+                                              int64_t p0, int64_t k0, int wr, int wc,
+                                              bool active, int8_t* lds) {
+    using R = typename std::conditional<F32, float, double>::type;
+    constexpr int TB = kMB, WN = 2, WM = 4;
+    const int lane = threadIdx.x % 64;
+    const int64_t n = a.n_v;
     const double* __restrict__ S = a.s;
     const int32_t* __restrict__ N2 = a.n2;
-    float* __restrict__ c3 = (float*)a.c3;
-    const double sj = S[j];
-    const int64_t cj = j * (j - 1) / 2;   // n2(i, j) = N2[cj + i], i < j
-    double si[WN];
-    int64_t nij[WN];
-#pragma unroll
-    for (int n = 0; n < WN; ++n) {
-        const int64_t i = ib + n * 32;
-        si[n] = i < j ? S[i] : 0.0;
-        nij[n] = i < j ? N2[cj + i] : 0;
+    R* rs2 = (R*)lds;   // 2 s_k
+    if (threadIdx.x < TB) {
+        const int64_t k = k0 + threadIdx.x;
+        rs2[threadIdx.x] = k < n ? (R)(2.0 * S[k]) : (R)0;
     }
-    // rows of the accumulators in batches of RB: the loads of batch b+1 are
-    // issued before batch b is computed and stored (two register sets)
+    __syncthreads();
+    if (!active) return;
+    const int64_t pe = a.r_end[0];
+    const int64_t jmin = pair_j(p0);
+    const int64_t jlast = pair_j(p0 + TB - 1 < pe ? p0 + TB - 1 : pe - 1);
+    const int64_t ob = slab_offset(n, a.j_begin);
+    const int64_t base0 = slab_offset(n, jmin) - ob + (k0 - jmin - 1) * jmin;
+    const __amdgpu_buffer_rsrc_t rc3 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.c3 + base0), (short)0, (int)((slab_offset(n, jlast + 1) - ob - base0) * 4),
+        kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rn2 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)N2, (short)0, (int)(n * (n - 1) / 2 * 4), kRsrcWord3);
+    R ls2[WN];            // 2 (s_i + s_j)
+    uint32_t nij[WN];     // n2(i, j)
+    int ii[WN], jj[WN];   // the column's pair; jj = n_v when past the part
+    uint32_t sb[WN];      // entry (i, j, k) - base0 = sb + k j (mod 2^32)
+#pragma unroll
+    for (int nn = 0; nn < WN; ++nn) {
+        const int64_t p = p0 + wc + nn * 32 + lane % 32;
+        const bool vp = p < pe;
+        const int64_t pp = vp ? p : pe - 1;
+        const int64_t j = pair_j(pp), i = pp - j * (j - 1) / 2;
+        ls2[nn] = (R)2 * ((R)S[i] + (R)S[j]);
+        nij[nn] = (uint32_t)N2[pp];
+        ii[nn] = (int)i;
+        jj[nn] = vp ? (int)j : (int)n;
+        sb[nn] = (uint32_t)(slab_offset(n, j) - ob - base0 - (j + 1) * j + i);
+    }
     constexpr int RB = 4, NB = WM * 16 / RB;
-    struct Batch {
-        double sk[RB];
-        int32_t njk[RB], nik[RB][WN];
-    };
-    auto row_k = [&](int b, int q) {   // k of row q of batch b
+    auto row_dk = [&](int b, int q) {
         const int m = b / (16 / RB), r = (b % (16 / RB)) * RB + q;
-        return k0 + wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
+        return wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
     };
+    struct Batch {
+        uint32_t nik[RB][WN], njk[RB][WN];
+    };
+    const int kb = (int)k0;
     auto load_batch = [&](int b, Batch& o) {
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            int64_t k = row_k(b, q);
-            if (k >= a.n_v) k = a.n_v - 1;   // loaded but not stored
-            const int64_t ck = k * (k - 1) / 2;   // n2(x, k) = N2[ck + x], x < k
-            o.sk[q] = S[k];
-            o.njk[q] = N2[ck + j];
+            const uint32_t k = (uint32_t)(kb + row_dk(b, q));
+            const uint32_t ck = (k * (k - 1)) >> 1;   // k < 2^16: the table is below 2^31 bytes
 #pragma unroll
-            for (int n = 0; n < WN; ++n) {
-                const int64_t i = ib + n * 32;
-                o.nik[q][n] = N2[ck + (i < j ? i : 0)];
+            for (int nn = 0; nn < WN; ++nn) {
+                o.nik[q][nn] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                    rn2, (int)((ck + (uint32_t)ii[nn]) * 4), 0, 0);
+                o.njk[q][nn] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                    rn2, (int)((ck + (uint32_t)jj[nn]) * 4), 0, 0);
             }
         }
     };
@@ -804,17 +1032,25 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_lv
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
             const int r = (b % (16 / RB)) * RB + q;
-            const int64_t k = row_k(b, q);
-            if (k >= a.n_v) continue;
-            float* row = c3 + base + (k - j - 1) * j;
+            const int dk = row_dk(b, q);
+            const int k = kb + dk;
+            const R rk = rs2[dk];
 #pragma unroll
-            for (int n = 0; n < WN; ++n) {
-                const int64_t i = ib + n * 32;
-                if (i >= j) continue;
-                const int64_t n3 =
-                    nij[n] + (int64_t)o.nik[q][n] + (int64_t)o.njk[q] - (int64_t)acc[m][n][r];
-                const double d3 = (si[n] + sj) + o.sk[q];
-                row[i] = d3 > 0.0 ? (float)((3.0 * (double)n3) / (2.0 * d3)) : 0.0f;
+            for (int nn = 0; nn < WN; ++nn) {
+                const bool ok = k > jj[nn] && k < (int)n;
+                const uint32_t n3 = nij[nn] + o.nik[q][nn] + o.njk[q][nn] - (uint32_t)acc[m][nn][r];
+                const R d = ls2[nn] + rk;
+                const R dd = d > (R)0 ? d : (R)1;
+                float qv;
+                if constexpr (F32)
+                    qv = (float)(3u * n3) / dd;
+                else
+                    qv = (float)((3.0 * (double)n3) / dd);
+                const float c = d > (R)0 ? qv : 0.0f;
+                const uint32_t off = ok ? (sb[nn] + (uint32_t)k * (uint32_t)jj[nn]) * 4u
+                                        : 0x80000000u;
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, c), rc3,
+                                                      (int)off, 0, 0);
             }
         }
     };
@@ -827,6 +1063,185 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_lv
         store_batch(b, bt[b & 1]);
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// Part 1 epilogue: a row is a pair (j, k); its 2 (s_j + s_k), n2(j, k), the
+// pair-table offsets of rows j and k, j and its output row offset are staged
+// in LDS once per tile; n2(i, j) and n2(i, k) are gathered per element
+// (contiguous in i).  Stores from the tile's first pair's entry i = 0 to the
+// end of the last pair's slab; columns i >= j get an offset past it.
+template <bool F32>
+__device__ __forceinline__ void lvs_epilogue1(const LvArgs& a, const v16i_t (&acc)[4][2],
+                                              int64_t q0, int64_t i0, int wr, int wc,
+                                              bool active, int8_t* lds) {
+    using R = typename std::conditional<F32, float, double>::type;
+    constexpr int TB = kMB, WN = 2, WM = 4;
+    const int lane = threadIdx.x % 64;
+    const int64_t n = a.n_v;
+    const double* __restrict__ S = a.s;
+    const int32_t* __restrict__ N2 = a.n2;
+    const int64_t qe = a.r_end[1];
+    const int64_t ob = slab_offset(n, a.j_begin);
+    int64_t jf, kf, jl, kl;
+    lex_pair(n, q0, jf, kf);
+    lex_pair(n, q0 + TB - 1 < qe ? q0 + TB - 1 : qe - 1, jl, kl);
+    const int64_t base0 = slab_offset(n, jf) - ob + (kf - jf - 1) * jf;
+    int4* rowi = (int4*)lds;                         // {c(j), c(k), j, output row offset}
+    R* rs2 = (R*)(lds + TB * sizeof(int4));           // 2 (s_j + s_k)
+    int32_t* rnj = (int32_t*)(lds + TB * (sizeof(int4) + sizeof(R)));   // n2(j, k)
+    if (threadIdx.x < TB) {
+        const int64_t q = q0 + threadIdx.x;
+        const bool vq = q < qe;
+        int64_t j, k;
+        lex_pair(n, vq ? q : qe - 1, j, k);
+        const int64_t cj = j * (j - 1) / 2, ck = k * (k - 1) / 2;
+        rowi[threadIdx.x] = make_int4((int)cj, (int)ck, vq ? (int)j : 0,
+                                      (int)(slab_offset(n, j) - ob + (k - j - 1) * j - base0));
+        rs2[threadIdx.x] = (R)2 * ((R)S[j] + (R)S[k]);
+        rnj[threadIdx.x] = N2[ck + j];
+    }
+    __syncthreads();
+    if (!active) return;
+    const __amdgpu_buffer_rsrc_t rc3 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.c3 + base0), (short)0, (int)((slab_offset(n, jl + 1) - ob - base0) * 4),
+        kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rn2 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)N2, (short)0, (int)(n * (n - 1) / 2 * 4), kRsrcWord3);
+    R ls[WN];        // 2 s_i
+    int ii[WN];
+#pragma unroll
+    for (int nn = 0; nn < WN; ++nn) {
+        const int64_t i = i0 + wc + nn * 32 + lane % 32;
+        ls[nn] = (R)(2.0 * S[i < n ? i : n - 1]);
+        ii[nn] = (int)i;
+    }
+    constexpr int RB = 4, NB = WM * 16 / RB;
+    auto row_dk = [&](int b, int q) {
+        const int m = b / (16 / RB), r = (b % (16 / RB)) * RB + q;
+        return wr + m * 32 + (r / 4) * 8 + (lane / 32) * 4 + (r % 4);
+    };
+    struct Batch {
+        uint32_t nij[RB][WN], nik[RB][WN];
+        int4 ri[RB];
+    };
+    auto load_batch = [&](int b, Batch& o) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int4 ri = rowi[row_dk(b, q)];
+            o.ri[q] = ri;
+#pragma unroll
+            for (int nn = 0; nn < WN; ++nn) {
+                o.nij[q][nn] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                    rn2, (int)(((uint32_t)ri.x + (uint32_t)ii[nn]) * 4), 0, 0);
+                o.nik[q][nn] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(
+                    rn2, (int)(((uint32_t)ri.y + (uint32_t)ii[nn]) * 4), 0, 0);
+            }
+        }
+    };
+    auto store_batch = [&](int b, const Batch& o) {
+        const int m = b / (16 / RB);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = (b % (16 / RB)) * RB + q;
+            const int dk = row_dk(b, q);
+            const R rr = rs2[dk];
+            const uint32_t njk = (uint32_t)rnj[dk];
+            const int4 ri = o.ri[q];
+#pragma unroll
+            for (int nn = 0; nn < WN; ++nn) {
+                const bool ok = ii[nn] < ri.z;
+                const uint32_t n3 = o.nij[q][nn] + o.nik[q][nn] + njk - (uint32_t)acc[m][nn][r];
+                const R d = ls[nn] + rr;
+                const R dd = d > (R)0 ? d : (R)1;
+                float qv;
+                if constexpr (F32)
+                    qv = (float)(3u * n3) / dd;
+                else
+                    qv = (float)((3.0 * (double)n3) / dd);
+                const float c = d > (R)0 ? qv : 0.0f;
+                const uint32_t off =
+                    ok ? ((uint32_t)ri.w + (uint32_t)ii[nn]) * 4u : 0x80000000u;
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, c), rc3,
+                                                      (int)off, 0, 0);
+            }
+        }
+    };
+    Batch bt[2];
+    load_batch(0, bt[0]);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB) load_batch(b + 1, bt[(b + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        store_batch(b, bt[b & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// One tile t of part PART of the split tiling.
+template <int PART, bool ALIGNED, int LC, int MODE>
+__device__ __forceinline__ void lvs_tile(const LvArgs& a, int64_t t, int8_t* lds) {
+    constexpr int TB = kMB, WN = 2, WM = TB / 64;
+    // row tile: the largest rt with prefix[rt] <= t
+    const int64_t* pre = a.pre[PART];
+    int64_t lo = 0, hi = a.nrt[PART];
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (pre[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int64_t ct = t - pre[lo];
+    const int64_t n = a.n_v;
+    const int64_t r0 = a.r_begin[PART] + lo * TB, re = a.r_end[PART];
+    const int wave = threadIdx.x / 64;
+    const int wr = (wave % 2) * (TB / 2);   // the wave's output rows
+    const int wc = (wave / 2) * 32 * WN;    // its output columns
+    v16i_t acc[WM][WN];
+    if constexpr (PART == 0) {
+        const int64_t k0 = pair_j(r0) + 1 + ct * TB;
+        const int64_t pq = r0 + wc;
+        const int64_t kq = k0 + wr + TB / 2 - 1 < n - 1 ? k0 + wr + TB / 2 - 1 : n - 1;
+        const bool active = k0 + wr < n && pq < re && pair_j(pq) < kq;
+        LvRows<WN, TB, ALIGNED, MODE, false> sa(a, k0, 0);
+        LvPairs<WN, TB, ALIGNED, MODE> sb(a, [&](int r, int64_t& x, int64_t& y) {
+            const int64_t p = r0 + r < re ? r0 + r : re - 1;
+            y = pair_j(p);
+            x = p - y * (y - 1) / 2;
+        });
+        lv_tile<WN, ALIGNED, LC, MODE, TB>(a, sa, sb, active, wr, wc, acc, lds);
+        if (a.f32div)
+            lvs_epilogue0<true>(a, acc, r0, k0, wr, wc, active, lds);
+        else
+            lvs_epilogue0<false>(a, acc, r0, k0, wr, wc, active, lds);
+    } else {
+        const int64_t i0 = ct * TB;
+        const int64_t qa = r0 + wr;
+        const int64_t qz = qa + TB / 2 - 1 < re ? qa + TB / 2 - 1 : re - 1;
+        int64_t jz, kz;
+        lex_pair(n, qz, jz, kz);
+        const bool active = qa < re && i0 + wc < jz;
+        LvPairs<WN, TB, ALIGNED, MODE> sa(a, [&](int r, int64_t& x, int64_t& y) {
+            lex_pair(n, r0 + r < re ? r0 + r : re - 1, x, y);
+        });
+        LvRows<WN, TB, ALIGNED, MODE, false> sb(a, i0, 0);
+        lv_tile<WN, ALIGNED, LC, MODE, TB>(a, sa, sb, active, wr, wc, acc, lds);
+        if (a.f32div)
+            lvs_epilogue1<true>(a, acc, r0, i0, wr, wc, active, lds);
+        else
+            lvs_epilogue1<false>(a, acc, r0, i0, wr, wc, active, lds);
+    }
+}
+
+// Both parts in one launch (one tail instead of two): tiles [0, nt[0]) are
+// part 0's, the rest part 1's.
+template <bool ALIGNED, int LC, int MODE>
+__global__ __launch_bounds__(mfma_threads<2>(), 1) void ps_mfma3_lvs_kernel(LvArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[4 * kMB * (kLvMK + kPad)];
+    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                      blockIdx.x / kXcds;
+    if (t >= a.ntiles) return;
+    if (t < a.nt[0])
+        lvs_tile<0, ALIGNED, LC, MODE>(a, t, lds);
+    else
+        lvs_tile<1, ALIGNED, LC, MODE>(a, t - a.nt[0], lds);
 }
 
 static LvArgs lv_args(const MfmaLaunch& m) {
@@ -862,8 +1277,45 @@ static hipError_t go_mfma2_lv(const MfmaLaunch& m, hipStream_t st) {
     });
 }
 
+// The split tiling (mfma3_split): part 0 over the colex pairs of slabs
+// [j_begin, js), part 1 over the lex pairs of slabs [js, j_end), in one
+// launch, each part with the prefix of its row tiles' column-tile counts
+// (part 1's after part 0's in the prefix workspace).
+template <bool ALIGNED, int LC, int MODE>
+static hipError_t go_mfma3_lvs(const MfmaLaunch& m, hipStream_t st) {
+    const int64_t n = m.n_v, jb = m.j_begin, je = m.j_end, js = mfma3_split(n, jb, je);
+    LvArgs a = lv_args(m);   // a.n2: the pair numerators of Eq. 1
+    a.j_begin = jb;
+    a.j_end = je;
+    a.f32div = 6 * (int64_t)m.levels * m.n_f < ((int64_t)1 << 24);
+    a.c3 = (uint32_t*)m.c3;
+    a.nrt[0] = flat_row_tiles(jb, js, kMB);
+    a.nrt[1] = lex_row_tiles(n, js, je, kMB);
+    a.pre[0] = m.prefix;
+    a.pre[1] = m.prefix + a.nrt[0] + 1;
+    a.r_begin[0] = jb * (jb - 1) / 2;
+    a.r_end[0] = js * (js - 1) / 2;
+    a.r_begin[1] = lex_first(n, js);
+    a.r_end[1] = lex_first(n, je);
+    a.nt[0] = a.nrt[0] > 0 ? flat_tiles(n, jb, js, kMB) : 0;
+    a.nt[1] = a.nrt[1] > 0 ? lex_tiles(n, js, je, kMB) : 0;
+    hipError_t e = hipSuccess;
+    if (a.nrt[0] > 0) e = launch_prefix3_flat(n, jb, js, kMB, m.prefix, st);
+    if (e == hipSuccess && a.nrt[1] > 0)
+        e = launch_prefix3_flat(n, js, je, kMB, m.prefix + a.nrt[0] + 1, st, true);
+    if (e != hipSuccess) return e;
+    a.ntiles = a.nt[0] + a.nt[1];
+    return launch_items(a.ntiles, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+        LvArgs b = a;
+        b.item0 = item0;
+        hipLaunchKernelGGL((ps_mfma3_lvs_kernel<ALIGNED, LC, MODE>), dim3(grid),
+                           dim3(mfma_threads<2>()), 0, st, b);
+    });
+}
+
 template <bool ALIGNED, int LC, int MODE>
 static hipError_t go_mfma3_lv(const MfmaLaunch& m, hipStream_t st) {
+    if (!m.slab3 && mfma3_split_ok(m.n_v, m.ld)) return go_mfma3_lvs<ALIGNED, LC, MODE>(m, st);
     constexpr int kEdge = kMB / 2;
     hipError_t e = launch_prefix3(m.n_v, m.j_begin, m.j_end, kMB, kSlabFull, kMB, m.prefix, st);
     if (e == hipSuccess)
@@ -872,6 +1324,7 @@ static hipError_t go_mfma3_lv(const MfmaLaunch& m, hipStream_t st) {
     LvArgs a = lv_args(m);   // a.n2: the pair numerators of Eq. 1
     a.j_begin = m.j_begin;
     a.j_end = m.j_end;
+    a.f32div = 6 * (int64_t)m.levels * m.n_f < ((int64_t)1 << 24);
     a.c3 = (uint32_t*)m.c3;
     a.prefix = m.prefix;
     a.mode = kSlabFull;

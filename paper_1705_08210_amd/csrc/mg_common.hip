@@ -343,18 +343,23 @@ hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Exclusive prefix of the column-tile counts of the flattened row tiles
-// (one workgroup; 1024 threads each own a contiguous run of row tiles).
+// Exclusive prefix of the column-tile counts of the flattened (colex) or the
+// lex-ordered row tiles (one workgroup; 1024 threads each own a contiguous
+// run of row tiles).
+__device__ __forceinline__ int64_t prefix3_cols(int64_t n_v, int64_t jb, int64_t je, int bm,
+                                                bool lex, int64_t rt) {
+    return lex ? lex_col_tiles(n_v, jb, je, bm, rt) : flat_col_tiles(n_v, jb, bm, rt);
+}
 __global__ __launch_bounds__(1024) void ps_prefix3_flat_kernel(int64_t n_v, int64_t jb,
-                                                               int64_t je, int bm,
+                                                               int64_t je, int bm, int lex,
                                                                int64_t* prefix) {
     __shared__ int64_t part[1024];
-    const int64_t nr = flat_row_tiles(jb, je, bm);
+    const int64_t nr = lex ? lex_row_tiles(n_v, jb, je, bm) : flat_row_tiles(jb, je, bm);
     const int64_t per = (nr + 1023) / 1024;
     const int64_t lo = (int64_t)threadIdx.x * per;
     const int64_t hi = lo + per < nr ? lo + per : nr;
     int64_t sum = 0;
-    for (int64_t t = lo; t < hi; ++t) sum += flat_col_tiles(n_v, jb, bm, t);
+    for (int64_t t = lo; t < hi; ++t) sum += prefix3_cols(n_v, jb, je, bm, lex, t);
     part[threadIdx.x] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -369,16 +374,16 @@ __global__ __launch_bounds__(1024) void ps_prefix3_flat_kernel(int64_t n_v, int6
     int64_t run = part[threadIdx.x];
     for (int64_t t = lo; t < hi; ++t) {
         prefix[t] = run;
-        run += flat_col_tiles(n_v, jb, bm, t);
+        run += prefix3_cols(n_v, jb, je, bm, lex, t);
     }
     if (hi == nr && lo < hi) prefix[nr] = run;
     if (nr == 0 && threadIdx.x == 0) prefix[0] = 0;
 }
 
 hipError_t launch_prefix3_flat(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
-                               hipStream_t st) {
+                               hipStream_t st, bool lex) {
     hipLaunchKernelGGL(ps_prefix3_flat_kernel, dim3(1), dim3(1024), 0, st, n_v, jb, je, bm,
-                       prefix);
+                       lex ? 1 : 0, prefix);
     return hipGetLastError();
 }
 
@@ -386,6 +391,13 @@ int64_t flat_tiles(int64_t n_v, int64_t jb, int64_t je, int bm) {
     int64_t t = 0;
     const int64_t nr = flat_row_tiles(jb, je, bm);
     for (int64_t rt = 0; rt < nr; ++rt) t += flat_col_tiles(n_v, jb, bm, rt);
+    return t;
+}
+
+int64_t lex_tiles(int64_t n_v, int64_t jb, int64_t je, int bm) {
+    int64_t t = 0;
+    const int64_t nr = lex_row_tiles(n_v, jb, je, bm);
+    for (int64_t rt = 0; rt < nr; ++rt) t += lex_col_tiles(n_v, jb, je, bm, rt);
     return t;
 }
 

@@ -129,10 +129,12 @@ int64_t max_grid_blocks(int threads, int64_t multiple) {
 bool is_mfma(int path) { return path == PS_PATH_MFMA || path == PS_PATH_MFMA_FP4; }
 
 // Whether a matrix-core path can take the shape (exact sums, 32-bit offsets).
-static bool mfma_can(int path, int64_t n_f, int levels, int wide, int64_t ld) {
+static bool mfma_can(int path, int way, int64_t n_f, int64_t n_v, int levels, int wide,
+                     int64_t ld) {
     if (path == PS_PATH_MFMA_FP4)
         return (int64_t)levels * n_f < ((int64_t)1 << 24) && mfma_row_fits(n_f, levels, 1);
-    if (mfma_fused(n_f, levels, 0, wide)) return mfma_ld_fits(ld);
+    if (mfma_fused(n_f, levels, 0, wide))
+        return mfma_ld_fits(ld) && (way != 3 || mfma3_nv_fits(n_v));
     return (int64_t)levels * n_f < ((int64_t)1 << 31) && mfma_row_fits(n_f, levels, 0);
 }
 
@@ -151,12 +153,14 @@ int choose_path(int32_t dt, const ps_opts* o, int way, int64_t n_f, int64_t n_v,
     if (p == PS_PATH_VALU || p == PS_PATH_MFMA || p == PS_PATH_MFMA_FP4 || p == PS_PATH_BITS)
         return p;
     if (dt != PS_U8 || !o || o->levels < 1 || o->levels > 15) return PS_PATH_VALU;
-    const int wide = o->tile == 2;
+    const int wide = way == 2 && o->tile == 2;   // 3-way: tile 2 picks the slab tiles
     const int t = tuned(dt, way, PS_PATH_AUTO, n_f, n_v);
     if (t == PS_PATH_VALU) return PS_PATH_VALU;
-    if ((t == PS_PATH_MFMA || t == PS_PATH_MFMA_FP4) && mfma_can(t, n_f, o->levels, wide, ld))
+    if ((t == PS_PATH_MFMA || t == PS_PATH_MFMA_FP4) &&
+        mfma_can(t, way, n_f, n_v, o->levels, wide, ld))
         return t;
-    return mfma_can(PS_PATH_MFMA, n_f, o->levels, wide, ld) ? PS_PATH_MFMA : PS_PATH_VALU;
+    return mfma_can(PS_PATH_MFMA, way, n_f, n_v, o->levels, wide, ld) ? PS_PATH_MFMA
+                                                                      : PS_PATH_VALU;
 }
 
 int mfma_group(int64_t n_f, int64_t n_v) {
@@ -173,6 +177,15 @@ extern "C" {
 int32_t ps_tile_config(int32_t dtype, int32_t way, int32_t path, int32_t idx, int32_t* bm,
                        int32_t* bn, int32_t* bk) {
     if (elem_size(dtype) == 0 || (way != 2 && way != 3)) return 0;
+    if (path == PS_PATH_MFMA && way == 3) {   // tilings of the fused 3-way int8 slices
+        if (dtype != PS_U8) return 0;
+        if (idx >= 0 && idx < 2) {
+            if (bm) *bm = kMfmaTile;
+            if (bn) *bn = kMfmaTile;
+            if (bk) *bk = 128;
+        }
+        return 2;
+    }
     if (path == PS_PATH_MFMA) {   // tile orders of the 2-way int8 kernel, 256 x 256 x 128
         if (dtype != PS_U8 || way != 2) return 0;
         if (idx >= 0 && idx < kNumMfmaCfgs) {

@@ -302,7 +302,9 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
 // the flattened row tiles of the VALU slices at the smallest tile edge (64).
 static int64_t prefix3_entries(int64_t n_v, int64_t jb, int64_t je) {
     const int64_t flat = flat_row_tiles(jb, je, 64) + 1;
-    return 2 * (n_v + 1) > flat ? 2 * (n_v + 1) : flat;
+    const int64_t split = flat_row_tiles(jb, je, kMfmaTile) + lex_row_tiles(n_v, jb, je, kMfmaTile) + 2;
+    const int64_t m = flat > split ? flat : split;
+    return 2 * (n_v + 1) > m ? 2 * (n_v + 1) : m;
 }
 
 static size_t ws3_layout(int64_t n_v, int64_t npre, int32_t s_given, int32_t n2_given,
@@ -336,7 +338,7 @@ static size_t ws3_layout(int64_t n_v, int64_t npre, int32_t s_given, int32_t n2_
 // Eq. 1 from exact integers.
 static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, const double* s,
                           const void* n2, int64_t j_begin, int64_t j_end, float* c3,
-                          void* workspace, size_t ws_bytes, int path, int levels,
+                          void* workspace, size_t ws_bytes, int path, int levels, int tile,
                           hipStream_t stream) {
     const int fmt = path == PS_PATH_MFMA_FP4 ? 1 : 0;
     const int64_t stage = ps3_stage_size(n_v, j_begin, j_end);
@@ -369,6 +371,7 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
         m.expand = 0;
     }
     m.n2 = (void*)n2;   // the pair numerators of Eq. 1
+    m.slab3 = tile == 2;
     e = launch_mfma3(m, stream);
     if (e != hipSuccess) return hip_fail(e, "3-way mfma launch");
     if (mfma_fused(n_f, levels, fmt, 0)) return PS_OK;   // Eq. 1 applied in the slices
@@ -495,6 +498,10 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     const int path = choose_path(dtype, opts, 3, n_f, n_v, ld);
     const int levels = opts ? opts->levels : 0;
     if ((st = check_mfma(path, dtype, levels, n_f, ld, 0)) != PS_OK) return st;
+    if (path == PS_PATH_MFMA && mfma_fused(n_f, levels, 0, 0) && !mfma3_nv_fits(n_v))
+        return fail(PS_ERR_UNSUPPORTED,
+                    "3-way int8 MFMA path: n_v = %lld is too large for the 32-bit offsets of "
+                    "its epilogue (n_v < 2^21); use the VALU path", (long long)n_v);
     if ((st = check_int_range(path, dtype, n_f)) != PS_OK) return st;
     if (n_v < 3) return PS_OK;
     if (j_begin < 1 || j_end > n_v - 1 || j_begin > j_end)
@@ -519,7 +526,7 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     int64_t* prefix = nullptr;
     float* partial = nullptr;
     if (is_mfma(path)) return ps3_mfma(V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, workspace,
-                                       ws_bytes, path, levels, stream);
+                                       ws_bytes, path, levels, opts ? opts->tile : 0, stream);
     const bool bits = is_bits(opts);
     const int32_t kdt = bits ? PS_B1 : dtype;   // operand type of the kernels
     const int cfg2 = choose_cfg(kdt, 2, bits ? PS_PATH_BITS : PS_PATH_VALU, n_f, n_v, opts);

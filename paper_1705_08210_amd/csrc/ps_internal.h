@@ -104,6 +104,37 @@ __host__ __device__ inline int64_t flat_col_tiles(int64_t n_v, int64_t jb, int b
     return w > 0 ? (w + bm - 1) / bm : 0;
 }
 
+// Lex order of the pairs (j, k), j < k < n: first index ascending, then k.
+// lex_first(n, j) pairs precede those with first index j; lex_pair inverts
+// the order through the colex index of the mirrored pair (n-1-k, n-1-j).
+__host__ __device__ inline int64_t lex_first(int64_t n, int64_t j) {
+    return j * (n - 1) - j * (j - 1) / 2;
+}
+__host__ __device__ inline void lex_pair(int64_t n, int64_t q, int64_t& j, int64_t& k) {
+    const int64_t p = n * (n - 1) / 2 - 1 - q;
+    const int64_t kk = pair_j(p);
+    j = n - 1 - kk;
+    k = n - 1 - (p - kk * (kk - 1) / 2);
+}
+// Lex-ordered 3-way tiling (the second part of the split tiling of the
+// fused int8 slices): the rows are the pairs (j, k), jb <= j < je, in lex
+// order; row tile rt (bm consecutive pairs) is paired with the column tiles
+// i in [c bm, (c + 1) bm) below the j of its last pair.  Entries with i >= j
+// are not stored; every triple of the rows' slabs lies in exactly one tile.
+__host__ __device__ inline int64_t lex_row_tiles(int64_t n, int64_t jb, int64_t je, int bm) {
+    const int64_t rows = lex_first(n, je) - lex_first(n, jb);
+    return rows > 0 ? (rows + bm - 1) / bm : 0;
+}
+__host__ __device__ inline int64_t lex_col_tiles(int64_t n, int64_t jb, int64_t je, int bm,
+                                                 int64_t rt) {
+    int64_t q = lex_first(n, jb) + (rt + 1) * bm - 1;
+    const int64_t qe = lex_first(n, je) - 1;
+    if (q > qe) q = qe;
+    int64_t j, k;
+    lex_pair(n, q, j, k);
+    return (j + bm - 1) / bm;
+}
+
 __host__ __device__ inline int64_t slab_tile_count(int64_t n_v, int64_t j, int bm, int mode,
                                                    int ob) {
     const int64_t wk = n_v - 1 - j;
@@ -409,6 +440,8 @@ struct MfmaLaunch {
     int64_t* prefix;             // workspace: j_end - j_begin + 1 int64
     float* c3;
     int64_t* edge_prefix;        // 3-way: the edge tiles' slab prefix, as prefix
+    int slab3;                   // fused 3-way: 1 = slab tiles (whole + edge), 0 = the
+                                 // split tiling when mfma3_split_ok
 };
 // The int8 thermometer kernels with the 4x2 wave layout threshold V's bytes
 // in registers (no plane pass and no plane workspace) when the sums fit
@@ -421,6 +454,23 @@ inline bool mfma_fused(int64_t n_f, int levels, int fmt, int wide) {
 // The fused kernels address a 256-row tile of V with 32-bit buffer offsets
 // (the last row's field offsets reach at most ld + 127 past its start).
 inline bool mfma_ld_fits(int64_t ld) { return 256 * ld + 256 < ((int64_t)1 << 31); }
+// The fused 3-way epilogue addresses a tile's rows of the pair table and of
+// the slab with 32-bit byte offsets: about 1028 n_v bytes at most.
+inline bool mfma3_nv_fits(int64_t n_v) { return n_v < ((int64_t)1 << 21); }
+// Split tiling of the fused 3-way int8 slices of a stage [jb, je): slabs
+// j < js as colex pairs (i, j) x columns k, slabs j >= js as lex pairs
+// (j, k) x columns i, so that the column range of a row tile is at least
+// about min(n_v - js, js) long and the ragged last column tile wastes
+// little (js = 2 n_v / 5 measured best over tile-area models).  Both parts
+// address all of V and the whole pair table with 32-bit byte offsets.
+inline bool mfma3_split_ok(int64_t n_v, int64_t ld) {
+    return n_v * ld + 256 < ((int64_t)1 << 31) &&
+           n_v * (n_v - 1) / 2 * 4 < ((int64_t)1 << 31);
+}
+inline int64_t mfma3_split(int64_t n_v, int64_t jb, int64_t je) {
+    const int64_t js = 2 * n_v / 5;
+    return js < jb ? jb : js > je ? je : js;
+}
 // Plane workspace of a thermometer launch (0 on the fused path).
 size_t mfma_workspace_bytes(int64_t n_f, int64_t n_v, int levels, int fmt, int wide);
 // Bytes of one thermometer plane row (all levels) of an n_f-field vector.
@@ -440,9 +490,12 @@ hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode,
 // prefix[rt] = column tiles of the flattened row tiles 0 .. rt-1,
 // rt = 0 .. flat_row_tiles(jb, je, bm).
 hipError_t launch_prefix3_flat(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
-                               hipStream_t st);
+                               hipStream_t st, bool lex = false);
 // Tiles of the flattened tiling (host loop over the row tiles).
 int64_t flat_tiles(int64_t n_v, int64_t jb, int64_t je, int bm);
+// Total tiles of the lex-ordered tiling (lex_row_tiles, lex_col_tiles), and
+// the prefix of its column-tile counts (launch_prefix3_flat with lex).
+int64_t lex_tiles(int64_t n_v, int64_t jb, int64_t je, int bm);
 // Output reduction (reduce.hip).
 hipError_t launch_quantize_u8(const float* c, int64_t n, uint8_t* q, hipStream_t st);
 int64_t select_tiles(int64_t n);

@@ -270,7 +270,7 @@ def test_tile_configs_and_tuning_table():
     assert lib.ps_tune_register(0, 2, 1, 0, 10, 0, 10, 1) == OK
     # matrix-core tile orders (uint8, 2-way) and the AUTO path for integer levels
     assert lib.ps_tile_config(2, 2, 2, 0, None, None, None) == 5
-    assert lib.ps_tile_config(2, 3, 2, 0, None, None, None) == 0
+    assert lib.ps_tile_config(2, 3, 2, 0, None, None, None) == 2   # 3-way tilings
     assert lib.ps_tile_config(0, 2, 3, 0, None, None, None) == 0
     assert lib.ps_tune_register(2, 2, 2, 0, 10, 0, 10, 4) == OK
     assert lib.ps_tune_register(2, 2, 2, 0, 10, 0, 10, 5) == ARG

@@ -148,7 +148,13 @@ def test_blocked_split_over_field_chunks(tile):
 # ---------------------------------------------------------------------------
 # 3-way on the matrix cores (uint8 levels, thermometer planes): exact.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
+# the int8 path's two tilings: opts.tile 0 (split: pair rows x vectors) and 2
+# (whole 256-wide tiles inside each slab, 128-wide over its edges)
+MFMA3 = {"mfma": dict(path="mfma"), "mfma_slab": dict(path="mfma", tile=2),
+         "mfma_fp4": dict(path="mfma_fp4")}
+
+
+@pytest.mark.parametrize("path", list(MFMA3))
 @pytest.mark.parametrize("n_v,n_f", [(140, 603), (300, 200), (3, 1), (4, 2), (259, 5),
                                      (520, 130)])
 def test_mfma_3way_exact(path, n_v, n_f):
@@ -156,7 +162,7 @@ def test_mfma_3way_exact(path, n_v, n_f):
     V = workloads.levels(n_v, n_f, seed=n_v * 3 + n_f)
     lev = max(1, int(V.max()))
     announce(f"3-way {path} {n_v}x{n_f}")
-    c3 = host(ps.ps3(to_dev(V), path=path, levels=lev))
+    c3 = host(ps.ps3(to_dev(V), levels=lev, **MFMA3[path]))
     check_exact_f32(c3, oracle.c3_all(V), "c3")
 
 
@@ -191,6 +197,27 @@ def test_mfma_3way_full_size_sampled(path):
     c3 = host(ps.ps3(to_dev(V), path=path, levels=3))
     i, j, k = sample_triples(n_v, 4096, seed=52)
     check_exact_f32(c3[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), "c3 sampled")
+
+
+@pytest.mark.parametrize("lo,hi,n_f", [(90, 100, 27962), (0, 100, 30000)])
+def test_mfma_3way_many_levels_quotient_precision(lo, hi, n_f):
+    """The fused int8 path's Eq. 1 quotient: while 6 levels n_f < 2^24 it is
+    taken in FP32 from exact integer operands (the first case puts the
+    denominators 2 (s_i + s_j + s_k) just under 2^24), beyond that in FP64
+    (the second case).  Both must equal the oracle's FP64 quotient rounded
+    once to FP32, bit for bit, and the VALU path's result."""
+    from paper_1705_08210_amd import ps
+    g = np.random.default_rng(n_f)
+    V = g.integers(lo, hi + 1, size=(30, n_f), dtype=np.uint8)
+    V[3] = 0                                   # zero denominators with zero rows
+    V[4] = 0
+    V[5] = 0
+    announce(f"3-way mfma levels={hi} 30x{n_f}")
+    Vd = to_dev(V)
+    c3 = host(ps.ps3(Vd, path="mfma", levels=hi))
+    check_exact_f32(c3, oracle.c3_all(V), "c3")
+    valu = host(ps.ps3(Vd, path="valu"))
+    assert np.array_equal(valu.view(np.uint32), c3.view(np.uint32))
 
 
 # ------------------------------------------- whole tiles + edge tiles ----
@@ -258,26 +285,28 @@ def test_edge_tiles_with_field_chunks_and_stages():
     check_rel(full[jslab(n_v, i, j, k)], oracle.c3_triples(V, i, j, k), FP32_TOL, "c3")
 
 
-@pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
+@pytest.mark.parametrize("path", list(MFMA3))
 @pytest.mark.parametrize("n_v", [300, 600])
 def test_mfma_whole_and_edge_tiles(path, n_v):
-    """The matrix-core slices run 256-wide tiles over the whole tiles of each
-    slab rectangle (from n_v = 513 there are some) and 128-wide tiles over
-    the rest: every triple is written once (NaN-filled output) and equals the
-    VALU result bit for bit; stages concatenate to the full run."""
+    """Every tiling of the matrix-core slices writes each triple once
+    (NaN-filled output) and equals the VALU result bit for bit; stages
+    concatenate to the full run.  The split tiling's two parts meet at
+    j = 2 n_v / 5 (120 and 240 here), inside the stages below; the slab
+    tiling runs whole 256-wide tiles (from n_v = 513 there are some) and
+    128-wide tiles over the rest."""
     import torch
     from paper_1705_08210_amd import ps
     V = workloads.levels(n_v, 333, seed=n_v + 7)
     Vd = to_dev(V)
-    announce(f"3-way {path} whole + edge tiles n_v={n_v}")
+    announce(f"3-way {path} tilings n_v={n_v}")
     c3 = torch.full((ps.stage_size(n_v, 1, n_v - 1),), float("nan"), device=Vd.device)
-    ps.ps3(Vd, c3=c3, path=path, levels=3)
+    ps.ps3(Vd, c3=c3, levels=3, **MFMA3[path])
     got = host(c3)
     assert not np.isnan(got).any()
     ref = host(ps.ps3(Vd, path="valu"))
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
     cuts = [1, 200, 257, n_v - 1]
-    parts = [host(ps.ps3(Vd, j_begin=a, j_end=b, path=path, levels=3))
+    parts = [host(ps.ps3(Vd, j_begin=a, j_end=b, levels=3, **MFMA3[path]))
              for a, b in zip(cuts, cuts[1:])]
     assert np.array_equal(np.concatenate(parts).view(np.uint32), got.view(np.uint32))
     i, j, k = sample_triples(n_v, 2048, seed=n_v + 8)
