@@ -560,26 +560,31 @@ __device__ __forceinline__ v4i_t lv_subb(v4i_t f, uint32_t tt) {   // [v >= t]
     return r;
 }
 
-// Staging geometry of a fused tile: each thread stages kStage 16-byte chunks
-// of each operand per field tile, chunk ch of rows row0 + c kRowStep.
-template <int WN, int TB>
+// Staging geometry of a fused tile: each of THREADS threads stages kStage
+// 16-byte chunks of an operand of ROWS rows per field tile, chunk ch of rows
+// row(0) + c kRowStep.
+template <int THREADS, int ROWS>
 struct LvGeom {
-    static constexpr int kMThreads = mfma_threads<WN, TB>();
+    static constexpr int kMThreads = THREADS;
+    static constexpr int kRows = ROWS;
     static constexpr int kRowChunks = kLvMK / 16;
-    static constexpr int kStage = TB * kRowChunks / kMThreads;
-    static constexpr int kRowStep = kMThreads / kRowChunks;
-    static_assert(TB * kRowChunks % kMThreads == 0, "staging must divide evenly");
+    static constexpr int kStage = ROWS * kRowChunks / THREADS;
+    static constexpr int kRowStep = THREADS / kRowChunks;
+    static_assert(ROWS * kRowChunks % THREADS == 0, "staging must divide evenly");
     __device__ static int ch() { return threadIdx.x % kRowChunks; }
     __device__ static int row(int c) { return threadIdx.x / kRowChunks + c * kRowStep; }
 };
+template <int WN, int TB>
+using LvGeomW = LvGeom<mfma_threads<WN, TB>(), TB>;
 
 // Row sources of the staging.  LvRows: TB consecutive rows of V from r0 (rows
 // at or past n_v read as zero through the buffer bound); with MASK each row
 // is min-ed bytewise with row mj (the 3-way X_j rows).  The host checks
 // 256 ld + 256 < 2^31, so a tile's rows take 32-bit offsets.
-template <int WN, int TB, bool ALIGNED, int MODE, bool MASK>
+template <class G, bool ALIGNED, int MODE, bool MASK>
 struct LvRows {
-    using G = LvGeom<WN, TB>;
+    using Geom = G;
+    static constexpr int TB = G::kRows;
     __amdgpu_buffer_rsrc_t rs, rm;
     int voff, step;
     uint4 mk;
@@ -613,9 +618,9 @@ struct LvRows {
 // min(v_x, v_y) (the 3-way rows X_y's column x, or X_x's column y).  The
 // rows come through one buffer resource over all of V (the host checks
 // n_v ld + 256 < 2^31); pair(r, x, y) gives each staged row's pair.
-template <int WN, int TB, bool ALIGNED, int MODE>
+template <class G, bool ALIGNED, int MODE>
 struct LvPairs {
-    using G = LvGeom<WN, TB>;
+    using Geom = G;
     __amdgpu_buffer_rsrc_t rs;
     int ox[G::kStage], oy[G::kStage];
     template <class F>
@@ -653,7 +658,7 @@ struct LvPairs {
 template <int WN, bool ALIGNED, int LC, int MODE, int TB, class SA, class SB>
 __device__ __forceinline__ void lv_tile(const LvArgs& a, SA& sa, SB& sb, bool active, int wr,
                                         int wc, v16i_t (&acc)[TB / 64][WN], int8_t* lds) {
-    using G = LvGeom<WN, TB>;
+    using G = LvGeomW<WN, TB>;
     constexpr int WM = TB / 64;
     constexpr int kMK = kLvMK;
     constexpr int KS = kMK / 32;                   // k-steps per field tile
@@ -767,22 +772,131 @@ __device__ __forceinline__ void lv_tile(const LvArgs& a, SA& sa, SB& sb, bool ac
     }
 }
 
+// Main loop of a half tile with one LDS buffer, two workgroups per CU:
+// the A operand's 256 rows and the B operand's 128, four waves of 128 x 64.
+// Field tile kt+1 is loaded into registers while kt is consumed from LDS,
+// then a barrier, the registers go to LDS, and a barrier; the other
+// workgroup on the CU keeps the matrix cores busy across this one's
+// barriers and epilogue.
+template <int WN, bool ALIGNED, int LC, int MODE, class SA, class SB>
+__device__ __forceinline__ void lv_tile_sb(const LvArgs& a, SA& sa, SB& sb, bool active, int wr,
+                                           int wc, v16i_t (&acc)[4][WN], int8_t* lds) {
+    using GA = typename SA::Geom;
+    using GB = typename SB::Geom;
+    constexpr int WM = 4;
+    constexpr int KS = kLvMK / 32;
+    constexpr int kPitch = kLvMK + kPad;
+    int8_t* As = lds;
+    int8_t* Bs = lds + GA::kRows * kPitch;
+    const int lane = threadIdx.x % 64;
+    const int L = LC > 0 ? LC : a.levels;
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int n = 0; n < WN; ++n) acc[m][n] = (v16i_t){};
+    uint4 ra[GA::kStage], rb[GB::kStage];
+    const int ch = GA::ch();
+    auto load = [&](int64_t kt) {
+        const int ko = (int)kt * kLvMK;
+        const int nvalid = (int)a.n_f - ko - ch * 16;
+        sa.prep(ko, nvalid);
+        sb.prep(ko, nvalid);
+#pragma unroll
+        for (int c = 0; c < GA::kStage; ++c) ra[c] = sa.load(c, ko, nvalid);
+#pragma unroll
+        for (int c = 0; c < GB::kStage; ++c) rb[c] = sb.load(c, ko, nvalid);
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int c = 0; c < GA::kStage; ++c)
+            *(uint4*)(As + GA::row(c) * kPitch + ch * 16) = ra[c];
+#pragma unroll
+        for (int c = 0; c < GB::kStage; ++c)
+            *(uint4*)(Bs + GB::row(c) * kPitch + ch * 16) = rb[c];
+    };
+    const int fr = lane % 32, fk = (lane / 32) * 16;
+    auto frag = [&](int ks, v4i_t (&fa)[WM], v4i_t (&fb)[WN]) {
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+            fa[m] = *(const v4i_t*)(As + (wr + m * 32 + fr) * kPitch + ks * 32 + fk);
+#pragma unroll
+        for (int n = 0; n < WN; ++n)
+            fb[n] = *(const v4i_t*)(Bs + (wc + n * 32 + fr) * kPitch + ks * 32 + fk);
+    };
+    auto level = [&](const v4i_t (&fa)[WM], const v4i_t (&fb)[WN], int t) {
+        v4i_t xa[WM], xb[WN];
+        if constexpr (MODE == kLvPerm) {
+            const uint32_t lo = t <= 3 ? 0x01010101u << (8 * t) : 0u;
+            const uint32_t hi = t <= 4 ? 0x01010101u : 0x01010101u << (8 * (t - 4));
+#pragma unroll
+            for (int m = 0; m < WM; ++m) xa[m] = lv_perm(fa[m], hi, lo);
+#pragma unroll
+            for (int n = 0; n < WN; ++n) xb[n] = lv_perm(fb[n], hi, lo);
+        } else {
+            const uint32_t tt = (uint32_t)t * 0x01010101u;
+#pragma unroll
+            for (int m = 0; m < WM; ++m) xa[m] = lv_suba(fa[m], tt);
+#pragma unroll
+            for (int n = 0; n < WN; ++n) xb[n] = lv_subb(fb[n], tt);
+        }
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[m], xb[n], acc[m][n], 0, 0,
+                                                                  0);
+    };
+    const int64_t nk = a.nk;
+    load(0);
+    store();
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load(kt + 1);
+        if (active) {
+            v4i_t fa[2][WM], fb[2][WN];
+            frag(0, fa[0], fb[0]);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks + 1 < KS) frag(ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
+#pragma unroll(LC > 0 ? LC : 1)
+                for (int t = 1; t <= L; ++t) level(fa[ks & 1], fb[ks & 1], t);
+            }
+        }
+        __syncthreads();   // everyone is done reading field tile kt
+        if (kt + 1 < nk) {
+            store();
+            __syncthreads();
+        }
+    }
+    if constexpr (MODE == kLvSub) {
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[m][n][r] = -acc[m][n][r] >> 7;
+    }
+}
+
+// 2-way half tiles: work item t2 is half t2 % 2 (output columns 0-127 or
+// 128-255) of 256 x 256 tile t2 / 2, four waves, two workgroups per CU.
 template <int WN, bool ALIGNED, int LC, int MODE>
-__global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_lv_kernel(LvArgs a) {
-    __shared__ __attribute__((aligned(16))) int8_t lds[4 * kMB * (kLvMK + kPad)];
-    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
-                      blockIdx.x / kXcds;
-    if (t >= a.ntiles) return;
+__global__ __launch_bounds__(256, 2) void ps_mfma2_lv_kernel(LvArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[(kMB + kMB / 2) * (kLvMK + kPad)];
+    const int64_t t2 = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                       blockIdx.x / kXcds;
+    if (t2 >= 2 * a.ntiles) return;
     int64_t bi, bj;
-    grouped_tri_decode_rt(t, a.nb, a.group, bi, bj);
-    const int64_t i0 = bi * kMB, j0 = bj * kMB;
+    grouped_tri_decode_rt(t2 / 2, a.nb, a.group, bi, bj);
+    const int64_t i0 = bi * kMB + (t2 % 2) * (kMB / 2), j0 = bj * kMB;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int wr = (wave % 2) * 128;        // j offset of the wave's block (A rows)
     const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
     const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
     v16i_t acc[4][WN];
-    LvRows<WN, kMB, ALIGNED, MODE, false> sa(a, j0, 0), sb(a, i0, 0);
-    lv_tile<WN, ALIGNED, LC, MODE, kMB>(a, sa, sb, active, wr, wc, acc, lds);
+    LvRows<LvGeom<256, kMB>, ALIGNED, MODE, false> sa(a, j0, 0);
+    LvRows<LvGeom<256, kMB / 2>, ALIGNED, MODE, false> sb(a, i0, 0);
+    lv_tile_sb<WN, ALIGNED, LC, MODE>(a, sa, sb, active, wr, wc, acc, lds);
     if (!active) return;
     MfmaArgs e{};
     e.n_v = a.n_v;
@@ -791,6 +905,7 @@ __global__ __launch_bounds__(mfma_threads<WN>(), 1) void ps_mfma2_lv_kernel(LvAr
     e.n2 = a.n2;
     mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
 }
+
 
 // Eq. 1 on exact integers for one 3-way tile (rows k0 .. k0+TB-1, columns
 // i0 .. i0+TB-1 of slab j): n3 = n2(i,j) + n2(i,k) + n2(j,k) - n3', then
@@ -932,8 +1047,8 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_lv
     const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
     const bool active = (k0 + wr < a.n_v) && (i0 + wc < j);
     v16i_t acc[WM][WN];
-    LvRows<WN, TB, ALIGNED, MODE, false> sa(a, k0, 0);
-    LvRows<WN, TB, ALIGNED, MODE, true> sb(a, i0, j);
+    LvRows<LvGeomW<WN, TB>, ALIGNED, MODE, false> sa(a, k0, 0);
+    LvRows<LvGeomW<WN, TB>, ALIGNED, MODE, true> sb(a, i0, j);
     lv_tile<WN, ALIGNED, LC, MODE, TB>(a, sa, sb, active, wr, wc, acc, lds);
     // The main loop ended on a barrier after its last LDS read, so the LDS is
     // free: the per-row operands of Eq. 1 for the tile's TB rows k go there
@@ -1065,17 +1180,17 @@ __device__ __forceinline__ void lvs_epilogue0(const LvArgs& a, const v16i_t (&ac
     }
 }
 
-// Part 1 epilogue: a row is a pair (j, k); its 2 (s_j + s_k), n2(j, k), the
+// Part 1 epilogue (TB rows): a row is a pair (j, k); its 2 (s_j + s_k), n2(j, k), the
 // pair-table offsets of rows j and k, j and its output row offset are staged
 // in LDS once per tile; n2(i, j) and n2(i, k) are gathered per element
 // (contiguous in i).  Stores from the tile's first pair's entry i = 0 to the
 // end of the last pair's slab; columns i >= j get an offset past it.
-template <bool F32>
+template <bool F32, int TB>
 __device__ __forceinline__ void lvs_epilogue1(const LvArgs& a, const v16i_t (&acc)[4][2],
                                               int64_t q0, int64_t i0, int wr, int wc,
                                               bool active, int8_t* lds) {
     using R = typename std::conditional<F32, float, double>::type;
-    constexpr int TB = kMB, WN = 2, WM = 4;
+    constexpr int WN = 2, WM = 4;   // TB rows (pairs) from q0
     const int lane = threadIdx.x % 64;
     const int64_t n = a.n_v;
     const double* __restrict__ S = a.s;
@@ -1083,7 +1198,7 @@ __device__ __forceinline__ void lvs_epilogue1(const LvArgs& a, const v16i_t (&ac
     const int64_t qe = a.r_end[1];
     const int64_t ob = slab_offset(n, a.j_begin);
     int64_t jf, kf, jl, kl;
-    lex_pair(n, q0, jf, kf);
+    lex_pair(n, q0 < qe ? q0 : qe - 1, jf, kf);   // (a half past the part stores nothing)
     lex_pair(n, q0 + TB - 1 < qe ? q0 + TB - 1 : qe - 1, jl, kl);
     const int64_t base0 = slab_offset(n, jf) - ob + (kf - jf - 1) * jf;
     int4* rowi = (int4*)lds;                         // {c(j), c(k), j, output row offset}
@@ -1177,10 +1292,16 @@ __device__ __forceinline__ void lvs_epilogue1(const LvArgs& a, const v16i_t (&ac
     }
 }
 
-// One tile t of part PART of the split tiling.
+// Half h of tile t of part PART of the split tiling: part 0's output columns
+// (pairs) 128 h .. 128 h + 127, part 1's output rows (pairs) likewise; four
+// waves of 128 x 64, two workgroups per CU (the epilogue and barriers of
+// one overlap the other's multiply-adds).
 template <int PART, bool ALIGNED, int LC, int MODE>
-__device__ __forceinline__ void lvs_tile(const LvArgs& a, int64_t t, int8_t* lds) {
-    constexpr int TB = kMB, WN = 2, WM = TB / 64;
+__device__ __forceinline__ void lvs_tile(const LvArgs& a, int64_t t, int h, int8_t* lds) {
+    constexpr int TB = kMB, WN = 2;
+    constexpr int HB = TB / 2;   // output columns of a half tile
+    using GA = LvGeom<256, TB>;
+    using GB = LvGeom<256, HB>;
     // row tile: the largest rt with prefix[rt] <= t
     const int64_t* pre = a.pre[PART];
     int64_t lo = 0, hi = a.nrt[PART];
@@ -1193,55 +1314,61 @@ __device__ __forceinline__ void lvs_tile(const LvArgs& a, int64_t t, int8_t* lds
     const int64_t r0 = a.r_begin[PART] + lo * TB, re = a.r_end[PART];
     const int wave = threadIdx.x / 64;
     const int wr = (wave % 2) * (TB / 2);   // the wave's output rows
-    const int wc = (wave / 2) * 32 * WN;    // its output columns
-    v16i_t acc[WM][WN];
+    const int wl = (wave / 2) * 32 * WN;    // its output columns in the half (LDS rows)
+    const int wc = h * HB + wl;             // ... in the tile
+    v16i_t acc[4][WN];
     if constexpr (PART == 0) {
         const int64_t k0 = pair_j(r0) + 1 + ct * TB;
         const int64_t pq = r0 + wc;
         const int64_t kq = k0 + wr + TB / 2 - 1 < n - 1 ? k0 + wr + TB / 2 - 1 : n - 1;
         const bool active = k0 + wr < n && pq < re && pair_j(pq) < kq;
-        LvRows<WN, TB, ALIGNED, MODE, false> sa(a, k0, 0);
-        LvPairs<WN, TB, ALIGNED, MODE> sb(a, [&](int r, int64_t& x, int64_t& y) {
-            const int64_t p = r0 + r < re ? r0 + r : re - 1;
+        LvRows<GA, ALIGNED, MODE, false> sa(a, k0, 0);
+        LvPairs<GB, ALIGNED, MODE> sb(a, [&](int r, int64_t& x, int64_t& y) {
+            const int64_t p = r0 + h * HB + r < re ? r0 + h * HB + r : re - 1;
             y = pair_j(p);
             x = p - y * (y - 1) / 2;
         });
-        lv_tile<WN, ALIGNED, LC, MODE, TB>(a, sa, sb, active, wr, wc, acc, lds);
+        lv_tile_sb<WN, ALIGNED, LC, MODE>(a, sa, sb, active, wr, wl, acc, lds);
         if (a.f32div)
             lvs_epilogue0<true>(a, acc, r0, k0, wr, wc, active, lds);
         else
             lvs_epilogue0<false>(a, acc, r0, k0, wr, wc, active, lds);
     } else {
+        // the halves split the rows (pairs), so no pair row is staged twice;
+        // the four waves take 64 of the 256 columns each
         const int64_t i0 = ct * TB;
-        const int64_t qa = r0 + wr;
-        const int64_t qz = qa + TB / 2 - 1 < re ? qa + TB / 2 - 1 : re - 1;
+        const int64_t qa = r0 + h * HB;
+        const int64_t qz = qa + HB - 1 < re ? qa + HB - 1 : re - 1;
+        const int wi = wave * 32 * WN;
         int64_t jz, kz;
         lex_pair(n, qz, jz, kz);
-        const bool active = qa < re && i0 + wc < jz;
-        LvPairs<WN, TB, ALIGNED, MODE> sa(a, [&](int r, int64_t& x, int64_t& y) {
-            lex_pair(n, r0 + r < re ? r0 + r : re - 1, x, y);
+        const bool active = qa < re && i0 + wi < jz;
+        LvPairs<LvGeom<256, HB>, ALIGNED, MODE> sa(a, [&](int r, int64_t& x, int64_t& y) {
+            lex_pair(n, qa + r < re ? qa + r : re - 1, x, y);
         });
-        LvRows<WN, TB, ALIGNED, MODE, false> sb(a, i0, 0);
-        lv_tile<WN, ALIGNED, LC, MODE, TB>(a, sa, sb, active, wr, wc, acc, lds);
+        LvRows<LvGeom<256, TB>, ALIGNED, MODE, false> sb(a, i0, 0);
+        lv_tile_sb<WN, ALIGNED, LC, MODE>(a, sa, sb, active, 0, wi, acc, lds);
         if (a.f32div)
-            lvs_epilogue1<true>(a, acc, r0, i0, wr, wc, active, lds);
+            lvs_epilogue1<true, HB>(a, acc, qa, i0, 0, wi, active, lds);
         else
-            lvs_epilogue1<false>(a, acc, r0, i0, wr, wc, active, lds);
+            lvs_epilogue1<false, HB>(a, acc, qa, i0, 0, wi, active, lds);
     }
 }
 
-// Both parts in one launch (one tail instead of two): tiles [0, nt[0]) are
-// part 0's, the rest part 1's.
+// Both parts in one launch (one tail instead of two): work item t2 is half
+// t2 % 2 of tile t2 / 2; tiles [0, nt[0]) are part 0's, the rest part 1's.
 template <bool ALIGNED, int LC, int MODE>
-__global__ __launch_bounds__(mfma_threads<2>(), 1) void ps_mfma3_lvs_kernel(LvArgs a) {
-    __shared__ __attribute__((aligned(16))) int8_t lds[4 * kMB * (kLvMK + kPad)];
-    const int64_t t = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
-                      blockIdx.x / kXcds;
-    if (t >= a.ntiles) return;
+__global__ __launch_bounds__(256, 2) void ps_mfma3_lvs_kernel(LvArgs a) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[(kMB + kMB / 2) * (kLvMK + kPad)];
+    const int64_t t2 = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                       blockIdx.x / kXcds;
+    if (t2 >= 2 * a.ntiles) return;
+    const int64_t t = t2 / 2;
+    const int h = (int)(t2 % 2);
     if (t < a.nt[0])
-        lvs_tile<0, ALIGNED, LC, MODE>(a, t, lds);
+        lvs_tile<0, ALIGNED, LC, MODE>(a, t, h, lds);
     else
-        lvs_tile<1, ALIGNED, LC, MODE>(a, t - a.nt[0], lds);
+        lvs_tile<1, ALIGNED, LC, MODE>(a, t - a.nt[0], h, lds);
 }
 
 static LvArgs lv_args(const MfmaLaunch& m) {
@@ -1269,13 +1396,14 @@ static hipError_t go_mfma2_lv(const MfmaLaunch& m, hipStream_t st) {
     LvArgs a = lv_args(m);
     a.nb = (m.n_v + kMB - 1) / kMB;
     a.ntiles = a.nb * (a.nb + 1) / 2;
-    return launch_items(a.ntiles, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+    return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
         LvArgs b = a;
         b.item0 = item0;
-        hipLaunchKernelGGL((ps_mfma2_lv_kernel<2, ALIGNED, LC, MODE>), dim3(grid),
-                           dim3(mfma_threads<2>()), 0, st, b);
+        hipLaunchKernelGGL((ps_mfma2_lv_kernel<2, ALIGNED, LC, MODE>), dim3(grid), dim3(256), 0,
+                           st, b);
     });
 }
+
 
 // The split tiling (mfma3_split): part 0 over the colex pairs of slabs
 // [j_begin, js), part 1 over the lex pairs of slabs [js, j_end), in one
@@ -1305,11 +1433,11 @@ static hipError_t go_mfma3_lvs(const MfmaLaunch& m, hipStream_t st) {
         e = launch_prefix3_flat(n, js, je, kMB, m.prefix + a.nrt[0] + 1, st, true);
     if (e != hipSuccess) return e;
     a.ntiles = a.nt[0] + a.nt[1];
-    return launch_items(a.ntiles, mfma_threads<2>(), kXcds, [&](unsigned grid, int64_t item0) {
+    return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
         LvArgs b = a;
         b.item0 = item0;
-        hipLaunchKernelGGL((ps_mfma3_lvs_kernel<ALIGNED, LC, MODE>), dim3(grid),
-                           dim3(mfma_threads<2>()), 0, st, b);
+        hipLaunchKernelGGL((ps_mfma3_lvs_kernel<ALIGNED, LC, MODE>), dim3(grid), dim3(256), 0,
+                           st, b);
     });
 }
 
