@@ -1061,7 +1061,7 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_lv
 
 
 // ---------------------------------------------------------------------------
-// Split tiling of the fused 3-way slices (mfma3_split): every tile is a whole
+// Split tiling of the fused 3-way slices (split3): every tile is a whole
 // 256 x 256 tile of pairs x single vectors, so no slab edge needs narrower
 // tiles.  Part 0: output columns are the colex pairs (i, j), j < js, staged
 // as min(v_i, v_j); output rows are k from the row tile's smallest j + 1.
@@ -1405,13 +1405,13 @@ static hipError_t go_mfma2_lv(const MfmaLaunch& m, hipStream_t st) {
 }
 
 
-// The split tiling (mfma3_split): part 0 over the colex pairs of slabs
+// The split tiling (split3): part 0 over the colex pairs of slabs
 // [j_begin, js), part 1 over the lex pairs of slabs [js, j_end), in one
 // launch, each part with the prefix of its row tiles' column-tile counts
 // (part 1's after part 0's in the prefix workspace).
 template <bool ALIGNED, int LC, int MODE>
 static hipError_t go_mfma3_lvs(const MfmaLaunch& m, hipStream_t st) {
-    const int64_t n = m.n_v, jb = m.j_begin, je = m.j_end, js = mfma3_split(n, jb, je);
+    const int64_t n = m.n_v, jb = m.j_begin, je = m.j_end, js = split3(n, jb, je);
     LvArgs a = lv_args(m);   // a.n2: the pair numerators of Eq. 1
     a.j_begin = jb;
     a.j_end = je;

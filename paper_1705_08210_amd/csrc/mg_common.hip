@@ -411,6 +411,13 @@ hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode,
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
     const int bm = kValuCfgs[a.cfg].bm();
     if (a.mode == kSlabFlat) return launch_prefix3_flat(a.n_v, a.j_begin, a.j_end, bm, a.prefix, st);
+    if (a.mode == kSlabSplit) {
+        hipError_t e = hipSuccess;
+        if (a.js > a.j_begin) e = launch_prefix3_flat(a.n_v, a.j_begin, a.js, bm, a.prefix, st);
+        if (e == hipSuccess && a.j_end > a.js)
+            e = launch_prefix3_flat(a.n_v, a.js, a.j_end, bm, a.prefix1, st, true);
+        return e;
+    }
     hipError_t e = launch_prefix3(a.n_v, a.j_begin, a.j_end, bm, a.mode, bm, a.prefix, st);
     if (e != hipSuccess || a.mode != kSlabFull) return e;
     return launch_prefix3(a.n_v, a.j_begin, a.j_end, kValuCfgs[a.edge_cfg].bm(), kSlabEdge, bm,

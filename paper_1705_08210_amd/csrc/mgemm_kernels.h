@@ -88,6 +88,15 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
 // patterns at the triple's packed index; ps_c3_finish_kernel turns them into
 // c3 in place.  Keeping Eq. 1 out of the tile kernel keeps its register
 // footprint (and so its occupancy) that of the bare min-product.
+// uint8 slices accumulate sum_q |x_q - y_q| (v_sad_u8) for the staged pair
+// row x = min(v_a, v_b) against a single vector y; the slices store
+// n3' = sum_q min(x_q, y_q) = (n2(a, b) + s_y - SAD) / 2 instead, from the
+// pair's numerator and the single vector's sum, so the finish need not know
+// which pair was staged.
+__device__ __forceinline__ uint32_t u8_min_sum(uint32_t sad, int32_t n2_pair, double s_single) {
+    return (uint32_t)(((int64_t)n2_pair + (int64_t)s_single - (int64_t)sad) / 2);
+}
+
 template <int DT, int TM, int TN>
 __device__ __forceinline__ void store_slice(const typename Ops<DT>::Acc (&acc)[TM][TN],
                                             int64_t row0, int64_t col0, int64_t j,
@@ -99,12 +108,16 @@ __device__ __forceinline__ void store_slice(const typename Ops<DT>::Acc (&acc)[T
     for (int r = 0; r < TM; ++r) {
         const int64_t i = row0 + lane_row<TM>(wave, lx, r);
         if (i >= j) continue;
+        int32_t nij = 0;   // the staged pair (i, j)
+        if constexpr (DT == PS_U8) nij = ((const int32_t*)a.n2)[j * (j - 1) / 2 + i];
 #pragma unroll
         for (int c = 0; c < TN; ++c) {
             const int64_t k = col0 + lane_col<TN>(wave, ly, c);
             if (k >= a.n_v) continue;
             if constexpr (DT == PS_F64)   // FP64 raw sums go to a double array
                 ((double*)out)[base + (k - j - 1) * j + i] = acc[r][c];
+            else if constexpr (DT == PS_U8)
+                out[base + (k - j - 1) * j + i] = u8_min_sum(acc[r][c], nij, a.s[k]);
             else
                 out[base + (k - j - 1) * j + i] = __builtin_bit_cast(uint32_t, acc[r][c]);
         }
@@ -174,14 +187,52 @@ __device__ __forceinline__ void store_slice_flat(const typename Ops<DT>::Acc (&a
         const int64_t i = p - j * (j - 1) / 2;
         // index of (i, j, k) = off(j) - off(jb) + (k - j - 1) j + i
         const int64_t base = slab_offset(a.n_v, j) - obase - (j + 1) * j + i;
+        int32_t nij = 0;   // the staged pair (i, j), colex index p
+        if constexpr (DT == PS_U8) nij = ((const int32_t*)a.n2)[p];
 #pragma unroll
         for (int c = 0; c < TM; ++c) {
             const int64_t k = col0 + lane_col<TM>(wave, ly, c);
             if (k >= a.n_v || k <= j) continue;
             if constexpr (DT == PS_F64)
                 ((double*)out)[base + k * j] = acc[r][c];
+            else if constexpr (DT == PS_U8)
+                out[base + k * j] = u8_min_sum(acc[r][c], nij, a.s[k]);
             else
                 out[base + k * j] = __builtin_bit_cast(uint32_t, acc[r][c]);
+        }
+    }
+}
+
+// The lex-ordered rows of kSlabSplit: row q is the pair (j, k) (lex_pair),
+// its A operand row min(v_j, v_k); columns are i from col0; entries with
+// i >= j are computed by waves that also hold wanted ones and never stored.
+template <int DT, int TM>
+__device__ __forceinline__ void store_slice_lex(const typename Ops<DT>::Acc (&acc)[TM][TM],
+                                                int64_t q0, int64_t qend, int64_t col0,
+                                                const Mg3Launch& a, uint32_t* out) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lx = lane % 8, ly = lane / 8;
+    const int64_t obase = slab_offset(a.n_v, a.j_begin);
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+        const int64_t q = q0 + lane_row<TM>(wave, lx, r);
+        if (q >= qend) continue;
+        int64_t j, k;
+        lex_pair(a.n_v, q, j, k);
+        // index of (i, j, k) = off(j) - off(jb) + (k - j - 1) j + i
+        const int64_t base = slab_offset(a.n_v, j) - obase + (k - j - 1) * j;
+        int32_t njk = 0;   // the staged pair (j, k)
+        if constexpr (DT == PS_U8) njk = ((const int32_t*)a.n2)[k * (k - 1) / 2 + j];
+#pragma unroll
+        for (int c = 0; c < TM; ++c) {
+            const int64_t i = col0 + lane_col<TM>(wave, ly, c);
+            if (i >= j) continue;
+            if constexpr (DT == PS_F64)
+                ((double*)out)[base + i] = acc[r][c];
+            else if constexpr (DT == PS_U8)
+                out[base + i] = u8_min_sum(acc[r][c], njk, a.s[i]);
+            else
+                out[base + i] = __builtin_bit_cast(uint32_t, acc[r][c]);
         }
     }
 }
@@ -197,33 +248,60 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3f_kernel(Mg3Laun
     __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
     const int64_t w = item0 + xcd_remap(blockIdx.x, gridDim.x);
     if (w >= a.ntiles * a.nchunks) return;
-    const int64_t chunk = w / a.ntiles, t = w % a.ntiles;
-    // row tile: largest rt with prefix[rt] <= t
-    int64_t lo = 0, hi = flat_row_tiles(a.j_begin, a.j_end, BM);
+    const int64_t chunk = w / a.ntiles, tw = w % a.ntiles;
+    // kSlabSplit: tiles past ntiles0 are the lex-ordered part's
+    const bool split = a.mode == kSlabSplit;
+    const bool lexp = split && tw >= a.ntiles0;
+    const int64_t t = lexp ? tw - a.ntiles0 : tw;
+    const int64_t je0 = split ? a.js : a.j_end;   // end of the colex part
+    const int64_t* pre = lexp ? a.prefix1 : a.prefix;
+    // row tile: largest rt with pre[rt] <= t
+    int64_t lo = 0;
+    int64_t hi = lexp ? lex_row_tiles(a.n_v, a.js, a.j_end, BM) : flat_row_tiles(a.j_begin, je0, BM);
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) / 2;
-        if (a.prefix[mid] <= t) lo = mid; else hi = mid;
+        if (pre[mid] <= t) lo = mid; else hi = mid;
     }
-    const int64_t pb = a.j_begin * (a.j_begin - 1) / 2;
-    const int64_t pend = a.j_end * (a.j_end - 1) / 2;
-    const int64_t p0 = pb + lo * BM;
-    const int64_t col0 = pair_j(p0) + 1 + (t - a.prefix[lo]) * BM;
     const int wave = threadIdx.x / 64;
-    // this wave's quadrant: pairs from pq, columns [cq, cq + 8 TM); it holds a
-    // wanted entry iff its smallest j is below its largest k
-    const int64_t pq = p0 + (wave & 1) * 8 * TM;
-    const int64_t cq = col0 + (wave >> 1) * 8 * TM;
-    const int64_t kq = cq + 8 * TM - 1 < a.n_v - 1 ? cq + 8 * TM - 1 : a.n_v - 1;
-    const bool active = pq < pend && cq < a.n_v && pair_j(pq) < kq;
+    // this wave's quadrant: rows from rq, columns [cq, cq + 8 TM); it holds a
+    // wanted entry iff (colex) its smallest j is below its largest k, or
+    // (lex) its smallest i is below its largest j
+    int64_t r0, rend, col0;
+    bool active;
+    if (!lexp) {
+        rend = je0 * (je0 - 1) / 2;
+        r0 = a.j_begin * (a.j_begin - 1) / 2 + lo * BM;
+        col0 = pair_j(r0) + 1 + (t - pre[lo]) * BM;
+        const int64_t rq = r0 + (wave & 1) * 8 * TM;
+        const int64_t cq = col0 + (wave >> 1) * 8 * TM;
+        const int64_t kq = cq + 8 * TM - 1 < a.n_v - 1 ? cq + 8 * TM - 1 : a.n_v - 1;
+        active = rq < rend && cq < a.n_v && pair_j(rq) < kq;
+    } else {
+        rend = lex_first(a.n_v, a.j_end);
+        r0 = lex_first(a.n_v, a.js) + lo * BM;
+        col0 = (t - pre[lo]) * BM;
+        const int64_t rq = r0 + (wave & 1) * 8 * TM;
+        const int64_t cq = col0 + (wave >> 1) * 8 * TM;
+        int64_t jz, kz;
+        lex_pair(a.n_v, rq + 8 * TM - 1 < rend ? rq + 8 * TM - 1 : rend - 1, jz, kz);
+        active = rq < rend && cq < jz;
+    }
     const int64_t ldb = a.ld * Ops<DT>::kEsz;
     const int64_t nbytes = a.n_f * Ops<DT>::kEsz;
     int64_t aoff[SA::kCh], xoff[SA::kCh];
 #pragma unroll
     for (int c = 0; c < SA::kCh; ++c) {
-        const int64_t p = p0 + (threadIdx.x + c * kThreads) % BM;
-        const int64_t j = p < pend ? pair_j(p) : 0;
-        aoff[c] = p < pend ? (p - j * (j - 1) / 2) * ldb : -1;
-        xoff[c] = j * ldb;
+        const int64_t r = r0 + (threadIdx.x + c * kThreads) % BM;
+        if (!lexp) {
+            const int64_t j = r < rend ? pair_j(r) : 0;
+            aoff[c] = r < rend ? (r - j * (j - 1) / 2) * ldb : -1;
+            xoff[c] = j * ldb;
+        } else {
+            int64_t j, k;
+            lex_pair(a.n_v, r < rend ? r : rend - 1, j, k);
+            aoff[c] = r < rend ? j * ldb : -1;
+            xoff[c] = k * ldb;
+        }
     }
     Acc acc[TM][TM];
     const int64_t kt0 = a.nchunks > 1 ? chunk * a.chunk_tiles : 0;
@@ -236,7 +314,10 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3f_kernel(Mg3Laun
                             ? (uint32_t*)a.partial +
                                   chunk * (slab_offset(a.n_v, a.j_end) - slab_offset(a.n_v, a.j_begin))
                             : (uint32_t*)a.c3;
-        store_slice_flat<DT, TM>(acc, p0, pend, col0, a, dst);
+        if (lexp)
+            store_slice_lex<DT, TM>(acc, r0, rend, col0, a, dst);
+        else
+            store_slice_flat<DT, TM>(acc, r0, rend, col0, a, dst);
     }
 }
 
@@ -295,9 +376,7 @@ __global__ __launch_bounds__(256) void ps_c3_finish_kernel(Mg3Launch a, int64_t 
         const double sk = a.s[k];
         double n3p;
         if constexpr (DT == PS_U8) {
-            // sum_q min(x, v_k) = (sum x + s_k - sum |x - v_k|) / 2 with
-            // x = min(v_i, v_j), so sum x = n2(i, j)
-            n3p = (double)(((int64_t)nij + (int64_t)sk - (int64_t)raw) / 2);
+            n3p = (double)(int32_t)raw;   // the slices store n3' (u8_min_sum), never split
         } else if constexpr (DT == PS_B1) {
             n3p = (double)raw;   // popcount(v_i AND v_j AND v_k), never split
         } else if constexpr (DT == PS_F64) {
@@ -394,7 +473,7 @@ template <int DT, int TM, int BKW>
 hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
     return launch_items(a.ntiles * a.nchunks, kThreads, kXcds, [&](unsigned grid, int64_t item0) {
-        if (a.mode == kSlabFlat)
+        if (a.mode == kSlabFlat || a.mode == kSlabSplit)
             hipLaunchKernelGGL((ps_mg3f_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st,
                                a, item0);
         else

@@ -301,7 +301,7 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
 // (whole and edge tiles of the matrix-core slices, the finish's ranges), or
 // the flattened row tiles of the VALU slices at the smallest tile edge (64).
 static int64_t prefix3_entries(int64_t n_v, int64_t jb, int64_t je) {
-    const int64_t flat = flat_row_tiles(jb, je, 64) + 1;
+    const int64_t flat = flat_row_tiles(jb, je, 64) + lex_row_tiles(n_v, jb, je, 64) + 2;
     const int64_t split = flat_row_tiles(jb, je, kMfmaTile) + lex_row_tiles(n_v, jb, je, kMfmaTile) + 2;
     const int64_t m = flat > split ? flat : split;
     return 2 * (n_v + 1) > m ? 2 * (n_v + 1) : m;
@@ -567,10 +567,14 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     }
     const int cfg = choose_cfg(kdt, 3, bits ? PS_PATH_BITS : PS_PATH_VALU, n_f, n_v, opts);
     const int bm = kValuCfgs[cfg].bm();
-    // one launch over the flattened (pair, k) tiles of the stage
+    // one launch over the split tiling of the stage: colex (pair, k) tiles of
+    // the slabs below js, lex (pair, i) tiles of the others
+    const int64_t js = split3(n_v, j_begin, j_end);
+    const int64_t nt0 = flat_tiles(n_v, j_begin, js, bm);
     Mg3Launch a{KV, kn_f, n_v, kld, s, n2, j_begin, j_end, c3, prefix,
-                flat_tiles(n_v, j_begin, j_end, bm), cfg, nchunks,
-                bits ? 0 : chunk_tiles(dtype, cfg), partial, kSlabFlat, bm, -1, nullptr, 0, 0};
+                nt0 + lex_tiles(n_v, js, j_end, bm), cfg, nchunks,
+                bits ? 0 : chunk_tiles(dtype, cfg), partial, kSlabSplit, bm, -1, nullptr, 0, 0,
+                js, nt0, prefix + flat_row_tiles(j_begin, js, bm) + 1};
     e = launch_mg3_prefix(a, stream);
     if (e == hipSuccess) e = launch_mg3(kdt, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way launch");

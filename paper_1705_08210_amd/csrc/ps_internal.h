@@ -76,7 +76,10 @@ __host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
 // kSlabRange counts ranges of bm consecutive outputs of the slab instead
 // (the elementwise 3-way finish).
 // kSlabFlat (the VALU slices) does not tile slab by slab: see flat_* below.
-enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2, kSlabRange = 3, kSlabFlat = 4 };
+// kSlabSplit (the VALU slices): kSlabFlat over the slabs below the split
+// point split3, then the lex-ordered tiling (lex_* below) over the
+// rest, in one launch.
+enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2, kSlabRange = 3, kSlabFlat = 4, kSlabSplit = 5 };
 
 // Pair (i, j), i < j, has colex index p = j (j - 1) / 2 + i.  pair_j(p) is
 // its j: the largest j with j (j - 1) / 2 <= p.
@@ -323,6 +326,10 @@ struct Mg3Launch {
     int32_t edge_cfg;
     int64_t* edge_prefix;        // workspace: j_end - j_begin + 1 int64
     int64_t edge_ntiles, edge_chunk_tiles;
+    // kSlabSplit: slabs [j_begin, js) as kSlabFlat (tiles [0, ntiles0), prefix),
+    // slabs [js, j_end) lex-ordered (the other tiles, prefix1)
+    int64_t js, ntiles0;
+    int64_t* prefix1;
 };
 
 // The kSlabEdge launch that completes a kSlabFull launch a.
@@ -457,17 +464,19 @@ inline bool mfma_ld_fits(int64_t ld) { return 256 * ld + 256 < ((int64_t)1 << 31
 // The fused 3-way epilogue addresses a tile's rows of the pair table and of
 // the slab with 32-bit byte offsets: about 1028 n_v bytes at most.
 inline bool mfma3_nv_fits(int64_t n_v) { return n_v < ((int64_t)1 << 21); }
-// Split tiling of the fused 3-way int8 slices of a stage [jb, je): slabs
-// j < js as colex pairs (i, j) x columns k, slabs j >= js as lex pairs
-// (j, k) x columns i, so that the column range of a row tile is at least
-// about min(n_v - js, js) long and the ragged last column tile wastes
-// little (js = 2 n_v / 5 measured best over tile-area models).  Both parts
-// address all of V and the whole pair table with 32-bit byte offsets.
+// Split tiling of the 3-way slices of a stage [jb, je): slabs j < js as
+// colex pairs (i, j) x columns k, slabs j >= js as lex pairs (j, k) x
+// columns i, so that the column range of a row tile is at least about
+// min(n_v - js, js) long and the ragged last column tile wastes little
+// (js = 2 n_v / 5, about the best in tile-area models for 128- and 256-wide
+// tiles).  The int8 matrix-core slices address all of V and the whole pair
+// table with 32-bit byte offsets (mfma3_split_ok); the VALU slices take it
+// at any size.
 inline bool mfma3_split_ok(int64_t n_v, int64_t ld) {
     return n_v * ld + 256 < ((int64_t)1 << 31) &&
            n_v * (n_v - 1) / 2 * 4 < ((int64_t)1 << 31);
 }
-inline int64_t mfma3_split(int64_t n_v, int64_t jb, int64_t je) {
+inline int64_t split3(int64_t n_v, int64_t jb, int64_t je) {
     const int64_t js = 2 * n_v / 5;
     return js < jb ? jb : js > je ? je : js;
 }

@@ -112,7 +112,7 @@ int main() {
             for (int64_t jb = 1; jb < n - 1; jb += (n > 100 ? 37 : 1))
                 for (int64_t je = jb; je <= n - 1; je += (n > 100 ? 53 : 1)) {
                     // the split point divides any stage between the two parts
-                    const int64_t js = mfma3_split(n, jb, je);
+                    const int64_t js = split3(n, jb, je);
                     bad += js < jb || js > je;
                     bad += cover_flat(n, jb, js, bm) + cover_lex(n, js, je, bm);
                 }
