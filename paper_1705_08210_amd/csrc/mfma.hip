@@ -477,12 +477,12 @@ struct LvArgs {
     const int64_t* pre[2];
 };
 
-// Bytewise unsigned min of two words whose bytes all have bit 7 set.  Per
-// byte, a - (b AND 0x7f) = 0x80 + (a7 - b7) lies in [1, 255], so bit 7 says
-// a >= b and nothing borrows; the flags widen to 0xff bytes.
-__device__ __forceinline__ uint32_t bytemin_hi(uint32_t a, uint32_t b) {
-    const uint32_t ge = (a - (b & 0x7f7f7f7fu)) & 0x80808080u;
-    const uint32_t m = ge | (ge - (ge >> 7));
+// Bytewise min of a and b given d, a word whose byte k has bit 7 set exactly
+// where byte k of a is at least byte k of b: the flags widen to 0xff bytes
+// with one byte permute (selectors 8-11 replicate bit 7 of bytes 1, 3, 5, 7
+// of {d, d << 8}, which are d's bytes 0, 2, 1, 3), then one bit-field insert.
+__device__ __forceinline__ uint32_t bytemin_flags(uint32_t d, uint32_t a, uint32_t b) {
+    const uint32_t m = __builtin_amdgcn_perm(d, d << 8, 0x0B090A08u);
     return (b & m) | (a & ~m);
 }
 
@@ -527,11 +527,14 @@ __device__ __forceinline__ uint4 lv_prep(uint4 v, int nvalid) {
     return v;
 }
 
-// Bytewise min of staged words (the 3-way X_j rows).
+// Bytewise min of staged words (the 3-way pair rows).  kLvSub bytes all have
+// bit 7 set: a - (b AND 0x7f) is 0x80 + (a7 - b7) per byte, in [1, 255]; the
+// other modes' bytes are below 128: (a OR 0x80) - b is 0x80 + a - b per byte,
+// in [1, 255].  Either way nothing borrows and bit 7 says a >= b.
 template <int MODE>
 __device__ __forceinline__ uint32_t lv_min(uint32_t a, uint32_t b) {
-    if constexpr (MODE == kLvSub) return bytemin_hi(a, b);
-    return bytemin_hi(a | 0x80808080u, b | 0x80808080u) & 0x7f7f7f7fu;
+    if constexpr (MODE == kLvSub) return bytemin_flags(a - (b & 0x7f7f7f7fu), a, b);
+    return bytemin_flags((a | 0x80808080u) - b, a, b);
 }
 
 // Level t of a fragment.
