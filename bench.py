@@ -62,6 +62,10 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3way", action="store_true",
                     help="default workload: skip the 3-way measurement of the same line")
+    ap.add_argument("--shard-of", type=int, default=0, metavar="N",
+                    help="2-way workloads: time one GPU's share when the pairs are spread "
+                         "over N GPUs by tiles (shard 0 of N, ps2_compute_shard); the whole "
+                         "call is timed beside it")
     ap.add_argument("--per-problem", action="store_true",
                     help="batched workload: one launch per problem instead of the plan")
     ap.add_argument("--campaign", type=int, default=0, metavar="STAGES",
@@ -444,15 +448,43 @@ def measure(args, wl, K, W, with_cpu=True):
         c2 = torch.empty(m, dtype=torch.float32, device=dev)
         levels = int(V.max()) if V.dtype == np.uint8 else 0
 
+        N = args.shard_of
+
         def step(rec):
             ps.vector_sums(Vd, out=s, want_bad=False)
             a = timer.mark() if rec else None
-            ps.ps2(Vd, s=s, c2=c2, acc=args.acc, path=args.path, levels=levels,
-                   tile=args.tile)
+            if N > 1:
+                ps.ps2_shard(Vd, 0, N, s=s, c2=c2, acc=args.acc, path=args.path,
+                             levels=levels, tile=args.tile)
+            else:
+                ps.ps2(Vd, s=s, c2=c2, acc=args.acc, path=args.path, levels=levels,
+                       tile=args.tile)
             if rec:
                 timer.add(a, timer.mark())
 
         cmp = n_f * m
+        if N > 1:   # the shard's pairs: those it writes into a NaN-filled output
+            c2.fill_(float("nan"))
+            ps.ps2_shard(Vd, 0, N, c2=c2, acc=args.acc, path=args.path, levels=levels,
+                         tile=args.tile)
+            shard_pairs = int((~torch.isnan(c2)).sum())
+            cmp = n_f * shard_pairs
+            # the whole call on the same box, for comparison (not the timed work)
+            for _ in range(2):
+                ps.ps2(Vd, s=s, c2=c2, acc=args.acc, path=args.path, levels=levels,
+                       tile=args.tile)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(3):
+                ps.ps2(Vd, s=s, c2=c2, acc=args.acc, path=args.path, levels=levels,
+                       tile=args.tile)
+            torch.cuda.synchronize()
+            full_ms = (time.perf_counter() - t1) / 3 * 1e3
+            c2.fill_(float("nan"))
+            extra["shard"] = {"shard": 0, "of": N, "pairs": shard_pairs, "pairs_total": m,
+                              "tiles": "upper-triangle tiles t with t mod N == 0",
+                              "whole_call_ms": round(full_ms, 3),
+                              "whole_call_cmp_per_s": n_f * m / (full_ms * 1e-3)}
         path = resolved_path(args, V, 2)
         if path == "bits":   # v_and + v_bcnt per 32 comparisons
             dtype, bound, ops_per_cmp, peak = "b1", "alu", 2.0 / 32, HALF_RATE_OPS_TOPS
@@ -476,9 +508,21 @@ def measure(args, wl, K, W, with_cpu=True):
             dtype, bound, ops_per_cmp, peak = "f32", "alu", 2.0, FP32_LANE_OPS_TOPS
             kernel = "ps_mg2_kernel"
         config = {"workload": wl, "way": 2, "n_f": n_f, "n_v": n_v, "path": path}
+        if N > 1:
+            config["shard"] = f"0 of {N}"
         cpu = (lambda: cpu_baseline(V, n_f, args.cpu_seconds, 2))
 
         def parity():
+            if N > 1:   # pairs of the shard only
+                import oracle
+                h = to_host(c2)
+                idx = np.flatnonzero(~np.isnan(h))
+                idx = np.random.default_rng(7).choice(idx, 2048)
+                J = ((1 + np.sqrt(1 + 8 * idx.astype(np.float64))) // 2).astype(np.int64)
+                J -= (J * (J - 1) // 2 > idx)
+                J += ((J + 1) * J // 2 <= idx)
+                I = idx - J * (J - 1) // 2
+                return _errors(h[idx], oracle.c2_pairs(V, I, J))
             got, ref = _parity_pairs(V, c2, n_v, 2048, 7, to_host)
             out = _errors(got, ref)
             if f16_source is not None:   # the user-visible error: against the FP32 input
@@ -619,6 +663,7 @@ def measure(args, wl, K, W, with_cpu=True):
         "value": cmp * K / wall, "unit": "comparisons/s", "ms_per_step": wall / K * 1e3,
         "dtype": dtype, "config": config,
         "roofline": dict(roofline(bound, ops_per_cmp, cmp, kernel_ms, peak,
+                                  None if args.shard_of > 1 else
                                   recorded_traffic(kernel, traffic_key(args, wl))),
                          kernel=kernel, kernel_ms=round(kernel_ms, 4)),
     }

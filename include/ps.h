@@ -181,6 +181,27 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
                       void* workspace, size_t ws_bytes, const ps_opts* opts,
                       hipStream_t stream);
 
+/*
+ * One GPU's share of ps2_compute when the pairs are spread over nshards GPUs
+ * by tiles (the single-node analogue of the block-circulant distribution of
+ * the pair blocks over processors, Section 4.1): the upper-triangle tiles of
+ * the chosen tile configuration are numbered t = bj (bj + 1) / 2 + bi
+ * (bi <= bj, block rows/columns of ps_tile_config's edge), and this call
+ * computes the tiles t with t mod nshards == shard, writing c2 (and n2) at
+ * those tiles' pairs only.  It takes the same tile configuration, field-chunk
+ * plan and workspace (ps2_workspace_size) as ps2_compute with these
+ * arguments, so the calls for shard = 0 .. nshards-1 together write every
+ * pair once, bit for bit as one ps2_compute call.  Arguments as for
+ * ps2_compute, with the full-size c2 / n2 arrays.  VALU and BITS paths only
+ * (MFMA paths with nshards > 1: PS_ERR_UNSUPPORTED); nshards = 1 is
+ * ps2_compute.  Errors: as ps2_compute; PS_ERR_ARG unless
+ * 0 <= shard < nshards.
+ */
+ps_status ps2_compute_shard(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
+                            int64_t ld, const double* s, float* c2, void* n2,
+                            int64_t shard, int64_t nshards, void* workspace,
+                            size_t ws_bytes, const ps_opts* opts, hipStream_t stream);
+
 /* Workspace bytes that ps3_compute needs for the stage [j_begin, j_end)
  * (s_given / n2_given as they will be passed). */
 size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,

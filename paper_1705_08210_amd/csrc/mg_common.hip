@@ -278,13 +278,18 @@ __global__ __launch_bounds__(1024) void ps_prefix3_kernel(int64_t n_v, int64_t j
 template <int DT>
 __device__ __forceinline__ void finish_pairs(int64_t n_v, int32_t nchunks, const float* partial,
                                              const double* s, float* c2, void* n2,
-                                             int64_t first, int64_t stride) {
+                                             int64_t first, int64_t stride, int bm = 0,
+                                             int64_t shard0 = 0, int64_t nshards = 1) {
     const int64_t np = n_v * (n_v - 1) / 2;
     for (int64_t idx = first; idx < np; idx += stride) {
         int64_t j = (int64_t)((1.0 + __builtin_sqrt(1.0 + 8.0 * (double)idx)) * 0.5);
         while (j * (j - 1) / 2 > idx) --j;
         while ((j + 1) * j / 2 <= idx) ++j;
         const int64_t i = idx - j * (j - 1) / 2;
+        if (nshards > 1) {   // a tile shard: only the pairs of its tiles
+            const int64_t bi = i / bm, bj = j / bm;
+            if ((bj * (bj + 1) / 2 + bi) % nshards != shard0) continue;
+        }
         double num;
         if constexpr (DT == PS_U8) {
             const uint32_t sad = ((const uint32_t*)partial)[idx];
@@ -303,10 +308,10 @@ __device__ __forceinline__ void finish_pairs(int64_t n_v, int32_t nchunks, const
     }
 }
 
-__global__ __launch_bounds__(256) void ps_finish2_kernel(Mg2Launch a) {
+__global__ __launch_bounds__(256) void ps_finish2_kernel(Mg2Launch a, int bm) {
     finish_pairs<PS_F32>(a.n_v, a.nchunks, a.partial, a.s, a.c2, a.n2,
                          (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
-                         (int64_t)gridDim.x * blockDim.x);
+                         (int64_t)gridDim.x * blockDim.x, bm, a.shard0, a.nshards);
 }
 
 // Every problem of a batch (blockIdx.y = problem).
@@ -339,7 +344,8 @@ hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
     if (np <= 0) return hipSuccess;
     int64_t blocks = (np + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(ps_finish2_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(ps_finish2_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a,
+                       kValuCfgs[a.cfg].bm());
     return hipGetLastError();
 }
 

@@ -47,7 +47,8 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
     // work item = (field chunk, tile), chunk-major; item0: this launch's first
     const int64_t w = item0 + xcd_remap(blockIdx.x, gridDim.x);
     if (w >= ntiles * a.nchunks) return;
-    const int64_t chunk = w / ntiles, t = w % ntiles;
+    const int64_t chunk = w / ntiles;
+    const int64_t t = a.nshards > 1 ? a.shard0 + (w % ntiles) * a.nshards : w % ntiles;
     int64_t bi, bj;
     tri_decode(t, bi, bj);   // column-major: measured faster here than grouped order
     const int64_t row0 = bi * BM, col0 = bj * BM;
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mgb_kernel(MgBatchL
 
 template <int DT, int TM, int BKW>
 hipError_t go_mg2(const Mg2Launch& a, hipStream_t st) {
-    const int64_t T = tri_tiles(a.n_v, 16 * TM);
+    const int64_t T = shard_tiles(tri_tiles(a.n_v, 16 * TM), a.shard0, a.nshards);
     if (T == 0) return hipSuccess;
     return launch_items(T * a.nchunks, kThreads, kXcds, [&](unsigned grid, int64_t item0) {
         hipLaunchKernelGGL((ps_mg2_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,

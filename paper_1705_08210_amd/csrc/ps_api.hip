@@ -238,12 +238,18 @@ size_t ps2_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v, int32_t s_giv
                       opts && opts->tile == 2, sp.nchunks, nullptr, nullptr, nullptr, nullptr);
 }
 
-ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
-                      const double* s, float* c2, void* n2, void* workspace, size_t ws_bytes,
-                      const ps_opts* opts, hipStream_t stream) {
+// ps2_compute over the tiles of one shard (nshards > 1, see
+// ps2_compute_shard) or over all tiles (nshards == 1).
+static ps_status ps2_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                         const double* s, float* c2, void* n2, int64_t shard, int64_t nshards,
+                         void* workspace, size_t ws_bytes, const ps_opts* opts,
+                         hipStream_t stream) {
     ps_status st = check_matrix(V, dtype, n_f, n_v, ld);
     if (st != PS_OK) return st;
     if ((st = check_opts(opts)) != PS_OK) return st;
+    if (nshards < 1 || shard < 0 || shard >= nshards)
+        return fail(PS_ERR_ARG, "need 0 <= shard < nshards, got shard %lld of %lld",
+                    (long long)shard, (long long)nshards);
     if (n_v < 2) return PS_OK;
     if (!c2 && !n2) return fail(PS_ERR_ARG, "both c2 and n2 are NULL");
     if (!aligned(c2, 4) || !aligned(n2, 4) || !aligned(s, 8))
@@ -254,12 +260,15 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
     const int wide = opts && opts->tile == 2;
     if ((st = check_mfma(path, dtype, levels, n_f, ld, wide)) != PS_OK) return st;
     if ((st = check_int_range(path, dtype, n_f)) != PS_OK) return st;
+    if (nshards > 1 && is_mfma(path))
+        return fail(PS_ERR_UNSUPPORTED, "sharded calls run on the VALU and BITS paths only");
     double* s_ws = nullptr;
     int8_t* planes = nullptr;
     float* partial = nullptr;
     const bool bits = path == PS_PATH_BITS;
     const int cfg = bits ? choose_cfg(PS_B1, 2, PS_PATH_BITS, n_f, n_v, opts)
                          : choose_cfg(dtype, 2, PS_PATH_VALU, n_f, n_v, opts);
+    // a shard takes the whole call's field-chunk plan: its workspace and sums are the same
     const Split sp = bits ? Split{1, 0} : plan_split(dtype, n_f, n_v, cfg, opts);
     const size_t need = ws2_layout(dtype, n_f, n_v, s != nullptr, path, levels, wide,
                                    sp.nchunks, workspace, &s_ws, &planes, &partial);
@@ -285,11 +294,12 @@ ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, in
         const int64_t W = bits_row_words(n_f);
         e = launch_pack_bits((const uint8_t*)V, n_f, n_v, ld, (uint32_t*)planes, stream);
         if (e != hipSuccess) return hip_fail(e, "bit packing launch");
-        Mg2Launch a{planes, W, n_v, W, s, c2, n2, cfg, 1, 0, nullptr};
+        Mg2Launch a{planes, W, n_v, W, s, c2, n2, cfg, 1, 0, nullptr, shard, nshards};
         e = launch_mg2(PS_B1, a, stream);
         return e == hipSuccess ? PS_OK : hip_fail(e, "2-way bits launch");
     }
-    Mg2Launch a{V, n_f, n_v, ld, s, c2, n2, cfg, sp.nchunks, sp.chunk_tiles, partial};
+    Mg2Launch a{V,         n_f,           n_v,     ld,    s,      c2, n2, cfg,
+                sp.nchunks, sp.chunk_tiles, partial, shard, nshards};
     e = launch_mg2(dtype, a, stream);
     if (e == hipSuccess && sp.nchunks > 1) e = launch_finish2(dtype, a, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "2-way launch");
@@ -583,6 +593,20 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
 }  // namespace ps
 
 extern "C" {
+
+ps_status ps2_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                      const double* s, float* c2, void* n2, void* workspace, size_t ws_bytes,
+                      const ps_opts* opts, hipStream_t stream) {
+    return ps2_run(V, dtype, n_f, n_v, ld, s, c2, n2, 0, 1, workspace, ws_bytes, opts, stream);
+}
+
+ps_status ps2_compute_shard(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
+                            const double* s, float* c2, void* n2, int64_t shard,
+                            int64_t nshards, void* workspace, size_t ws_bytes,
+                            const ps_opts* opts, hipStream_t stream) {
+    return ps2_run(V, dtype, n_f, n_v, ld, s, c2, n2, shard, nshards, workspace, ws_bytes, opts,
+                   stream);
+}
 
 ps_status ps3_compute(const void* V, int32_t dtype, int64_t n_f, int64_t n_v, int64_t ld,
                       const double* s, const void* n2, int64_t j_begin, int64_t j_end,

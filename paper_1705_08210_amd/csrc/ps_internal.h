@@ -301,7 +301,17 @@ struct Mg2Launch {
     int32_t nchunks;
     int64_t chunk_tiles;
     float* partial;
+    // tile shard: only the tiles t = shard0 + u * nshards of the upper
+    // triangle (nshards <= 1: all tiles)
+    int64_t shard0, nshards;
 };
+
+// Tiles of the upper triangle in shard shard0 of nshards (tri_tiles when
+// nshards <= 1).
+inline int64_t shard_tiles(int64_t T, int64_t shard0, int64_t nshards) {
+    if (nshards <= 1) return T;
+    return T > shard0 ? (T - shard0 + nshards - 1) / nshards : 0;
+}
 
 // Arguments of one 3-way launch over the tiles of middle indices
 // [j_begin, j_end).

@@ -61,6 +61,8 @@ _sig("ps_vector_sums", ctypes.c_int, [P, I32, I64, I64, I64, P, P, P])
 _sig("ps2_workspace_size", SZ, [I32, I64, I64, I32, ctypes.POINTER(Opts)])
 _sig("ps2_compute", ctypes.c_int,
      [P, I32, I64, I64, I64, P, P, P, P, SZ, ctypes.POINTER(Opts), P])
+_sig("ps2_compute_shard", ctypes.c_int,
+     [P, I32, I64, I64, I64, P, P, P, I64, I64, P, SZ, ctypes.POINTER(Opts), P])
 _sig("ps3_workspace_size", SZ, [I32, I64, I64, I32, I32, I64, I64, ctypes.POINTER(Opts)])
 _sig("ps3_compute", ctypes.c_int,
      [P, I32, I64, I64, I64, P, P, I64, I64, P, P, SZ, ctypes.POINTER(Opts), P])
@@ -186,6 +188,30 @@ def ps2(V: torch.Tensor, s: torch.Tensor | None = None, want_c2: bool = True,
         ws = _workspace(ws_n, V.device)
         _check(lib.ps2_compute(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(c2), _ptr(n2),
                                ws.data_ptr(), ws.numel(), ctypes.byref(o), _stream(stream)))
+    return c2, n2
+
+
+def ps2_shard(V: torch.Tensor, shard: int, nshards: int, s: torch.Tensor | None = None,
+              want_c2: bool = True, want_n2: bool = False, acc="auto", path="auto", levels=0,
+              tile=0, c2: torch.Tensor | None = None, n2: torch.Tensor | None = None,
+              stream=None):
+    """One GPU's share of ps2 when the pairs are spread over nshards GPUs by
+    tiles (ps2_compute_shard): writes the full-size colex c2 / n2 at the pairs
+    of the upper-triangle tiles t with t % nshards == shard only, with the
+    same tile configuration and accumulation plan as ps2.  Returns (c2, n2)."""
+    dt, n_f, n_v, ld = _matrix(V)
+    m = n_v * (n_v - 1) // 2
+    with _on(stream):
+        if want_c2 and c2 is None:
+            c2 = torch.empty(m, dtype=torch.float32, device=V.device)
+        if want_n2 and n2 is None:
+            n2 = torch.empty(m, dtype=n2_dtype(V.dtype), device=V.device)
+        o = _opts(acc, path, levels, tile)
+        ws_n = lib.ps2_workspace_size(dt, n_f, n_v, int(s is not None), ctypes.byref(o))
+        ws = _workspace(ws_n, V.device)
+        _check(lib.ps2_compute_shard(V.data_ptr(), dt, n_f, n_v, ld, _ptr(s), _ptr(c2),
+                                     _ptr(n2), shard, nshards, ws.data_ptr(), ws.numel(),
+                                     ctypes.byref(o), _stream(stream)))
     return c2, n2
 
 
@@ -450,6 +476,7 @@ def clock_probe(iters: int = 200000, stream=None) -> float:
 # The C ABI's names (include/ps.h) for the same calls.
 ps_vector_sums = vector_sums
 ps2_compute = ps2
+ps2_compute_shard = ps2_shard
 ps3_compute = ps3
 ps3_compute_noalloc = ps3_noalloc
 ps2_compute_batched = ps2_batched

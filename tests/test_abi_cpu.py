@@ -132,6 +132,29 @@ def test_u8_valu_range_in_a_batch():
     assert lib.ps2_compute_batched(arr, 2, 0, FAKE, 16, None, None) == WS
 
 
+def call2s(shard, nshards, **kw):
+    """ps2_compute_shard with call2's fake arguments."""
+    a = dict(V=FAKE, dt=0, n_f=10, n_v=5, ld=10, s=None, c2=FAKE, n2=None, ws=FAKE,
+             ws_bytes=1 << 20, o=None)
+    a.update(kw)
+    return lib.ps2_compute_shard(a["V"], a["dt"], a["n_f"], a["n_v"], a["ld"], a["s"],
+                                 a["c2"], a["n2"], shard, nshards, a["ws"], a["ws_bytes"],
+                                 a["o"], None)
+
+
+@pytest.mark.parametrize("shard,nshards,kw,status", [
+    (0, 0, {}, ARG),                                   # no shards
+    (-1, 4, {}, ARG),
+    (4, 4, {}, ARG),                                   # shard past the last
+    (1, 4, dict(dt=2, o=opts(path=2, levels=3)), UNSUP),   # MFMA paths are not sharded
+    (1, 4, dict(ws_bytes=16), WS),                     # arguments fine up to the workspace
+    (1, 4, dict(o=opts(acc=1), ws_bytes=16), WS),      # BLOCKED: chunk partials in the workspace
+    (0, 1, dict(o=opts(acc=1), ws_bytes=16), WS),      # one shard is ps2_compute
+])
+def test_ps2_shard_argument_errors(shard, nshards, kw, status):
+    assert call2s(shard, nshards, **kw) == status
+
+
 def test_ps2_no_pairs_is_noop():
     # n_v < 2: nothing to compute, nothing launched, pointers unused
     assert call2(n_v=1, c2=None, ws=None, ws_bytes=0) == OK

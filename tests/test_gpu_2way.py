@@ -311,3 +311,49 @@ def test_blocked_split_fp16():
     c2, _ = run2(V16, acc="blocked")
     check_rel(c2, oracle.c2_all(V16), FP32_TOL, "c2 vs fp16 values")
     check_rel(c2, oracle.c2_all(V32), FP16_TOL, "c2 vs fp32 source")
+
+
+# ------------------------------------------------------ tile shards ----
+
+@pytest.mark.parametrize("storage,tile,acc,n_f", [("f32", 1, "plain", 333),
+                                                  ("f32", 2, "auto", 5000),
+                                                  ("u8", 1, "auto", 333),
+                                                  ("bits", 2, "auto", 333)])
+@pytest.mark.parametrize("nshards", [3, 8])
+def test_shards_partition_the_pairs(storage, tile, acc, n_f, nshards):
+    """ps2_compute_shard: shard k writes exactly the pairs of the upper-triangle
+    tiles t = bj (bj + 1) / 2 + bi with t mod nshards == k (NaN-filled
+    outputs show what was written); the shards together write every pair
+    once, bit for bit as one ps2 call with the same options (with AUTO on
+    5000 fields the field axis is split over chunks and the finish pass runs
+    per shard); integer data equals the oracle."""
+    import torch
+    from paper_1705_08210_amd import ps
+    n_v = 700
+    if storage == "f32":
+        V, kw = workloads.sparse_uniform(n_v, n_f, seed=91), {}
+    elif storage == "u8":
+        V, kw = workloads.levels(n_v, n_f, seed=92), dict(path="valu")
+    else:
+        V, kw = workloads.binary(n_v, n_f, seed=93, dtype=np.uint8), dict(path="bits", levels=1)
+    Vd = to_dev(V)
+    announce(f"2-way shards {storage} tile={tile} acc={acc} n_f={n_f} nshards={nshards}")
+    full = host(ps.ps2(Vd, acc=acc, tile=tile, **kw)[0])
+    if storage != "f32":
+        check_exact_f32(full, oracle.c2_all(V), "c2")
+    bm = ps.tile_configs(Vd.dtype if storage != "bits" else torch.uint8, 2)[tile - 1][0]
+    i, j = np.triu_indices(n_v, 1)
+    order = np.argsort(j * n_v + i, kind="stable")       # colex: (i, j) at j (j - 1) / 2 + i
+    i, j = i[order], j[order]
+    bi, bj = i // bm, j // bm
+    owner = (bj * (bj + 1) // 2 + bi) % nshards
+    m = n_v * (n_v - 1) // 2
+    union = np.full(m, np.nan, dtype=np.float32)
+    for k in range(nshards):
+        c2 = torch.full((m,), float("nan"), device=Vd.device)
+        ps.ps2_shard(Vd, k, nshards, c2=c2, acc=acc, tile=tile, **kw)
+        got = host(c2)
+        written = ~np.isnan(got)
+        assert np.array_equal(written, owner == k), f"shard {k}"
+        union[written] = got[written]
+    assert np.array_equal(union.view(np.uint32), full.view(np.uint32))
