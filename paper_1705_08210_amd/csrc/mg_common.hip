@@ -424,10 +424,7 @@ hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
             e = launch_prefix3_flat(a.n_v, a.js, a.j_end, bm, a.prefix1, st, true);
         return e;
     }
-    hipError_t e = launch_prefix3(a.n_v, a.j_begin, a.j_end, bm, a.mode, bm, a.prefix, st);
-    if (e != hipSuccess || a.mode != kSlabFull) return e;
-    return launch_prefix3(a.n_v, a.j_begin, a.j_end, kValuCfgs[a.edge_cfg].bm(), kSlabEdge, bm,
-                          a.edge_prefix, st);
+    return hipErrorInvalidValue;   // the slices run kSlabFlat or kSlabSplit only
 }
 
 }  // namespace ps

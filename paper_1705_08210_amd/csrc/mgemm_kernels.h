@@ -79,16 +79,17 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
 }
 
 // ---------------------------------------------------------------------------
-// 3-way: one workgroup per (j, i-tile, k-tile) of the slices
-// B_j = X_j^T o_min V, X_j = min(V, v_j) (Section 3.2), restricted to i < j < k.
-// With j the middle index the rectangle i < j, k > j holds every triple once.
+// 3-way slices B_j = X_j^T o_min V, X_j = min(V, v_j) (Section 3.2),
+// restricted to i < j < k: with j the middle index the rectangle i < j, k > j
+// holds every triple once.  The tiles are the split tiling (kSlabSplit) of
+// the pairs (i, j) or (j, k) against the single vectors k or i.
 // ---------------------------------------------------------------------------
 
-// 3-way, first half of the epilogue: the raw slice sums (n3' for the
-// floating and binary types, sum |min(v_i,v_j) - v_k| for uint8) are stored as 32-bit
-// patterns at the triple's packed index; ps_c3_finish_kernel turns them into
-// c3 in place.  Keeping Eq. 1 out of the tile kernel keeps its register
-// footprint (and so its occupancy) that of the bare min-product.
+// 3-way, first half of the epilogue: the slice sums (n3' for the floating
+// and binary types) are stored as 32-bit patterns at the triple's packed
+// index; ps_c3_finish_kernel turns them into c3 in place.  Keeping Eq. 1 out
+// of the tile kernel keeps its register footprint (and so its occupancy)
+// that of the bare min-product.
 // uint8 slices accumulate sum_q |x_q - y_q| (v_sad_u8) for the staged pair
 // row x = min(v_a, v_b) against a single vector y; the slices store
 // n3' = sum_q min(x_q, y_q) = (n2(a, b) + s_y - SAD) / 2 instead, from the
@@ -96,76 +97,6 @@ __global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg2_kernel(Mg2Launc
 // which pair was staged.
 __device__ __forceinline__ uint32_t u8_min_sum(uint32_t sad, int32_t n2_pair, double s_single) {
     return (uint32_t)(((int64_t)n2_pair + (int64_t)s_single - (int64_t)sad) / 2);
-}
-
-template <int DT, int TM, int TN>
-__device__ __forceinline__ void store_slice(const typename Ops<DT>::Acc (&acc)[TM][TN],
-                                            int64_t row0, int64_t col0, int64_t j,
-                                            const Mg3Launch& a, uint32_t* out) {
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int lx = lane % 8, ly = lane / 8;
-    const int64_t base = slab_offset(a.n_v, j) - slab_offset(a.n_v, a.j_begin);
-#pragma unroll
-    for (int r = 0; r < TM; ++r) {
-        const int64_t i = row0 + lane_row<TM>(wave, lx, r);
-        if (i >= j) continue;
-        int32_t nij = 0;   // the staged pair (i, j)
-        if constexpr (DT == PS_U8) nij = ((const int32_t*)a.n2)[j * (j - 1) / 2 + i];
-#pragma unroll
-        for (int c = 0; c < TN; ++c) {
-            const int64_t k = col0 + lane_col<TN>(wave, ly, c);
-            if (k >= a.n_v) continue;
-            if constexpr (DT == PS_F64)   // FP64 raw sums go to a double array
-                ((double*)out)[base + (k - j - 1) * j + i] = acc[r][c];
-            else if constexpr (DT == PS_U8)
-                out[base + (k - j - 1) * j + i] = u8_min_sum(acc[r][c], nij, a.s[k]);
-            else
-                out[base + (k - j - 1) * j + i] = __builtin_bit_cast(uint32_t, acc[r][c]);
-        }
-    }
-}
-
-template <int DT, int TM, int BKW>
-__global__ __launch_bounds__(kThreads, PS_MIN_WAVES) void ps_mg3_kernel(Mg3Launch a, int64_t item0) {
-    using Acc = typename Ops<DT>::Acc;
-    constexpr int BM = 16 * TM;
-    using Word = typename Ops<DT>::Word;
-    __shared__ __attribute__((aligned(16))) Word As[BKW * (BM + 4)];
-    __shared__ __attribute__((aligned(16))) Word Bs[BKW * (BM + 4)];
-    const int64_t w = item0 + xcd_remap(blockIdx.x, gridDim.x);
-    if (w >= a.ntiles * a.nchunks) return;
-    const int64_t chunk = w / a.ntiles, t = w % a.ntiles;
-    // slice j: largest jj with prefix[jj] <= t (the slice holding tile t;
-    // slices without tiles in this tile set repeat their prefix and are passed)
-    int64_t lo = 0, hi = a.j_end - a.j_begin;
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) / 2;
-        if (a.prefix[mid] <= t) lo = mid; else hi = mid;
-    }
-    const int64_t j = a.j_begin + lo;
-    int64_t row0, col0;
-    slab_tile_origin(a.n_v, j, t - a.prefix[lo], BM, a.mode, a.ob, row0, col0);
-    const int wave = threadIdx.x / 64;
-    const int64_t r_lo = row0 + (wave & 1) * 8 * TM;
-    const int64_t c_lo = col0 + (wave >> 1) * 8 * TM;
-    const bool active = r_lo < j && c_lo < a.n_v;
-    const int64_t ldb = a.ld * Ops<DT>::kEsz;
-    const int64_t nbytes = a.n_f * Ops<DT>::kEsz;
-    const char* Vb = (const char*)a.V;
-    Acc acc[TM][TM];
-    const int64_t kt0 = a.nchunks > 1 ? chunk * a.chunk_tiles : 0;
-    const int64_t kt1 = a.nchunks > 1 ? kt0 + a.chunk_tiles : -1;
-    run_tile<DT, TM, TM, BKW, true>(Vb, ldb, nbytes, rows_vec_ok<DT>(a.V, a.ld),
-                                             row0, j, col0, a.n_v, Vb + j * ldb, active,
-                                             As, Bs, acc, kt0, kt1);
-    if (active) {
-        uint32_t* dst = DT == PS_F64 ? (uint32_t*)a.partial   // stage doubles, never split
-                        : a.nchunks > 1
-                            ? (uint32_t*)a.partial +
-                                  chunk * (slab_offset(a.n_v, a.j_end) - slab_offset(a.n_v, a.j_begin))
-                            : (uint32_t*)a.c3;
-        store_slice<DT, TM, TM>(acc, row0, col0, j, a, dst);
-    }
 }
 
 // 3-way over the flattened rows (kSlabFlat): one workgroup per (row tile of
@@ -473,29 +404,20 @@ hipError_t go_mg2(const Mg2Launch& a, hipStream_t st) {
 template <int DT, int TM, int BKW>
 hipError_t go_mg3(const Mg3Launch& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
+    if (a.mode != kSlabFlat && a.mode != kSlabSplit) return hipErrorInvalidValue;
     return launch_items(a.ntiles * a.nchunks, kThreads, kXcds, [&](unsigned grid, int64_t item0) {
-        if (a.mode == kSlabFlat || a.mode == kSlabSplit)
-            hipLaunchKernelGGL((ps_mg3f_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st,
-                               a, item0);
-        else
-            hipLaunchKernelGGL((ps_mg3_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st,
-                               a, item0);
+        hipLaunchKernelGGL((ps_mg3f_kernel<DT, TM, BKW>), dim3(grid), dim3(kThreads), 0, st, a,
+                           item0);
     });
 }
 
-// The slice launches of a: one over its tile set and, for kSlabFull, the
-// kSlabEdge launch that completes it.  dispatch(cfg, go) runs go with the
-// compiled tile configuration cfg.
+// The slice launch of a.  dispatch(cfg, go) runs go with the compiled tile
+// configuration cfg.
 template <int DT, class Dispatch>
 hipError_t go_mg3_all(const Mg3Launch& a, Dispatch dispatch, hipStream_t st) {
-    auto one = [&](const Mg3Launch& p) {
-        return dispatch(p.cfg, [&](auto tm, auto bkw) {
-            return go_mg3<DT, decltype(tm)::value, decltype(bkw)::value>(p, st);
-        });
-    };
-    hipError_t e = one(a);
-    if (e == hipSuccess && a.mode == kSlabFull) e = one(mg3_edge_launch(a));
-    return e;
+    return dispatch(a.cfg, [&](auto tm, auto bkw) {
+        return go_mg3<DT, decltype(tm)::value, decltype(bkw)::value>(a, st);
+    });
 }
 
 template <int DT, int TM, int BKW>

@@ -51,16 +51,6 @@ int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
     return default_cfg(way, n_v);
 }
 
-// The 128-wide tiles run over the whole tiles of each slab rectangle only and
-// 64-wide tiles (configuration 1, whose waves skip 32-wide quarters outside
-// the rectangle) cover its edges: the waste at the ragged slab edges shrinks
-// from 64-wide to 32-wide quarters, and every 128-wide tile runs all its
-// waves.  An explicit opts.tile runs its configuration over every tile.
-int edge_cfg3(int cfg, const ps_opts* o) {
-    if (o && o->tile > 0) return -1;
-    return kValuCfgs[cfg].bm() == 128 ? 1 : -1;
-}
-
 int choose_acc(int64_t n_f, const ps_opts* o) {
     const int a = o ? o->acc : PS_ACC_AUTO;
     if (a == PS_ACC_PLAIN || a == PS_ACC_BLOCKED) return a;

@@ -385,8 +385,7 @@ static ps_status ps3_mfma(const void* V, int64_t n_f, int64_t n_v, int64_t ld, c
     e = launch_mfma3(m, stream);
     if (e != hipSuccess) return hip_fail(e, "3-way mfma launch");
     if (mfma_fused(n_f, levels, fmt, 0)) return PS_OK;   // Eq. 1 applied in the slices
-    Mg3Launch f{V,        n_f,     n_v, ld, s,  n2,      j_begin, j_end, c3, prefix, 0, 0, 1,
-                0,        nullptr, kSlabAll, 0, -1, nullptr, 0,       0};
+    Mg3Launch f{V, n_f, n_v, ld, s, n2, j_begin, j_end, c3, prefix, 0, 0, 1, 0, nullptr, kSlabAll};
     e = launch_c3_finish_int(f, stream);
     return e == hipSuccess ? PS_OK : hip_fail(e, "3-way finish launch");
 }
@@ -583,7 +582,7 @@ static ps_status ps3_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
     const int64_t nt0 = flat_tiles(n_v, j_begin, js, bm);
     Mg3Launch a{KV, kn_f, n_v, kld, s, n2, j_begin, j_end, c3, prefix,
                 nt0 + lex_tiles(n_v, js, j_end, bm), cfg, nchunks,
-                bits ? 0 : chunk_tiles(dtype, cfg), partial, kSlabSplit, bm, -1, nullptr, 0, 0,
+                bits ? 0 : chunk_tiles(dtype, cfg), partial, kSlabSplit,
                 js, nt0, prefix + flat_row_tiles(j_begin, js, bm) + 1};
     e = launch_mg3_prefix(a, stream);
     if (e == hipSuccess) e = launch_mg3(kdt, a, stream);

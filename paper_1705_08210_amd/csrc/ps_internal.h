@@ -267,9 +267,6 @@ constexpr int64_t kMinChunkTiles = 4;
 int choose_cfg(int32_t dt, int32_t way, int32_t path, int64_t n_f, int64_t n_v,
                const ps_opts* o);
 int choose_acc(int64_t n_f, const ps_opts* o);
-// 3-way slices: the configuration of the edge tiles that complete a launch
-// over whole tiles of cfg (kSlabFull), or -1 for one launch over every tile.
-int edge_cfg3(int cfg, const ps_opts* o);
 int32_t split_chunks(int32_t dt, int64_t n_f, int acc);
 int64_t chunk_tiles(int32_t dt, int cfg);
 Split plan_split(int32_t dt, int64_t n_f, int64_t n_v, int cfg, const ps_opts* o);
@@ -328,34 +325,13 @@ struct Mg3Launch {
     int32_t nchunks;             // field-chunk split as for Mg2Launch; partial
     int64_t chunk_tiles;         // holds nchunks * stage-size FP32 values (for
     float* partial;              // PS_F64: stage-size doubles of raw n3', no split)
-    int32_t mode;                // tile set of this launch (kSlabAll / kSlabFull / kSlabEdge,
-                                 // or kSlabFlat: prefix over flattened row tiles)
-    int32_t ob;                  // kSlabEdge: edge of the whole tiles around which it runs
-    // kSlabFull: a second launch covers the slab edges with configuration
-    // edge_cfg (kSlabEdge around the cfg tiles); its slab prefix is edge_prefix
-    int32_t edge_cfg;
-    int64_t* edge_prefix;        // workspace: j_end - j_begin + 1 int64
-    int64_t edge_ntiles, edge_chunk_tiles;
+    int32_t mode;                // tile set of the slice launch: kSlabFlat (prefix over the
+                                 // colex row tiles) or kSlabSplit; kSlabAll for the finish
     // kSlabSplit: slabs [j_begin, js) as kSlabFlat (tiles [0, ntiles0), prefix),
     // slabs [js, j_end) lex-ordered (the other tiles, prefix1)
     int64_t js, ntiles0;
     int64_t* prefix1;
 };
-
-// The kSlabEdge launch that completes a kSlabFull launch a.
-inline Mg3Launch mg3_edge_launch(const Mg3Launch& a) {
-    Mg3Launch e = a;
-    e.mode = kSlabEdge;
-    e.ob = kValuCfgs[a.cfg].bm();
-    e.cfg = a.edge_cfg;
-    e.prefix = a.edge_prefix;
-    e.ntiles = a.edge_ntiles;
-    e.chunk_tiles = a.edge_chunk_tiles;
-    e.edge_cfg = -1;
-    e.edge_prefix = nullptr;
-    e.edge_ntiles = e.edge_chunk_tiles = 0;
-    return e;
-}
 
 // Device problem record of a batched launch.
 struct DevProblem {
