@@ -220,6 +220,27 @@ def test_mfma_3way_many_levels_quotient_precision(lo, hi, n_f):
     assert np.array_equal(valu.view(np.uint32), c3.view(np.uint32))
 
 
+def test_mfma_split_tiling_falls_back_past_32bit_offsets():
+    """The split tiling of the int8 slices addresses all of V with 32-bit
+    offsets (n_v ld < 2^31); a strided view past that (300 rows of stride 7.2e6
+    bytes, inside the per-tile bound 256 ld < 2^31) runs the per-slab tiles
+    instead, bit for bit as the VALU path and the oracle."""
+    import torch
+    from paper_1705_08210_amd import ps
+    n_v, n_f, ld = 300, 200, 7_200_000
+    V = workloads.levels(n_v, n_f, seed=57)
+    big = torch.zeros((n_v, ld), dtype=torch.uint8, device="cuda")
+    big[:, :n_f] = to_dev(V)
+    view = big[:, :n_f]
+    announce(f"3-way mfma {n_v}x{n_f} ld={ld} (slab fallback)")
+    got = host(ps.ps3(view, path="mfma", levels=3))
+    check_exact_f32(got, oracle.c3_all(V), "c3")
+    valu = host(ps.ps3(view, path="valu"))
+    assert np.array_equal(valu.view(np.uint32), got.view(np.uint32))
+    del big, view
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------- whole tiles + edge tiles ----
 
 def _edge_case_input(storage, n_v, n_f, seed):
