@@ -1430,10 +1430,7 @@ static hipError_t go_mfma3_lvs(const MfmaLaunch& m, hipStream_t st) {
     a.r_end[1] = lex_first(n, je);
     a.nt[0] = a.nrt[0] > 0 ? flat_tiles(n, jb, js, kMB) : 0;
     a.nt[1] = a.nrt[1] > 0 ? lex_tiles(n, js, je, kMB) : 0;
-    hipError_t e = hipSuccess;
-    if (a.nrt[0] > 0) e = launch_prefix3_flat(n, jb, js, kMB, m.prefix, st);
-    if (e == hipSuccess && a.nrt[1] > 0)
-        e = launch_prefix3_flat(n, js, je, kMB, m.prefix + a.nrt[0] + 1, st, true);
+    hipError_t e = launch_prefix3_split(n, jb, js, je, kMB, m.prefix, m.prefix + a.nrt[0] + 1, st);
     if (e != hipSuccess) return e;
     a.ntiles = a.nt[0] + a.nt[1];
     return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {

@@ -350,46 +350,64 @@ hipError_t launch_finish2(int32_t dt, const Mg2Launch& a, hipStream_t st) {
 }
 
 // Exclusive prefix of the column-tile counts of the flattened (colex) or the
-// lex-ordered row tiles (one workgroup; 1024 threads each own a contiguous
-// run of row tiles).
+// lex-ordered row tiles of a stage part, one workgroup per part (blockIdx.x):
+// 1024 threads each own a contiguous run of row tiles; the run sums are
+// scanned in LDS (Hillis-Steele, ten steps) and each thread writes its run.
+struct Prefix3Part {
+    int64_t jb, je;
+    int lex;
+    int64_t* prefix;
+};
 __device__ __forceinline__ int64_t prefix3_cols(int64_t n_v, int64_t jb, int64_t je, int bm,
                                                 bool lex, int64_t rt) {
     return lex ? lex_col_tiles(n_v, jb, je, bm, rt) : flat_col_tiles(n_v, jb, bm, rt);
 }
-__global__ __launch_bounds__(1024) void ps_prefix3_flat_kernel(int64_t n_v, int64_t jb,
-                                                               int64_t je, int bm, int lex,
-                                                               int64_t* prefix) {
+__global__ __launch_bounds__(1024) void ps_prefix3_flat_kernel(int64_t n_v, int bm,
+                                                               Prefix3Part p0,
+                                                               Prefix3Part p1) {
     __shared__ int64_t part[1024];
-    const int64_t nr = lex ? lex_row_tiles(n_v, jb, je, bm) : flat_row_tiles(jb, je, bm);
+    const Prefix3Part p = blockIdx.x == 0 ? p0 : p1;
+    const bool lex = p.lex != 0;
+    const int64_t nr = lex ? lex_row_tiles(n_v, p.jb, p.je, bm) : flat_row_tiles(p.jb, p.je, bm);
     const int64_t per = (nr + 1023) / 1024;
     const int64_t lo = (int64_t)threadIdx.x * per;
     const int64_t hi = lo + per < nr ? lo + per : nr;
     int64_t sum = 0;
-    for (int64_t t = lo; t < hi; ++t) sum += prefix3_cols(n_v, jb, je, bm, lex, t);
+    for (int64_t t = lo; t < hi; ++t) sum += prefix3_cols(n_v, p.jb, p.je, bm, lex, t);
     part[threadIdx.x] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = 0;
-        for (int t = 0; t < 1024; ++t) {
-            const int64_t v = part[t];
-            part[t] = run;
-            run += v;
-        }
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
     }
-    __syncthreads();
-    int64_t run = part[threadIdx.x];
+    int64_t run = part[threadIdx.x] - sum;   // exclusive
     for (int64_t t = lo; t < hi; ++t) {
-        prefix[t] = run;
-        run += prefix3_cols(n_v, jb, je, bm, lex, t);
+        p.prefix[t] = run;
+        run += prefix3_cols(n_v, p.jb, p.je, bm, lex, t);
     }
-    if (hi == nr && lo < hi) prefix[nr] = run;
-    if (nr == 0 && threadIdx.x == 0) prefix[0] = 0;
+    if (hi == nr && lo < hi) p.prefix[nr] = run;
+    if (nr == 0 && threadIdx.x == 0) p.prefix[0] = 0;
 }
 
 hipError_t launch_prefix3_flat(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
                                hipStream_t st, bool lex) {
-    hipLaunchKernelGGL(ps_prefix3_flat_kernel, dim3(1), dim3(1024), 0, st, n_v, jb, je, bm,
-                       lex ? 1 : 0, prefix);
+    const Prefix3Part p{jb, je, lex ? 1 : 0, prefix};
+    hipLaunchKernelGGL(ps_prefix3_flat_kernel, dim3(1), dim3(1024), 0, st, n_v, bm, p, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix3_split(int64_t n_v, int64_t jb, int64_t js, int64_t je, int bm,
+                                int64_t* prefix0, int64_t* prefix1, hipStream_t st) {
+    const Prefix3Part p0{jb, js, 0, prefix0}, p1{js, je, 1, prefix1};
+    const bool has0 = js > jb, has1 = je > js;
+    if (!has0 && !has1) return hipSuccess;
+    if (has0 && has1)
+        hipLaunchKernelGGL(ps_prefix3_flat_kernel, dim3(2), dim3(1024), 0, st, n_v, bm, p0, p1);
+    else
+        hipLaunchKernelGGL(ps_prefix3_flat_kernel, dim3(1), dim3(1024), 0, st, n_v, bm,
+                           has0 ? p0 : p1, has0 ? p0 : p1);
     return hipGetLastError();
 }
 
@@ -417,13 +435,8 @@ hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode,
 hipError_t launch_mg3_prefix(const Mg3Launch& a, hipStream_t st) {
     const int bm = kValuCfgs[a.cfg].bm();
     if (a.mode == kSlabFlat) return launch_prefix3_flat(a.n_v, a.j_begin, a.j_end, bm, a.prefix, st);
-    if (a.mode == kSlabSplit) {
-        hipError_t e = hipSuccess;
-        if (a.js > a.j_begin) e = launch_prefix3_flat(a.n_v, a.j_begin, a.js, bm, a.prefix, st);
-        if (e == hipSuccess && a.j_end > a.js)
-            e = launch_prefix3_flat(a.n_v, a.js, a.j_end, bm, a.prefix1, st, true);
-        return e;
-    }
+    if (a.mode == kSlabSplit)
+        return launch_prefix3_split(a.n_v, a.j_begin, a.js, a.j_end, bm, a.prefix, a.prefix1, st);
     return hipErrorInvalidValue;   // the slices run kSlabFlat or kSlabSplit only
 }
 

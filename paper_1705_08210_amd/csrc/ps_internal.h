@@ -486,6 +486,10 @@ hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode,
 // rt = 0 .. flat_row_tiles(jb, je, bm).
 hipError_t launch_prefix3_flat(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
                                hipStream_t st, bool lex = false);
+// Both parts of the split tiling of a stage (colex slabs [jb, js) into
+// prefix0, lex slabs [js, je) into prefix1) in one launch.
+hipError_t launch_prefix3_split(int64_t n_v, int64_t jb, int64_t js, int64_t je, int bm,
+                                int64_t* prefix0, int64_t* prefix1, hipStream_t st);
 // Tiles of the flattened tiling (host loop over the row tiles).
 int64_t flat_tiles(int64_t n_v, int64_t jb, int64_t je, int bm);
 // Total tiles of the lex-ordered tiling (lex_row_tiles, lex_col_tiles), and
