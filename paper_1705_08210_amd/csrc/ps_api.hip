@@ -308,13 +308,14 @@ static ps_status ps2_run(const void* V, int32_t dtype, int64_t n_f, int64_t n_v,
 // The field-split partials of the pair prepass and of the slices run one
 // after the other on the stream and share one region.
 // Prefix entries of a 3-way stage [jb, je): two slab prefixes of n_v + 1
-// (whole and edge tiles of the matrix-core slices, the finish's ranges), or
-// the flattened row tiles of the VALU slices at the smallest tile edge (64).
+// (whole and edge tiles of the per-slab matrix-core slices, the finish's
+// ranges), or the row tiles of the split tiling's two parts, whichever is more.
 static int64_t prefix3_entries(int64_t n_v, int64_t jb, int64_t je) {
-    const int64_t flat = flat_row_tiles(jb, je, 64) + lex_row_tiles(n_v, jb, je, 64) + 2;
-    const int64_t split = flat_row_tiles(jb, je, kMfmaTile) + lex_row_tiles(n_v, jb, je, kMfmaTile) + 2;
-    const int64_t m = flat > split ? flat : split;
-    return 2 * (n_v + 1) > m ? 2 * (n_v + 1) : m;
+    // the split tiling's two parts (colex slabs [jb, js), lex slabs [js, je)) at
+    // the smallest tile edge of any path (64; the matrix-core tiles are 256)
+    const int64_t js = split3(n_v, jb, je);
+    const int64_t split = flat_row_tiles(jb, js, 64) + lex_row_tiles(n_v, js, je, 64) + 2;
+    return 2 * (n_v + 1) > split ? 2 * (n_v + 1) : split;
 }
 
 static size_t ws3_layout(int64_t n_v, int64_t npre, int32_t s_given, int32_t n2_given,
