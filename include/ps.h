@@ -220,9 +220,11 @@ size_t ps3_workspace_size(int32_t dtype, int64_t n_f, int64_t n_v,
  *          for F64, int32 for U8, as written by ps2_compute for the same V),
  *          or NULL to compute them into the workspace
  *   opts   path VALU, BITS (binary U8 data, X_j = V AND v_j), or for U8
- *          data the MFMA paths (the thermometer planes with the B operand
- *          ANDed with the planes of v_j: [a>=t][b>=t][c>=t] =
- *          [min(a,b,c)>=t], exact); AUTO picks as for ps2_compute
+ *          data the MFMA paths, exact: a pair's row is staged as the
+ *          bytewise min of its two vectors and thresholded per level,
+ *          [min(a,b) >= t][c >= t] = [min(a,b,c) >= t]; the int8 path tiles
+ *          the stage as pairs x vectors (ps_tile_config, way 3); AUTO picks
+ *          as for ps2_compute
  *   c3     device float; receives the triples of [j_begin, j_end) packed in
  *          j-slab order starting at offset 0 (i.e. at global index
  *          off(j_begin))
