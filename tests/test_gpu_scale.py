@@ -90,12 +90,19 @@ def test_nested_support_2way_full_size_exact():
         check_exact_f32(c2[colex(ii, jj)], ref, f"c2 columns {j0}..{j1}")
 
 
-def test_nested_support_3way_full_size_exact():
+@pytest.mark.parametrize("kind", ["f32", "u8_mfma", "u8_valu"])
+def test_nested_support_3way_full_size_exact(kind):
+    """Every one of the 1.78e8 triples of the 3-way benchmark's shape against
+    the closed form, bit for bit: FP32 data on the VALU slices, integer levels
+    on the int8 matrix-core split tiling (the bench's integer 3-way launch)
+    and on the uint8 VALU slices."""
     from paper_1705_08210_amd import ps
     n_v, n_f = 1024, 4096
-    V, a, L = workloads.nested_support(n_v, n_f, seed=52)
-    announce("scale 3-way nested support 4096x1024 full")
-    c3 = host(ps.ps3(to_dev(V)))
+    V, a, L = workloads.nested_support(n_v, n_f, seed=52, integer=kind != "f32")
+    announce(f"scale 3-way nested support 4096x1024 {kind} full")
+    kw = {"f32": {}, "u8_mfma": dict(path="mfma", levels=3),
+          "u8_valu": dict(path="valu")}[kind]
+    c3 = host(ps.ps3(to_dev(V), **kw))
     s = a * L
     pos = 0
     for j in range(1, n_v - 1):
