@@ -99,11 +99,13 @@ __device__ __forceinline__ uint32_t u8_min_sum(uint32_t sad, int32_t n2_pair, do
     return (uint32_t)(((int64_t)n2_pair + (int64_t)s_single - (int64_t)sad) / 2);
 }
 
-// 3-way over the flattened rows (kSlabFlat): one workgroup per (row tile of
-// BM consecutive pairs (i, j) in colex order, column tile of BM k's from the
-// row tile's first j + 1), field chunk.  The A operand row of pair (i, j) is
-// X_j's column i, min(v_i, v_j), formed while staging; entries with k <= j
-// are computed by waves that also hold wanted ones and never stored.
+// 3-way over pair rows (kSlabFlat, and part 0 of kSlabSplit): one workgroup
+// per (row tile of BM consecutive pairs (i, j) in colex order, column tile of
+// BM k's from the row tile's first j + 1, field chunk).  The A operand row of
+// pair (i, j) is X_j's column i, min(v_i, v_j), formed while staging; entries
+// with k <= j are computed by waves that also hold wanted ones and never
+// stored.  Part 1 of kSlabSplit: row tiles of lex pairs (j, k) against
+// column tiles of i (store_slice_lex).
 template <int DT, int TM>
 __device__ __forceinline__ void store_slice_flat(const typename Ops<DT>::Acc (&acc)[TM][TM],
                                                  int64_t p0, int64_t pend, int64_t col0,

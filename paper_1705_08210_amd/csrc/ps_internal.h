@@ -75,10 +75,11 @@ __host__ __device__ inline int64_t slab_offset(int64_t n, int64_t j) {
 // rectangle exactly once, with edge waste at the bm granularity only.
 // kSlabRange counts ranges of bm consecutive outputs of the slab instead
 // (the elementwise 3-way finish).
-// kSlabFlat (the VALU slices) does not tile slab by slab: see flat_* below.
-// kSlabSplit (the VALU slices): kSlabFlat over the slabs below the split
-// point split3, then the lex-ordered tiling (lex_* below) over the
-// rest, in one launch.
+// kSlabFlat does not tile slab by slab: its rows are the colex pairs of the
+// stage (flat_* below).  kSlabSplit (the VALU slices): kSlabFlat over the
+// slabs below the split point split3, then the lex-ordered tiling (lex_*
+// below) over the rest, in one launch.  The per-slab sets serve the
+// matrix-core slices' per-slab tiling and the finish.
 enum { kSlabAll = 0, kSlabFull = 1, kSlabEdge = 2, kSlabRange = 3, kSlabFlat = 4, kSlabSplit = 5 };
 
 // Pair (i, j), i < j, has colex index p = j (j - 1) / 2 + i.  pair_j(p) is
@@ -483,7 +484,8 @@ hipError_t launch_mfma3(const MfmaLaunch& a, hipStream_t st);
 hipError_t launch_prefix3(int64_t n_v, int64_t jb, int64_t je, int bm, int mode, int ob,
                           int64_t* prefix, hipStream_t st);
 // prefix[rt] = column tiles of the flattened row tiles 0 .. rt-1,
-// rt = 0 .. flat_row_tiles(jb, je, bm).
+// rt = 0 .. flat_row_tiles(jb, je, bm) (with lex: of the lex-ordered row
+// tiles, rt = 0 .. lex_row_tiles(n_v, jb, je, bm)).
 hipError_t launch_prefix3_flat(int64_t n_v, int64_t jb, int64_t je, int bm, int64_t* prefix,
                                hipStream_t st, bool lex = false);
 // Both parts of the split tiling of a stage (colex slabs [jb, js) into
