@@ -172,6 +172,7 @@ KERNEL_SOURCES = {
     "ps_mg3f_kernel": _VALU_SOURCES,
     "ps_mgb_kernel": _VALU_SOURCES,
     "ps_mfma2_lv_kernel": _MFMA_SOURCES,
+    "ps_mfma2_lvd_kernel": _MFMA_SOURCES,
     "ps_mfma2_kernel": _MFMA_SOURCES,
     "ps_mfma2_dma_kernel": _MFMA_SOURCES,
     "ps_mfma3_lv_kernel": _MFMA_SOURCES,
@@ -494,7 +495,8 @@ def measure(args, wl, K, W, with_cpu=True):
             kernel = "ps_mfma2_dma_kernel"
         elif path == "mfma":   # thermometer levels: `levels` int8 MACs (2 ops) per comparison
             dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
-            kernel = "ps_mfma2_kernel" if args.tile == 2 else "ps_mfma2_lv_kernel"
+            kernel = ("ps_mfma2_kernel" if args.tile == 2 else
+                      "ps_mfma2_lvd_kernel" if n_f % 64 == 0 else "ps_mfma2_lv_kernel")
         elif V.dtype == np.uint8:   # v_sad_u8: 4 comparisons per op
             dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
             kernel = "ps_mg2_kernel"

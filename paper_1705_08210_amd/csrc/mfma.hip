@@ -446,6 +446,11 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_ke
 //     levels * n_f < 2^24.
 // For the 3-way slices the B rows are min(v_i, v_j) bytewise, formed while
 // staging ([min(a, b) >= t] = [a >= t][b >= t]).
+// Kernels: ps_mfma2_lvd_kernel (2-way, rows 16-byte aligned and n_f a
+// multiple of 64: stages go straight into LDS), ps_mfma2_lv_kernel (2-way,
+// any rows: staged through registers, fields past n_f cleared),
+// ps_mfma3_lvs_kernel (3-way split tiling) and ps_mfma3_lv_kernel (3-way
+// per-slab tiles).
 // ---------------------------------------------------------------------------
 constexpr int kLvMK = 128;   // fields per field tile (one byte each)
 enum { kLvPerm = 0, kLvSub = 1 };
@@ -883,6 +888,8 @@ __device__ __forceinline__ void lv_tile_sb(const LvArgs& a, SA& sa, SB& sb, bool
 
 // 2-way half tiles: work item t2 is half t2 % 2 (output columns 0-127 or
 // 128-255) of 256 x 256 tile t2 / 2, four waves, two workgroups per CU.
+// Register staging with the fields past n_f cleared: the launch for rows
+// that are not 16-byte aligned or n_f not a multiple of kLvdMK.
 template <int WN, bool ALIGNED, int LC, int MODE>
 __global__ __launch_bounds__(256, 2) void ps_mfma2_lv_kernel(LvArgs a) {
     __shared__ __attribute__((aligned(16))) int8_t lds[(kMB + kMB / 2) * (kLvMK + kPad)];
@@ -1394,11 +1401,174 @@ static bool lv_aligned(const MfmaLaunch& m) {
     return (uintptr_t)m.V % 16 == 0 && m.ld % 16 == 0;
 }
 
+// 2-way half tiles with LDS-direct staging (rows 16-byte aligned, n_f a
+// multiple of kLvdMK): stages of kLvdMK fields of the tile's 384 rows (256 j
+// rows, then 128 i rows) go from global memory straight into a ring of
+// kLvdStages LDS slots (global_load_lds_dwordx4: one wave instruction fills
+// 1 KB, 16 rows of 64 bytes, lane l at byte 16 l), two stages ahead of the
+// multiply-adds, so no registers hold staged data and the fragment reads of
+// the next k-step are in flight while a k-step runs.  16-byte chunk c of
+// row r sits at chunk position c ^ lvd_swz(r).  Rows past n_v load row
+// n_v - 1 (their outputs are never stored).  One barrier per stage.
+constexpr int kLvdMK = 64;
+constexpr int kLvdStages = 3;
+
+// Chunk swizzle of 64-byte rows: for every chunk c, the slots of any 8
+// consecutive rows are distinct modulo 128 bytes and those of any 16
+// consecutive rows distinct modulo 256 bytes (b128 fragment reads free of
+// bank conflicts whether the LDS serves 8 or 16 lanes at once); rows r and
+// r + 32 share a swizzle.
+__device__ __forceinline__ int lvd_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// This wave's stage loads but the N most recent have landed and its LDS
+// accesses are done, then the barrier; the empty asm statements keep the
+// compiler from moving memory accesses across.
+template <int N>
+__device__ __forceinline__ void lvd_sync() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (0x7 << 4) | ((N >> 4) << 14));   // lgkmcnt 0
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int LC, int MODE>
+__global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
+    constexpr int MK = kLvdMK;
+    constexpr int kRowsA = kMB;                      // j rows; the i rows follow
+    constexpr int kRows = kMB + kMB / 2;
+    constexpr int kStageBytes = kRows * MK;
+    constexpr int NU = kStageBytes / 1024 / 4;       // wave instructions per stage
+    constexpr int WM = 4, WN = 2, KS = MK / 32;
+    static_assert(NU * 4 * 1024 == kStageBytes, "stage split");
+    __shared__ __attribute__((aligned(1024))) int8_t lds[kLvdStages * kStageBytes];
+    const int64_t t2 = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                       blockIdx.x / kXcds;
+    if (t2 >= 2 * a.ntiles) return;
+    int64_t bi, bj;
+    grouped_tri_decode_rt(t2 / 2, a.nb, a.group, bi, bj);
+    const int64_t i0 = bi * kMB + (t2 % 2) * (kMB / 2), j0 = bj * kMB;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int wr = (wave % 2) * 128;        // j offset of the wave's block (A rows)
+    const int wc = (wave / 2) * 32 * WN;    // i offset (B rows)
+    const bool active = (i0 + wc < a.n_v) && (j0 + wr < a.n_v) && (i0 + wc + 1 < j0 + wr + 128);
+    const uint8_t* src[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int row = (wave + 4 * u) * 16 + lane / 4;
+        const int c = (lane % 4) ^ lvd_swz(row);
+        int64_t g = row < kRowsA ? j0 + row : i0 + (row - kRowsA);
+        if (g >= a.n_v) g = a.n_v - 1;
+        src[u] = a.V + g * a.ld + c * 16;
+    }
+    auto issue = [&](int64_t s, int slot) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            __builtin_amdgcn_global_load_lds(
+                (const void*)(src[u] + s * MK),
+                (void*)(lds + slot * kStageBytes + (wave + 4 * u) * 1024), 16, 0, 0);
+    };
+    v16i_t acc[WM][WN];
+#pragma unroll
+    for (int m = 0; m < WM; ++m)
+#pragma unroll
+        for (int n = 0; n < WN; ++n) acc[m][n] = (v16i_t){};
+    const int L = LC > 0 ? LC : a.levels;
+    const int fr = lane % 32, hk = lane / 32;
+    const int sw = lvd_swz(fr);   // the swizzle of rows wr + m 32 + fr and wc + n 32 + fr
+    auto compute = [&](int slot) {
+        const int8_t* A = lds + slot * kStageBytes;
+        const int8_t* B = A + kRowsA * MK;
+        auto frag = [&](int ks, v4i_t (&fa)[WM], v4i_t (&fb)[WN]) {
+            const int co = ((ks * 2 + hk) ^ sw) * 16;
+#pragma unroll
+            for (int m = 0; m < WM; ++m)
+                fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * MK + co);
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+                fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * MK + co);
+            if constexpr (MODE == kLvSub) {   // the subtraction form wants bit 7 set
+                const int h = (int)0x80808080u;
+#pragma unroll
+                for (int m = 0; m < WM; ++m) fa[m] |= h;
+#pragma unroll
+                for (int n = 0; n < WN; ++n) fb[n] |= h;
+            }
+        };
+        auto level = [&](const v4i_t (&fa)[WM], const v4i_t (&fb)[WN], int t) {
+            v4i_t xa[WM], xb[WN];
+            if constexpr (MODE == kLvPerm) {
+                const uint32_t lo = t <= 3 ? 0x01010101u << (8 * t) : 0u;
+                const uint32_t hi = t <= 4 ? 0x01010101u : 0x01010101u << (8 * (t - 4));
+#pragma unroll
+                for (int m = 0; m < WM; ++m) xa[m] = lv_perm(fa[m], hi, lo);
+#pragma unroll
+                for (int n = 0; n < WN; ++n) xb[n] = lv_perm(fb[n], hi, lo);
+            } else {
+                const uint32_t tt = (uint32_t)t * 0x01010101u;
+#pragma unroll
+                for (int m = 0; m < WM; ++m) xa[m] = lv_suba(fa[m], tt);
+#pragma unroll
+                for (int n = 0; n < WN; ++n) xb[n] = lv_subb(fb[n], tt);
+            }
+#pragma unroll
+            for (int m = 0; m < WM; ++m)
+#pragma unroll
+                for (int n = 0; n < WN; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[m], xb[n], acc[m][n],
+                                                                      0, 0, 0);
+        };
+        v4i_t fa[2][WM], fb[2][WN];
+        frag(0, fa[0], fb[0]);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks + 1 < KS) frag(ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
+#pragma unroll(LC > 0 ? LC : 1)
+            for (int t = 1; t <= L; ++t) level(fa[ks & 1], fb[ks & 1], t);
+        }
+    };
+    const int64_t ns = a.n_f / MK;
+    issue(0, 0);
+    if (ns > 1) issue(1, 1);
+    int slot = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        // stage s landed everywhere; slot (s + 2) % 3 (stage s - 1) no longer read
+        if (s + 1 < ns)
+            lvd_sync<NU>();
+        else
+            lvd_sync<0>();
+        if (s + 2 < ns) issue(s + 2, slot == 0 ? 2 : slot - 1);
+        if (active) compute(slot);
+        slot = slot == 2 ? 0 : slot + 1;
+    }
+    if constexpr (MODE == kLvSub) {
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[m][n][r] = -acc[m][n][r] >> 7;
+    }
+    if (!active) return;
+    MfmaArgs e{};
+    e.n_v = a.n_v;
+    e.s = a.s;
+    e.c2 = a.c2;
+    e.n2 = a.n2;
+    mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
+}
+
 template <bool ALIGNED, int LC, int MODE>
 static hipError_t go_mfma2_lv(const MfmaLaunch& m, hipStream_t st) {
     LvArgs a = lv_args(m);
     a.nb = (m.n_v + kMB - 1) / kMB;
     a.ntiles = a.nb * (a.nb + 1) / 2;
+    if (ALIGNED && m.n_f >= kLvdMK && m.n_f % kLvdMK == 0)
+        return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
+            LvArgs b = a;
+            b.item0 = item0;
+            hipLaunchKernelGGL((ps_mfma2_lvd_kernel<LC, MODE>), dim3(grid), dim3(256), 0, st, b);
+        });
     return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
         LvArgs b = a;
         b.item0 = item0;
@@ -1507,7 +1677,8 @@ static hipError_t go_lv(const MfmaLaunch& m, hipStream_t st) {
 // 16-byte chunk c of row r sits at chunk position c ^ dma_swz(r).  Rows past
 // n_v load row n_v - 1 (their outputs are never stored).
 // Measured on the int8 planes the register-staged kernel above is faster
-// (it is kept for int8); on fp4 this one is.
+// (it is kept for int8 planes); on fp4 this one is.  (The fused int8 level
+// tiles have an LDS-direct form of their own, ps_mfma2_lvd_kernel.)
 // ---------------------------------------------------------------------------
 constexpr int kDmaMK = 128;
 

@@ -225,7 +225,9 @@ def test_sampled_pairs_match_listed_oracle():
 @pytest.mark.parametrize("wide", [0, 2])
 @pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
 @pytest.mark.parametrize("n_v,n_f,L", [(300, 1001, 3), (257, 64, 1), (513, 333, 7),
-                                       (2, 5, 3), (256, 128, 3), (40, 3000, 15)])
+                                       (2, 5, 3), (256, 128, 3), (40, 3000, 15),
+                                       (300, 1024, 3), (513, 320, 7), (41, 3008, 15),
+                                       (1000, 192, 2)])
 def test_mfma_thermometer_bit_exact(n_v, n_f, L, path, wide):
     """min(a,b) = sum_t [a>=t][b>=t] on integer levels: the int8 matrix-core
     path must equal the oracle (and the VALU path) bit for bit."""

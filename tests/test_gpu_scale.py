@@ -70,16 +70,17 @@ def test_sparse_4096x1024_3way_sampled(storage):
         print(f"fp16 storage vs fp32 source: max abs {ea:.3e} max rel {er:.3e}")
 
 
-@pytest.mark.parametrize("kind", ["f32", "u8_mfma"])
+@pytest.mark.parametrize("kind", ["f32", "u8_mfma", "u8_mfma_lds"])
 def test_nested_support_2way_full_size_exact(kind):
     """Every one of the 1.34e8 outputs at the benchmark's size, against the
     closed form, bit for bit: FP32 data on the VALU tiles, integer levels on
-    the int8 matrix-core half tiles."""
+    the int8 matrix-core half tiles (n_f = 20000 with register staging; a
+    multiple of 64 fields with staging straight into LDS)."""
     from paper_1705_08210_amd import ps
-    n_v, n_f = 16384, 20000
+    n_v, n_f = 16384, 19968 if kind == "u8_mfma_lds" else 20000
     V, a, L = workloads.nested_support(n_v, n_f, seed=51, integer=kind != "f32")
-    announce(f"scale 2-way nested support 20000x16384 {kind} full")
-    kw = dict(path="mfma", levels=3) if kind == "u8_mfma" else {}
+    announce(f"scale 2-way nested support {n_f}x{n_v} {kind} full")
+    kw = dict(path="mfma", levels=3) if kind.startswith("u8_mfma") else {}
     c2 = host(ps.ps2(to_dev(V), **kw)[0])
     del V
     s = a * L
