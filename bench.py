@@ -177,6 +177,7 @@ KERNEL_SOURCES = {
     "ps_mfma2_dma_kernel": _MFMA_SOURCES,
     "ps_mfma3_lv_kernel": _MFMA_SOURCES,
     "ps_mfma3_lvs_kernel": _MFMA_SOURCES,
+    "ps_mfma3_lvsd_kernel": _MFMA_SOURCES,
     "ps_mfma3_kernel": _MFMA_SOURCES,
 }
 PROFILES = os.path.join(ROOT, "profiles")
@@ -588,7 +589,9 @@ def measure(args, wl, K, W, with_cpu=True):
         elif path == "mfma":
             dtype, bound, ops_per_cmp, peak = "u8", "mfma", 2.0 * levels, INT8_MFMA_PEAK_TOPS
             # opts.tile 2: per-slab tiles; else the split tiling (pairs x vectors)
-            kernel = "ps_mfma3_lv_kernel" if args.tile == 2 else "ps_mfma3_lvs_kernel"
+            kernel = ("ps_mfma3_lv_kernel" if args.tile == 2 else
+                      "ps_mfma3_lvsd_kernel" if levels == 3 and n_f % 64 == 0 else
+                      "ps_mfma3_lvs_kernel")
         elif V.dtype == np.uint8:
             dtype, bound, ops_per_cmp, peak = "u8", "alu", 0.25, HALF_RATE_OPS_TOPS
             kernel = "ps_mg3f_kernel"

@@ -449,8 +449,10 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_ke
 // Kernels: ps_mfma2_lvd_kernel (2-way, rows 16-byte aligned and n_f a
 // multiple of 64: stages go straight into LDS), ps_mfma2_lv_kernel (2-way,
 // any rows: staged through registers, fields past n_f cleared),
-// ps_mfma3_lvs_kernel (3-way split tiling) and ps_mfma3_lv_kernel (3-way
-// per-slab tiles).
+// ps_mfma3_lvsd_kernel (3-way split tiling, three levels on aligned rows
+// with n_f a multiple of 64: plain rows straight into LDS, pair rows through
+// registers), ps_mfma3_lvs_kernel (3-way split tiling, any rows and levels)
+// and ps_mfma3_lv_kernel (3-way per-slab tiles).
 // ---------------------------------------------------------------------------
 constexpr int kLvMK = 128;   // fields per field tile (one byte each)
 enum { kLvPerm = 0, kLvSub = 1 };
@@ -1432,6 +1434,63 @@ __device__ __forceinline__ void lvd_sync() {
     asm volatile("" ::: "memory");
 }
 
+// One kLvdMK-field stage of a wave's 128 x 64 block: A rows wr + 0..127 and
+// B rows wc + 0..63 of LDS regions of 64-byte rows in the lvd_swz layout
+// (wr, wc multiples of 32); the fragments of the second k-step are read
+// while the first runs.
+template <int LC, int MODE>
+__device__ __forceinline__ void lvd_stage(const int8_t* A, const int8_t* B, int wr, int wc, int L,
+                                          v16i_t (&acc)[4][2]) {
+    constexpr int MK = kLvdMK, WM = 4, WN = 2, KS = MK / 32;
+    const int lane = threadIdx.x % 64;
+    const int fr = lane % 32, hk = lane / 32;
+    const int sw = lvd_swz(fr);   // the swizzle of rows wr + m 32 + fr and wc + n 32 + fr
+    auto frag = [&](int ks, v4i_t (&fa)[WM], v4i_t (&fb)[WN]) {
+        const int co = ((ks * 2 + hk) ^ sw) * 16;
+#pragma unroll
+        for (int m = 0; m < WM; ++m) fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * MK + co);
+#pragma unroll
+        for (int n = 0; n < WN; ++n) fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * MK + co);
+        if constexpr (MODE == kLvSub) {   // the subtraction form wants bit 7 set
+            const int h = (int)0x80808080u;
+#pragma unroll
+            for (int m = 0; m < WM; ++m) fa[m] |= h;
+#pragma unroll
+            for (int n = 0; n < WN; ++n) fb[n] |= h;
+        }
+    };
+    auto level = [&](const v4i_t (&fa)[WM], const v4i_t (&fb)[WN], int t) {
+        v4i_t xa[WM], xb[WN];
+        if constexpr (MODE == kLvPerm) {
+            const uint32_t lo = t <= 3 ? 0x01010101u << (8 * t) : 0u;
+            const uint32_t hi = t <= 4 ? 0x01010101u : 0x01010101u << (8 * (t - 4));
+#pragma unroll
+            for (int m = 0; m < WM; ++m) xa[m] = lv_perm(fa[m], hi, lo);
+#pragma unroll
+            for (int n = 0; n < WN; ++n) xb[n] = lv_perm(fb[n], hi, lo);
+        } else {
+            const uint32_t tt = (uint32_t)t * 0x01010101u;
+#pragma unroll
+            for (int m = 0; m < WM; ++m) xa[m] = lv_suba(fa[m], tt);
+#pragma unroll
+            for (int n = 0; n < WN; ++n) xb[n] = lv_subb(fb[n], tt);
+        }
+#pragma unroll
+        for (int m = 0; m < WM; ++m)
+#pragma unroll
+            for (int n = 0; n < WN; ++n)
+                acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[m], xb[n], acc[m][n], 0, 0, 0);
+    };
+    v4i_t fa[2][WM], fb[2][WN];
+    frag(0, fa[0], fb[0]);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        if (ks + 1 < KS) frag(ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
+#pragma unroll(LC > 0 ? LC : 1)
+        for (int t = 1; t <= L; ++t) level(fa[ks & 1], fb[ks & 1], t);
+    }
+}
+
 template <int LC, int MODE>
 __global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
     constexpr int MK = kLvdMK;
@@ -1439,7 +1498,7 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
     constexpr int kRows = kMB + kMB / 2;
     constexpr int kStageBytes = kRows * MK;
     constexpr int NU = kStageBytes / 1024 / 4;       // wave instructions per stage
-    constexpr int WM = 4, WN = 2, KS = MK / 32;
+    constexpr int WM = 4, WN = 2;
     static_assert(NU * 4 * 1024 == kStageBytes, "stage split");
     __shared__ __attribute__((aligned(1024))) int8_t lds[kLvdStages * kStageBytes];
     const int64_t t2 = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
@@ -1474,58 +1533,9 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
 #pragma unroll
         for (int n = 0; n < WN; ++n) acc[m][n] = (v16i_t){};
     const int L = LC > 0 ? LC : a.levels;
-    const int fr = lane % 32, hk = lane / 32;
-    const int sw = lvd_swz(fr);   // the swizzle of rows wr + m 32 + fr and wc + n 32 + fr
     auto compute = [&](int slot) {
         const int8_t* A = lds + slot * kStageBytes;
-        const int8_t* B = A + kRowsA * MK;
-        auto frag = [&](int ks, v4i_t (&fa)[WM], v4i_t (&fb)[WN]) {
-            const int co = ((ks * 2 + hk) ^ sw) * 16;
-#pragma unroll
-            for (int m = 0; m < WM; ++m)
-                fa[m] = *(const v4i_t*)(A + (wr + m * 32 + fr) * MK + co);
-#pragma unroll
-            for (int n = 0; n < WN; ++n)
-                fb[n] = *(const v4i_t*)(B + (wc + n * 32 + fr) * MK + co);
-            if constexpr (MODE == kLvSub) {   // the subtraction form wants bit 7 set
-                const int h = (int)0x80808080u;
-#pragma unroll
-                for (int m = 0; m < WM; ++m) fa[m] |= h;
-#pragma unroll
-                for (int n = 0; n < WN; ++n) fb[n] |= h;
-            }
-        };
-        auto level = [&](const v4i_t (&fa)[WM], const v4i_t (&fb)[WN], int t) {
-            v4i_t xa[WM], xb[WN];
-            if constexpr (MODE == kLvPerm) {
-                const uint32_t lo = t <= 3 ? 0x01010101u << (8 * t) : 0u;
-                const uint32_t hi = t <= 4 ? 0x01010101u : 0x01010101u << (8 * (t - 4));
-#pragma unroll
-                for (int m = 0; m < WM; ++m) xa[m] = lv_perm(fa[m], hi, lo);
-#pragma unroll
-                for (int n = 0; n < WN; ++n) xb[n] = lv_perm(fb[n], hi, lo);
-            } else {
-                const uint32_t tt = (uint32_t)t * 0x01010101u;
-#pragma unroll
-                for (int m = 0; m < WM; ++m) xa[m] = lv_suba(fa[m], tt);
-#pragma unroll
-                for (int n = 0; n < WN; ++n) xb[n] = lv_subb(fb[n], tt);
-            }
-#pragma unroll
-            for (int m = 0; m < WM; ++m)
-#pragma unroll
-                for (int n = 0; n < WN; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[m], xb[n], acc[m][n],
-                                                                      0, 0, 0);
-        };
-        v4i_t fa[2][WM], fb[2][WN];
-        frag(0, fa[0], fb[0]);
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            if (ks + 1 < KS) frag(ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
-#pragma unroll(LC > 0 ? LC : 1)
-            for (int t = 1; t <= L; ++t) level(fa[ks & 1], fb[ks & 1], t);
-        }
+        lvd_stage<LC, MODE>(A, A + kRowsA * MK, wr, wc, L, acc);
     };
     const int64_t ns = a.n_f / MK;
     issue(0, 0);
@@ -1556,6 +1566,203 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
     e.c2 = a.c2;
     e.n2 = a.n2;
     mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
+}
+
+// Half h of tile t of part PART of the split tiling with LDS-direct stages
+// (rows 16-byte aligned, n_f a multiple of kLvdMK): the tiles, waves and
+// epilogues of lvs_tile, with the half's 256 plain rows (part 0: the k rows,
+// part 1: the i rows) loaded straight into a ring of kLvdStages LDS slots
+// and its 128 pair rows formed in registers (bytewise mins) and written into
+// the same slots, both two stages ahead of the multiply-adds.  A slot holds
+// the plain rows, then the pair rows, 64 bytes each in the lvd_swz layout.
+// Plain rows past n_v load row n_v - 1 (their outputs are never stored).
+// Per stage: the pair loads, then the plain-row loads of stage s + 2 are
+// issued, stage s runs, the pair rows go to LDS once their loads (all but
+// the newest plain-row loads) have landed, and a barrier.
+template <int PART, int LC, int MODE>
+__device__ __forceinline__ void lvsd_tile(const LvArgs& a, int64_t t, int h, int8_t* lds) {
+    constexpr int TB = kMB, WN = 2, HB = TB / 2, MK = kLvdMK;
+    constexpr int kStageBytes = (TB + HB) * MK;
+    constexpr int NU = TB * MK / 1024 / 4;   // plain-row wave instructions per stage
+    constexpr int NP = HB * MK / 16 / 256;   // pair-row chunks per thread per stage
+    static_assert(NU * 4 * 1024 == TB * MK && NP * 256 * 16 == HB * MK, "stage split");
+    const int64_t* pre = a.pre[PART];
+    int64_t lo = 0, hi = a.nrt[PART];
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (pre[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int64_t ct = t - pre[lo];
+    const int64_t n = a.n_v;
+    const int64_t r0 = a.r_begin[PART] + lo * TB, re = a.r_end[PART];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    int64_t g0;        // first plain row
+    int64_t k0 = 0, i0 = 0, qa = 0;
+    int wr, wl, wc;    // the wave's A rows, B rows (LDS) and output columns in the tile
+    bool active;
+    int ox[NP], oy[NP];
+    auto pair_offsets = [&](auto pair) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            const int q = (int)threadIdx.x + 256 * c;
+            int64_t x, y;
+            pair(q / 4, x, y);
+            ox[c] = (int)(x * a.ld) + (q % 4) * 16;
+            oy[c] = (int)(y * a.ld) + (q % 4) * 16;
+        }
+    };
+    if constexpr (PART == 0) {
+        k0 = pair_j(r0) + 1 + ct * TB;
+        g0 = k0;
+        wr = (wave % 2) * (TB / 2);
+        wl = (wave / 2) * 32 * WN;
+        wc = h * HB + wl;
+        const int64_t pq = r0 + wc;
+        const int64_t kq = k0 + wr + TB / 2 - 1 < n - 1 ? k0 + wr + TB / 2 - 1 : n - 1;
+        active = k0 + wr < n && pq < re && pair_j(pq) < kq;
+        pair_offsets([&](int r, int64_t& x, int64_t& y) {
+            const int64_t p = r0 + h * HB + r < re ? r0 + h * HB + r : re - 1;
+            y = pair_j(p);
+            x = p - y * (y - 1) / 2;
+        });
+    } else {
+        i0 = ct * TB;
+        g0 = i0;
+        qa = r0 + h * HB;
+        const int64_t qz = qa + HB - 1 < re ? qa + HB - 1 : re - 1;
+        wr = 0;
+        wl = wave * 32 * WN;
+        wc = wl;
+        int64_t jz, kz;
+        lex_pair(n, qz, jz, kz);
+        active = qa < re && i0 + wl < jz;
+        pair_offsets([&](int r, int64_t& x, int64_t& y) {
+            lex_pair(n, qa + r < re ? qa + r : re - 1, x, y);
+        });
+    }
+    const uint8_t* src[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int row = (wave + 4 * u) * 16 + lane / 4;
+        const int c = (lane % 4) ^ lvd_swz(row);
+        const int64_t g = g0 + row < n ? g0 + row : n - 1;
+        src[u] = a.V + g * a.ld + c * 16;
+    }
+    int pd[NP];   // LDS byte offsets of this thread's pair chunks within a slot
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        const int q = (int)threadIdx.x + 256 * c, r = q / 4;
+        pd[c] = (TB + r) * MK + ((q % 4) ^ lvd_swz(r)) * 16;
+    }
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.V, (short)0, (int)(n * a.ld), kRsrcWord3);
+    uint4 px[NP], py[NP];
+    auto pload = [&](int64_t s) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            px[c] = lv_load16<true>(rs, ox[c] + (int)s * MK);
+            py[c] = lv_load16<true>(rs, oy[c] + (int)s * MK);
+        }
+    };
+    auto dma = [&](int64_t s, int slot) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            __builtin_amdgcn_global_load_lds(
+                (const void*)(src[u] + s * MK),
+                (void*)(lds + slot * kStageBytes + (wave + 4 * u) * 1024), 16, 0, 0);
+    };
+    auto issue = [&](int64_t s, int slot) {
+        pload(s);
+        asm volatile("" ::: "memory");   // pair loads first: their wait leaves the DMA in flight
+        dma(s, slot);
+    };
+    auto pstore = [&](int slot) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            const uint4 x = lv_prep<MODE>(px[c], 16), y = lv_prep<MODE>(py[c], 16);
+            *(uint4*)(lds + slot * kStageBytes + pd[c]) =
+                make_uint4(lv_min<MODE>(x.x, y.x), lv_min<MODE>(x.y, y.y),
+                           lv_min<MODE>(x.z, y.z), lv_min<MODE>(x.w, y.w));
+        }
+    };
+    v16i_t acc[4][WN];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int nn = 0; nn < WN; ++nn) acc[m][nn] = (v16i_t){};
+    const int L = LC > 0 ? LC : a.levels;
+    const int64_t ns = a.n_f / MK;
+    issue(0, 0);
+    pstore(0);
+    if (ns > 1) {
+        issue(1, 1);
+        pstore(1);
+    }
+    // stage s: stage s complete everywhere and slot (s + 2) % 3 (stage
+    // s - 1) no longer read, then stage s + 2 in flight while s runs (one loop
+    // for waves with work, one for the rest: a branch inside the loop makes
+    // the accumulators spill)
+    auto run = [&](auto compute) {
+        int slot = 0;
+        for (int64_t s = 0; s < ns; ++s) {
+            if (s + 1 < ns)
+                lvd_sync<NU>();
+            else
+                lvd_sync<0>();
+            const int sn = slot == 0 ? 2 : slot - 1;
+            if (s + 2 < ns) issue(s + 2, sn);
+            compute(slot);
+            if (s + 2 < ns) pstore(sn);
+            slot = slot == 2 ? 0 : slot + 1;
+        }
+    };
+    if (active)
+        run([&](int slot) {
+            const int8_t* P = lds + slot * kStageBytes;   // plain rows
+            const int8_t* Q = P + TB * MK;                 // pair rows
+            if constexpr (PART == 0)
+                lvd_stage<LC, MODE>(P, Q, wr, wl, L, acc);
+            else
+                lvd_stage<LC, MODE>(Q, P, wr, wl, L, acc);
+        });
+    else
+        run([](int) {});
+    if constexpr (MODE == kLvSub) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WN; ++nn)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[m][nn][r] = -acc[m][nn][r] >> 7;
+    }
+    // the epilogue's row data goes to slot (ns + 1) % 3, last read by stage
+    // ns - 2 before the barrier of stage ns - 1
+    int8_t* ep = lds + (int)((ns + 1) % 3) * kStageBytes;
+    if constexpr (PART == 0) {
+        if (a.f32div)
+            lvs_epilogue0<true>(a, acc, r0, k0, wr, wc, active, ep);
+        else
+            lvs_epilogue0<false>(a, acc, r0, k0, wr, wc, active, ep);
+    } else {
+        if (a.f32div)
+            lvs_epilogue1<true, HB>(a, acc, qa, i0, 0, wl, active, ep);
+        else
+            lvs_epilogue1<false, HB>(a, acc, qa, i0, 0, wl, active, ep);
+    }
+}
+
+template <int LC, int MODE>
+__global__ __launch_bounds__(256, 2) void ps_mfma3_lvsd_kernel(LvArgs a) {
+    __shared__ __attribute__((aligned(1024))) int8_t lds[kLvdStages * (kMB + kMB / 2) * kLvdMK];
+    const int64_t t2 = a.item0 + (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) +
+                       blockIdx.x / kXcds;
+    if (t2 >= 2 * a.ntiles) return;
+    const int64_t t = t2 / 2;
+    const int h = (int)(t2 % 2);
+    if (t < a.nt[0])
+        lvsd_tile<0, LC, MODE>(a, t, h, lds);
+    else
+        lvsd_tile<1, LC, MODE>(a, t - a.nt[0], h, lds);
 }
 
 template <bool ALIGNED, int LC, int MODE>
@@ -1603,6 +1810,17 @@ static hipError_t go_mfma3_lvs(const MfmaLaunch& m, hipStream_t st) {
     hipError_t e = launch_prefix3_split(n, jb, js, je, kMB, m.prefix, m.prefix + a.nrt[0] + 1, st);
     if (e != hipSuccess) return e;
     a.ntiles = a.nt[0] + a.nt[1];
+    // LDS-direct stages for three levels (the other level counts run their
+    // level loop at run time, which spills the accumulators in that kernel)
+    if constexpr (LC == 3) {
+        if (ALIGNED && m.n_f >= kLvdMK && m.n_f % kLvdMK == 0)
+            return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
+                LvArgs b = a;
+                b.item0 = item0;
+                hipLaunchKernelGGL((ps_mfma3_lvsd_kernel<LC, MODE>), dim3(grid), dim3(256), 0,
+                                   st, b);
+            });
+    }
     return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
         LvArgs b = a;
         b.item0 = item0;

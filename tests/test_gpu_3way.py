@@ -166,6 +166,31 @@ def test_mfma_3way_exact(path, n_v, n_f):
     check_exact_f32(c3, oracle.c3_all(V), "c3")
 
 
+@pytest.mark.parametrize("n_v,n_f", [(3, 64), (140, 320), (300, 192), (520, 128)])
+def test_mfma_3way_lds_direct_stages_exact(n_v, n_f):
+    """Three levels on aligned rows with n_f a multiple of 64 (the split
+    tiling with its plain rows staged straight into LDS): every triple once
+    (NaN-filled output), equal to the oracle and to the VALU path bit for
+    bit, and stages across the split point concatenate to the full run."""
+    import torch
+    from paper_1705_08210_amd import ps
+    probs = np.full(4, 0.25)
+    V = workloads.levels(n_v, n_f, seed=n_v + n_f, probs=probs)
+    Vd = to_dev(V)
+    announce(f"3-way mfma lds-direct {n_v}x{n_f}")
+    c3 = torch.full((ps.stage_size(n_v, 1, n_v - 1),), float("nan"), device=Vd.device)
+    ps.ps3(Vd, c3=c3, path="mfma", levels=3)
+    got = host(c3)
+    assert not np.isnan(got).any()
+    check_exact_f32(got, oracle.c3_all(V), "c3")
+    ref = host(ps.ps3(Vd, path="valu"))
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    cuts = sorted({1, max(1, n_v // 3), max(1, 2 * n_v // 3), n_v - 1})
+    parts = [host(ps.ps3(Vd, j_begin=a, j_end=b, path="mfma", levels=3))
+             for a, b in zip(cuts, cuts[1:])]
+    assert np.array_equal(np.concatenate(parts).view(np.uint32), got.view(np.uint32))
+
+
 @pytest.mark.parametrize("path", ["mfma", "mfma_fp4"])
 def test_mfma_3way_stages_given_inputs_and_valu(path):
     """Stages concatenate bit for bit; given s and n2 change nothing; the
