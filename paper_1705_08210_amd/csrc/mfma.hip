@@ -918,6 +918,20 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lv_kernel(LvArgs a) {
     mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
 }
 
+// n / d correctly rounded, for integers 0 <= n < 2^24 and 1 <= d < 2^24 held
+// in floats (the FP32 quotients of Eq. 1): the reciprocal refinement and the
+// two remainder corrections of the IEEE division sequence, without its range
+// scaling and special-case fix-up.  No operand, reciprocal, partial quotient
+// or remainder here is denormal, infinite or needs scaling, so those steps
+// are identities and the result is the sequence's own, the correctly rounded
+// quotient.
+__device__ __forceinline__ float div_u24(float n, float d) {
+    const float y0 = __builtin_amdgcn_rcpf(d);
+    const float y = __builtin_fmaf(__builtin_fmaf(-d, y0, 1.0f), y0, y0);
+    const float q0 = n * y;
+    const float q1 = __builtin_fmaf(__builtin_fmaf(-d, q0, n), y, q0);
+    return __builtin_fmaf(__builtin_fmaf(-d, q1, n), y, q1);
+}
 
 // Eq. 1 on exact integers for one 3-way tile (rows k0 .. k0+TB-1, columns
 // i0 .. i0+TB-1 of slab j): n3 = n2(i,j) + n2(i,k) + n2(j,k) - n3', then
@@ -1017,7 +1031,7 @@ __device__ __forceinline__ void lv3_epilogue(const LvArgs& a, const v16i_t (&acc
                 const R dd = d > (R)0 ? d : (R)1;
                 float q;
                 if constexpr (F32)
-                    q = (float)(3u * n3) / dd;
+                    q = div_u24((float)(3u * n3), dd);
                 else
                     q = (float)((3.0 * (double)n3) / dd);
                 const float c = d > (R)0 ? q : 0.0f;
@@ -1170,11 +1184,11 @@ __device__ __forceinline__ void lvs_epilogue0(const LvArgs& a, const v16i_t (&ac
                 const R dd = d > (R)0 ? d : (R)1;
                 float qv;
                 if constexpr (F32)
-                    qv = (float)(3u * n3) / dd;
+                    qv = div_u24((float)(3u * n3), dd);
                 else
                     qv = (float)((3.0 * (double)n3) / dd);
                 const float c = d > (R)0 ? qv : 0.0f;
-                const uint32_t off = ok ? (sb[nn] + (uint32_t)k * (uint32_t)jj[nn]) * 4u
+                const uint32_t off = ok ? (sb[nn] + __umul24((uint32_t)k, (uint32_t)jj[nn])) * 4u
                                         : 0x80000000u;
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, c), rc3,
                                                       (int)off, 0, 0);
@@ -1282,7 +1296,7 @@ __device__ __forceinline__ void lvs_epilogue1(const LvArgs& a, const v16i_t (&ac
                 const R dd = d > (R)0 ? d : (R)1;
                 float qv;
                 if constexpr (F32)
-                    qv = (float)(3u * n3) / dd;
+                    qv = div_u24((float)(3u * n3), dd);
                 else
                     qv = (float)((3.0 * (double)n3) / dd);
                 const float c = d > (R)0 ? qv : 0.0f;
@@ -1437,10 +1451,15 @@ __device__ __forceinline__ void lvd_sync() {
 // One kLvdMK-field stage of a wave's 128 x 64 block: A rows wr + 0..127 and
 // B rows wc + 0..63 of LDS regions of 64-byte rows in the lvd_swz layout
 // (wr, wc multiples of 32); the fragments of the second k-step are read
-// while the first runs.
-template <int LC, int MODE>
+// while the first runs.  mid() (the loads of a later stage) is issued
+// between the two k-steps, behind the first one's multiply-adds, so that
+// neither the stage's first fragment reads nor its first multiply-adds wait
+// behind the load issue (measured against issuing at the top of the stage:
+// 2-way 7.96 -> 7.74 ms, 3-way 1.75 -> 1.71 ms; after the first fragment
+// reads, 3-way 1.79 -> 1.75 ms and the 2-way unchanged).
+template <int LC, int MODE, class MID>
 __device__ __forceinline__ void lvd_stage(const int8_t* A, const int8_t* B, int wr, int wc, int L,
-                                          v16i_t (&acc)[4][2]) {
+                                          v16i_t (&acc)[4][2], MID mid) {
     constexpr int MK = kLvdMK, WM = 4, WN = 2, KS = MK / 32;
     const int lane = threadIdx.x % 64;
     const int fr = lane % 32, hk = lane / 32;
@@ -1488,6 +1507,11 @@ __device__ __forceinline__ void lvd_stage(const int8_t* A, const int8_t* B, int 
         if (ks + 1 < KS) frag(ks + 1, fa[(ks + 1) & 1], fb[(ks + 1) & 1]);
 #pragma unroll(LC > 0 ? LC : 1)
         for (int t = 1; t <= L; ++t) level(fa[ks & 1], fb[ks & 1], t);
+        if (ks == 0) {
+            asm volatile("" ::: "memory");
+            mid();
+            asm volatile("" ::: "memory");
+        }
     }
 }
 
@@ -1533,9 +1557,9 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
 #pragma unroll
         for (int n = 0; n < WN; ++n) acc[m][n] = (v16i_t){};
     const int L = LC > 0 ? LC : a.levels;
-    auto compute = [&](int slot) {
+    auto compute = [&](int slot, auto mid) {
         const int8_t* A = lds + slot * kStageBytes;
-        lvd_stage<LC, MODE>(A, A + kRowsA * MK, wr, wc, L, acc);
+        lvd_stage<LC, MODE>(A, A + kRowsA * MK, wr, wc, L, acc, mid);
     };
     const int64_t ns = a.n_f / MK;
     issue(0, 0);
@@ -1547,8 +1571,14 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
             lvd_sync<NU>();
         else
             lvd_sync<0>();
-        if (s + 2 < ns) issue(s + 2, slot == 0 ? 2 : slot - 1);
-        if (active) compute(slot);
+        const int sn = slot == 0 ? 2 : slot - 1;
+        auto mid = [&]() {
+            if (s + 2 < ns) issue(s + 2, sn);
+        };
+        if (active)
+            compute(slot, mid);
+        else
+            mid();
         slot = slot == 2 ? 0 : slot + 1;
     }
     if constexpr (MODE == kLvSub) {
@@ -1710,23 +1740,24 @@ __device__ __forceinline__ void lvsd_tile(const LvArgs& a, int64_t t, int h, int
             else
                 lvd_sync<0>();
             const int sn = slot == 0 ? 2 : slot - 1;
-            if (s + 2 < ns) issue(s + 2, sn);
-            compute(slot);
+            compute(slot, [&]() {
+                if (s + 2 < ns) issue(s + 2, sn);
+            });
             if (s + 2 < ns) pstore(sn);
             slot = slot == 2 ? 0 : slot + 1;
         }
     };
     if (active)
-        run([&](int slot) {
+        run([&](int slot, auto mid) {
             const int8_t* P = lds + slot * kStageBytes;   // plain rows
             const int8_t* Q = P + TB * MK;                 // pair rows
             if constexpr (PART == 0)
-                lvd_stage<LC, MODE>(P, Q, wr, wl, L, acc);
+                lvd_stage<LC, MODE>(P, Q, wr, wl, L, acc, mid);
             else
-                lvd_stage<LC, MODE>(Q, P, wr, wl, L, acc);
+                lvd_stage<LC, MODE>(Q, P, wr, wl, L, acc, mid);
         });
     else
-        run([](int) {});
+        run([](int, auto mid) { mid(); });
     if constexpr (MODE == kLvSub) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
