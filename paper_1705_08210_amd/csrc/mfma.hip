@@ -159,9 +159,28 @@ struct MfmaArgs {
 template <int WN, int TB = kMB>
 __host__ __device__ constexpr int mfma_threads() { return 64 * 2 * (TB / (32 * WN)); }
 
+// n / d correctly rounded, for integers 0 <= n < 2^24 and 1 <= d < 2^24 held
+// in floats (the FP32 quotients of Section 2.1 and Eq. 1): the reciprocal
+// refinement and the two remainder corrections of the IEEE division
+// sequence, without its range scaling and special-case fix-up.  No
+// operand, reciprocal, partial quotient or remainder here is denormal,
+// infinite or needs scaling, so those steps are identities and the result
+// is the sequence's own, the correctly rounded quotient.
+__device__ __forceinline__ float div_u24(float n, float d) {
+    const float y0 = __builtin_amdgcn_rcpf(d);
+    const float y = __builtin_fmaf(__builtin_fmaf(-d, y0, 1.0f), y0, y0);
+    const float q0 = n * y;
+    const float q1 = __builtin_fmaf(__builtin_fmaf(-d, q0, n), y, q0);
+    return __builtin_fmaf(__builtin_fmaf(-d, q1, n), y, q1);
+}
+
 // Epilogue of one wave's 4 x WN blocks of 32 x 32 (Section 2.1): n2 exact,
 // c2 = 2 n2 / (s_i + s_j) in FP64, rounded once to FP32, d = 0 gives 0.
-template <int WN, typename AccT>
+// F32: the same value from the FP32 division of the exact integers (both
+// below 2^24: 2 L n_f < 2^24 for L levels): the FP64 quotient lies more
+// than 2^-48 (relative) from every FP32 rounding boundary, so rounding it
+// to FP32 gives the correctly rounded FP32 quotient.
+template <int WN, bool F32 = false, typename AccT>
 __device__ __forceinline__ void mfma_epilogue(const AccT (&acc)[4][WN], const MfmaArgs& a,
                                               int64_t i0, int64_t j0, int wr, int wc,
                                               int lane) {
@@ -184,7 +203,12 @@ __device__ __forceinline__ void mfma_epilogue(const AccT (&acc)[4][WN], const Mf
                 if (a.n2) a.n2[base + i] = num;
                 if (a.c2) {
                     const double d = a.s[i] + sj;
-                    a.c2[base + i] = d > 0.0 ? (float)((2.0 * (double)num) / d) : 0.0f;
+                    if constexpr (F32) {
+                        const float q = div_u24((float)(2 * num), d > 0.0 ? (float)d : 1.0f);
+                        a.c2[base + i] = d > 0.0 ? q : 0.0f;
+                    } else {
+                        a.c2[base + i] = d > 0.0 ? (float)((2.0 * (double)num) / d) : 0.0f;
+                    }
                 }
             }
         }
@@ -475,7 +499,7 @@ struct LvArgs {
     uint32_t* c3;
     int64_t item0;
     int32_t mode, ob;
-    int32_t f32div;       // 3-way: the Eq. 1 quotient is exact in FP32
+    int32_t f32div;       // the quotient's operands are integers below 2^24 (FP32 division)
     // split 3-way tiling, part p = 0, 1: its tiles, row tiles, the prefix of
     // their column-tile counts, and its pairs [r_begin, r_end) (colex indices
     // for the (i, j) part, lex indices for the (j, k) part); tiles
@@ -915,22 +939,10 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lv_kernel(LvArgs a) {
     e.s = a.s;
     e.c2 = a.c2;
     e.n2 = a.n2;
-    mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
-}
-
-// n / d correctly rounded, for integers 0 <= n < 2^24 and 1 <= d < 2^24 held
-// in floats (the FP32 quotients of Eq. 1): the reciprocal refinement and the
-// two remainder corrections of the IEEE division sequence, without its range
-// scaling and special-case fix-up.  No operand, reciprocal, partial quotient
-// or remainder here is denormal, infinite or needs scaling, so those steps
-// are identities and the result is the sequence's own, the correctly rounded
-// quotient.
-__device__ __forceinline__ float div_u24(float n, float d) {
-    const float y0 = __builtin_amdgcn_rcpf(d);
-    const float y = __builtin_fmaf(__builtin_fmaf(-d, y0, 1.0f), y0, y0);
-    const float q0 = n * y;
-    const float q1 = __builtin_fmaf(__builtin_fmaf(-d, q0, n), y, q0);
-    return __builtin_fmaf(__builtin_fmaf(-d, q1, n), y, q1);
+    if (a.f32div)
+        mfma_epilogue<WN, true>(acc, e, i0, j0, wr, wc, lane);
+    else
+        mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
 }
 
 // Eq. 1 on exact integers for one 3-way tile (rows k0 .. k0+TB-1, columns
@@ -1595,7 +1607,10 @@ __global__ __launch_bounds__(256, 2) void ps_mfma2_lvd_kernel(LvArgs a) {
     e.s = a.s;
     e.c2 = a.c2;
     e.n2 = a.n2;
-    mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
+    if (a.f32div)
+        mfma_epilogue<WN, true>(acc, e, i0, j0, wr, wc, lane);
+    else
+        mfma_epilogue<WN>(acc, e, i0, j0, wr, wc, lane);
 }
 
 // Half h of tile t of part PART of the split tiling with LDS-direct stages
@@ -1799,6 +1814,7 @@ __global__ __launch_bounds__(256, 2) void ps_mfma3_lvsd_kernel(LvArgs a) {
 template <bool ALIGNED, int LC, int MODE>
 static hipError_t go_mfma2_lv(const MfmaLaunch& m, hipStream_t st) {
     LvArgs a = lv_args(m);
+    a.f32div = 2 * (int64_t)m.levels * m.n_f < ((int64_t)1 << 24);   // 2 n2 and s_i + s_j
     a.nb = (m.n_v + kMB - 1) / kMB;
     a.ntiles = a.nb * (a.nb + 1) / 2;
     if (ALIGNED && m.n_f >= kLvdMK && m.n_f % kLvdMK == 0)
