@@ -401,10 +401,12 @@ __device__ __forceinline__ void run_tile_flat_body(
     const int64_t nk_all = (nbytes + tile_bytes - 1) / tile_bytes;
     const int64_t nk = kt1 < 0 || kt1 > nk_all ? nk_all : kt1;
     // The plain B rows of the next field tile are prefetched into registers
-    // while this one is consumed, for the FP32 / FP16 tiles with TM = 8
-    // (measured on sparse_4096x1024: 26.4 -> 25.5 ms; the TM = 4 tiles lose
-    // a wave per SIMD to the extra registers and run slower).
-    constexpr bool kPrefetchB = (DT == PS_F32 || DT == PS_F16) && TM >= 8;
+    // while this one is consumed, for the FP32 / FP16 tiles that stage two
+    // B chunks per thread (measured on sparse_4096x1024, FP32: 128 x 128
+    // tiles with 16-word field tiles 26.5 -> 25.5 ms, 64 x 64 28.7 -> 28.3
+    // ms; the 128 x 128 tiles with 32-word field tiles stage four, lose a
+    // wave per SIMD to the extra registers and ran 28.1 -> 33.5 ms).
+    constexpr bool kPrefetchB = (DT == PS_F32 || DT == PS_F16) && SB::kCh <= 2;
     SA sa;
     SB sb;
     if (kPrefetchB && kt0 < nk)
