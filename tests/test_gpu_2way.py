@@ -227,7 +227,8 @@ def test_sampled_pairs_match_listed_oracle():
 @pytest.mark.parametrize("n_v,n_f,L", [(300, 1001, 3), (257, 64, 1), (513, 333, 7),
                                        (2, 5, 3), (256, 128, 3), (40, 3000, 15),
                                        (300, 1024, 3), (513, 320, 7), (41, 3008, 15),
-                                       (1000, 192, 2)])
+                                       (1000, 192, 2), (300, 1008, 3), (257, 48, 1),
+                                       (513, 2000, 7), (41, 16, 15)])
 def test_mfma_thermometer_bit_exact(n_v, n_f, L, path, wide):
     """min(a,b) = sum_t [a>=t][b>=t] on integer levels: the int8 matrix-core
     path must equal the oracle (and the VALU path) bit for bit."""
@@ -253,6 +254,23 @@ def test_mfma_auto_path_and_unaligned_rows():
     Vd = to_dev(big)[:, :511]
     c2, _ = ps.ps2(Vd, levels=3)
     check_exact_f32(host(c2), oracle.c2_all(V), "c2")
+
+
+def test_mfma_padded_rows_partial_last_stage():
+    """Aligned rows (pitch 1024) whose length is not a multiple of the
+    64-field stage take the register-staged tiles; the bytes past n_f (here
+    255, inside the row pitch) must not count."""
+    from paper_1705_08210_amd import ps
+    for n_v, n_f, L in [(300, 1001, 3), (129, 77, 15)]:
+        big = workloads.levels(n_v, 1024, seed=n_v + n_f, probs=np.full(L + 1, 1.0 / (L + 1)))
+        big[:, n_f:] = 255
+        V = np.ascontiguousarray(big[:, :n_f])
+        announce(f"2-way mfma padded rows n_v={n_v} n_f={n_f} ld=1024 L={L}")
+        Vd = to_dev(big)[:, :n_f]
+        c2, n2 = ps.ps2(Vd, want_n2=True, path="mfma", levels=L)
+        ref, rn2 = oracle.c2_all(V, with_n2=True)
+        check_exact_f32(host(c2), ref, "c2")
+        assert np.array_equal(host(n2).astype(np.float64), rn2)
 
 
 def test_mfma_rows_beyond_32bit_tile_offsets():
