@@ -473,7 +473,7 @@ __global__ __launch_bounds__((mfma_threads<2, TB>()), kMB / TB) void ps_mfma3_ke
 // Kernels: ps_mfma2_lvd_kernel (2-way, rows 16-byte aligned and n_f a
 // multiple of 64: stages go straight into LDS), ps_mfma2_lv_kernel (2-way,
 // any rows: staged through registers, fields past n_f cleared),
-// ps_mfma3_lvsd_kernel (3-way split tiling, three levels on aligned rows
+// ps_mfma3_lvsd_kernel (3-way split tiling, 1..7 levels on aligned rows
 // with n_f a multiple of 64: plain rows straight into LDS, pair rows through
 // registers), ps_mfma3_lvs_kernel (3-way split tiling, any rows and levels)
 // and ps_mfma3_lv_kernel (3-way per-slab tiles).
@@ -1857,16 +1857,29 @@ static hipError_t go_mfma3_lvs(const MfmaLaunch& m, hipStream_t st) {
     hipError_t e = launch_prefix3_split(n, jb, js, je, kMB, m.prefix, m.prefix + a.nrt[0] + 1, st);
     if (e != hipSuccess) return e;
     a.ntiles = a.nt[0] + a.nt[1];
-    // LDS-direct stages for three levels (the other level counts run their
-    // level loop at run time, which spills the accumulators in that kernel)
-    if constexpr (LC == 3) {
-        if (ALIGNED && m.n_f >= kLvdMK && m.n_f % kLvdMK == 0)
-            return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
-                LvArgs b = a;
-                b.item0 = item0;
-                hipLaunchKernelGGL((ps_mfma3_lvsd_kernel<LC, MODE>), dim3(grid), dim3(256), 0,
-                                   st, b);
-            });
+    // LDS-direct stages for 1..7 levels, one instantiation per level count
+    // (with the count known only at run time the level loop spills the
+    // accumulators in that kernel; more levels keep the register-staged one)
+    if constexpr (ALIGNED && MODE == kLvPerm) {
+        if (m.n_f >= kLvdMK && m.n_f % kLvdMK == 0 && m.levels >= 1 && m.levels <= 7) {
+            auto go = [&](auto lc) {
+                return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
+                    LvArgs b = a;
+                    b.item0 = item0;
+                    hipLaunchKernelGGL((ps_mfma3_lvsd_kernel<decltype(lc)::value, kLvPerm>),
+                                       dim3(grid), dim3(256), 0, st, b);
+                });
+            };
+            switch (m.levels) {
+            case 1: return go(std::integral_constant<int, 1>{});
+            case 2: return go(std::integral_constant<int, 2>{});
+            case 3: return go(std::integral_constant<int, 3>{});
+            case 4: return go(std::integral_constant<int, 4>{});
+            case 5: return go(std::integral_constant<int, 5>{});
+            case 6: return go(std::integral_constant<int, 6>{});
+            default: return go(std::integral_constant<int, 7>{});
+            }
+        }
     }
     return launch_items(2 * a.ntiles, 256, kXcds, [&](unsigned grid, int64_t item0) {
         LvArgs b = a;

@@ -166,27 +166,30 @@ def test_mfma_3way_exact(path, n_v, n_f):
     check_exact_f32(c3, oracle.c3_all(V), "c3")
 
 
-@pytest.mark.parametrize("n_v,n_f", [(3, 64), (140, 320), (300, 192), (520, 128)])
-def test_mfma_3way_lds_direct_stages_exact(n_v, n_f):
-    """Three levels on aligned rows with n_f a multiple of 64 (the split
-    tiling with its plain rows staged straight into LDS): every triple once
-    (NaN-filled output), equal to the oracle and to the VALU path bit for
-    bit, and stages across the split point concatenate to the full run."""
+@pytest.mark.parametrize("n_v,n_f,L", [(3, 64, 3), (140, 320, 3), (300, 192, 3), (520, 128, 3),
+                                       (140, 320, 2), (300, 192, 1), (259, 128, 5),
+                                       (200, 64, 7)])
+def test_mfma_3way_lds_direct_stages_exact(n_v, n_f, L):
+    """1..7 levels on aligned rows with n_f a multiple of 64 (the split
+    tiling with its plain rows staged straight into LDS, one kernel per level
+    count): every triple once (NaN-filled output), equal to the oracle and to
+    the VALU path bit for bit, and stages across the split point concatenate
+    to the full run."""
     import torch
     from paper_1705_08210_amd import ps
-    probs = np.full(4, 0.25)
-    V = workloads.levels(n_v, n_f, seed=n_v + n_f, probs=probs)
+    probs = np.full(L + 1, 1.0 / (L + 1))
+    V = workloads.levels(n_v, n_f, seed=n_v + n_f + L, probs=probs)
     Vd = to_dev(V)
-    announce(f"3-way mfma lds-direct {n_v}x{n_f}")
+    announce(f"3-way mfma lds-direct {n_v}x{n_f} L={L}")
     c3 = torch.full((ps.stage_size(n_v, 1, n_v - 1),), float("nan"), device=Vd.device)
-    ps.ps3(Vd, c3=c3, path="mfma", levels=3)
+    ps.ps3(Vd, c3=c3, path="mfma", levels=L)
     got = host(c3)
     assert not np.isnan(got).any()
     check_exact_f32(got, oracle.c3_all(V), "c3")
     ref = host(ps.ps3(Vd, path="valu"))
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
     cuts = sorted({1, max(1, n_v // 3), max(1, 2 * n_v // 3), n_v - 1})
-    parts = [host(ps.ps3(Vd, j_begin=a, j_end=b, path="mfma", levels=3))
+    parts = [host(ps.ps3(Vd, j_begin=a, j_end=b, path="mfma", levels=L))
              for a, b in zip(cuts, cuts[1:])]
     assert np.array_equal(np.concatenate(parts).view(np.uint32), got.view(np.uint32))
 
