@@ -228,7 +228,8 @@ def test_sampled_pairs_match_listed_oracle():
                                        (2, 5, 3), (256, 128, 3), (40, 3000, 15),
                                        (300, 1024, 3), (513, 320, 7), (41, 3008, 15),
                                        (1000, 192, 2), (300, 1008, 3), (257, 48, 1),
-                                       (513, 2000, 7), (41, 16, 15)])
+                                       (513, 2000, 7), (41, 16, 15), (300, 128, 4),
+                                       (200, 256, 5), (130, 64, 6)])
 def test_mfma_thermometer_bit_exact(n_v, n_f, L, path, wide):
     """min(a,b) = sum_t [a>=t][b>=t] on integer levels: the int8 matrix-core
     path must equal the oracle (and the VALU path) bit for bit."""

@@ -168,7 +168,7 @@ def test_mfma_3way_exact(path, n_v, n_f):
 
 @pytest.mark.parametrize("n_v,n_f,L", [(3, 64, 3), (140, 320, 3), (300, 192, 3), (520, 128, 3),
                                        (140, 320, 2), (300, 192, 1), (259, 128, 5),
-                                       (200, 64, 7)])
+                                       (200, 64, 7), (140, 128, 4), (100, 64, 6)])
 def test_mfma_3way_lds_direct_stages_exact(n_v, n_f, L):
     """1..7 levels on aligned rows with n_f a multiple of 64 (the split
     tiling with its plain rows staged straight into LDS, one kernel per level
