@@ -1947,8 +1947,10 @@ static hipError_t go_mfma3_lv(const MfmaLaunch& m, hipStream_t st) {
 }
 
 // The fused launch for m: 16-byte row loads when V and its stride allow;
-// table lookups for levels <= 7 (three levels unrolled and scheduled at
-// compile time, the common case), the subtraction form above.
+// table lookups for levels <= 7, the subtraction form above.  Three levels
+// are a compile-time count throughout; the LDS-direct kernels (aligned rows,
+// n_f a multiple of 64) take a compile-time count for every level count up
+// to 7, the register-staged kernels a run-time one.
 template <int WAY, bool AL>
 static hipError_t go_lv_al(const MfmaLaunch& m, hipStream_t st) {
     if (WAY == 2) {
